@@ -1,0 +1,510 @@
+"""Pins of the FP64 oracle against what the thesis and the mathematics fix (no GPU).
+
+Each test names the passage it checks. None of them re-calls the oracle's own formula to
+produce its expectation: they use closed forms (the prolate spheroidal eigen-property),
+invariants (sum, translation, Hermitian flip, adjoint), hand-derived tie cases, an exact
+identity between gridding+inverse DFT and the table's image-plane function, and
+brute-force scans written independently with exact rational arithmetic.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------- helpers
+def small_geom(**kw):
+    g = dict(n=64, beta=8, n_w=4, s_lo=7, s_hi=7, m_img=64, du=10.0, w_max=50.0)
+    g.update(kw)
+    return g
+
+
+def fake_table(n_w, beta, support, values=None, seed=0):
+    """Table with a given support per plane; `values` = 'ones' or random slices that each
+    sum to exactly kappa = 1 (complex)."""
+    support = np.asarray(support, dtype=np.int32)
+    offset = np.zeros(n_w + 1, dtype=np.int64)
+    for k in range(n_w):
+        offset[k + 1] = offset[k] + beta * beta * int(support[k]) ** 2
+    rng = np.random.default_rng(seed)
+    data = np.zeros(int(offset[-1]), dtype=np.complex128)
+    zeta = np.zeros((n_w, beta * beta))
+    for k in range(n_w):
+        S2 = int(support[k]) ** 2
+        for s in range(beta * beta):
+            if values == "ones":
+                sl = np.ones(S2, dtype=np.complex128)
+            else:
+                sl = rng.standard_normal(S2) + 1j * rng.standard_normal(S2)
+                sl = sl - sl.mean() + 1.0 / S2   # every slice sums to 1+0j
+            data[offset[k] + s * S2: offset[k] + (s + 1) * S2] = sl
+            zeta[k, s] = sl.real.sum()
+    import oracle
+    return dict(support=support, offset=offset, zeta=zeta, data=data,
+                wbound=oracle.ktable.w_bounds(n_w, 1.0))
+
+
+def random_records(nb, nc, nt, geom, seed, spread=0.35, w_max=None):
+    rng = np.random.default_rng(seed)
+    lim = spread * geom["n"] * geom["du"]
+    uvw = np.empty((nb, nt, 3))
+    uvw[..., 0] = rng.uniform(-lim, lim, (nb, nt))
+    uvw[..., 1] = rng.uniform(-lim, lim, (nb, nt))
+    wm = geom["w_max"] if w_max is None else w_max
+    uvw[..., 2] = rng.uniform(-wm, wm, (nb, nt))
+    il = np.linspace(0.98, 1.02, nc)
+    vis = (rng.standard_normal((nb, nc, nt)) + 1j * rng.standard_normal((nb, nc, nt))).astype(np.complex64)
+    wt = rng.uniform(0.5, 2.0, (nb, nc, nt)).astype(np.float32)
+    return uvw, il, vis, wt
+
+
+# ----------------------------------------------------------------------- taper (A6)
+def test_taper_is_prolate_eigenfunction():
+    """psi_0(c, x) solves lambda psi(x) = int_{-1}^{1} cos(c x y) psi(y) dy (even PSWF;
+    tapering-function section, Slepian/Landau). Nystrom with 96 Gauss-Legendre nodes is an
+    independent route to the same function."""
+    from oracle.ktable import taper, TAPER_C
+    xg, wg = np.polynomial.legendre.leggauss(96)
+    A = np.cos(TAPER_C * np.outer(xg, xg)) * wg[None, :]
+    vals, vecs = np.linalg.eig(A)
+    i = int(np.argmax(np.abs(vals)))
+    lam, v = vals[i].real, vecs[:, i].real
+    # Nystrom interpolation to arbitrary points
+    xs = np.linspace(-0.99, 0.99, 41)
+    ny = (np.cos(TAPER_C * np.outer(xs, xg)) * wg[None, :]) @ v / lam
+    ps = taper(xs)
+    ny *= ps[20] / ny[20]
+    assert np.max(np.abs(ny - ps)) < 1e-9 * np.max(np.abs(ps))
+    assert abs(taper(np.array([1.0]))[0]) == 0.0 and abs(taper(np.array([-1.0]))[0]) == 0.0
+
+
+# ---------------------------------------------------------------- kernel table (A6-A9)
+def test_w0_kernel_is_spheroidal_and_support_7():
+    """w = 0: the FFT-built kernel equals the prolate spheroidal itself (self-Fourier
+    property with c = pi*m/2, m = 6 cells), C(u)/C(0) = psi_0(u/(3 du))/psi_0(0) on |u| < 3 du;
+    separable; real; normalised to C_0(0,0) = 1; natural support 7 at beta=8 (Algorithm
+    convgen and the support rule after it)."""
+    from oracle import ktable as kt
+    g = small_geom(m_img=256, n=256, n_w=1, w_max=0.0)
+    tb = kt.build(g, "f64", keep_fine=True)
+    C = tb["fine"][0]
+    L = C.shape[0]
+    beta = g["beta"]
+    assert abs(C[L // 2, L // 2] - 1.0) < 1e-15
+    fu = np.arange(-3 * beta + 1, 3 * beta)
+    ref = kt.taper(fu / (3.0 * beta)) / kt.taper(np.array([0.0]))[0]
+    assert np.max(np.abs(C[L // 2, L // 2 + fu] - ref)) < 3e-5
+    assert np.max(np.abs(C[L // 2 + fu, L // 2] - ref)) < 3e-5
+    win = C[L // 2 - 40:L // 2 + 41, L // 2 - 40:L // 2 + 41]
+    sep = np.outer(C[L // 2 - 40:L // 2 + 41, L // 2], C[L // 2, L // 2 - 40:L // 2 + 41])
+    assert np.max(np.abs(win - sep)) < 1e-12
+    assert np.max(np.abs(C.imag)) < 1e-12
+    assert tb["s_nat"][0] == 7
+
+
+def test_table_matches_direct_dft():
+    """The FFT step equals a brute-force direct DFT of the zero-padded image samples at
+    arbitrary taps (Algorithm convgen: sample, zero-pad, FFT)."""
+    from oracle import ktable as kt
+    g = small_geom(m_img=32, n=32, beta=4, n_w=3, w_max=400.0)
+    M, L = g["m_img"], g["beta"] * g["m_img"]
+    tb = kt.build(g, "f64", keep_fine=True)
+    p = np.arange(M) - M // 2
+    for k in range(3):
+        f = kt.image_plane(g, k)
+        C = tb["fine"][k] * tb["c00"]
+        for fv, fu in [(0, 0), (3, -7), (-12, 5), (40, -33), (-64, 63)]:
+            ph = np.exp(-2j * math.pi * (fu * p[None, :] + fv * p[:, None]) / L)
+            direct = np.sum(f * ph)
+            assert abs(C[L // 2 + fv, L // 2 + fu] - direct) < 1e-12 * abs(tb["c00"])
+
+
+def test_table_symmetries():
+    """Every plane is u<->v symmetric and even in u and in v (the image-plane function is
+    even in l and m and symmetric under l<->m); the w=0 plane is real."""
+    from oracle import ktable as kt
+    g = small_geom(m_img=64, n=64, n_w=3, w_max=200.0)
+    tb = kt.build(g, "f64", keep_fine=True)
+    for k in range(3):
+        C = tb["fine"][k]
+        L = C.shape[0]
+        W = C[1:, 1:]                        # centred, odd-size window: index L/2 -> L/2-1
+        assert np.max(np.abs(W - W.T)) < 1e-12
+        assert np.max(np.abs(W - W[::-1, :])) < 1e-12
+        assert np.max(np.abs(W - W[:, ::-1])) < 1e-12
+    assert np.max(np.abs(tb["fine"][0].imag)) < 1e-12
+
+
+def test_support_grows_with_w_and_law():
+    """Support of the w-kernels increases with w (w-projection treatment); the padded/trimmed
+    supports follow the configured law between s_lo and s_hi."""
+    from oracle import ktable as kt
+    g = small_geom(m_img=128, n=128, n_w=6, w_max=3000.0, s_lo=1, s_hi=1)
+    tb = kt.build(g, "f64")
+    sn = tb["s_nat"]
+    assert sn[0] == 7 and np.all(np.diff(sn) >= 0) and sn[-1] > sn[0]
+    g2 = small_geom(m_img=64, n=64, n_w=5, w_max=10.0, s_lo=9, s_hi=17)
+    tb2 = kt.build(g2, "f64")
+    assert list(tb2["support"]) == [9, 11, 13, 15, 17]
+
+
+def test_quantised_tables_round_to_nearest_even():
+    """bf16/f16/f32 tables are the FP64 table rounded to nearest-even per component."""
+    from oracle import ktable as kt
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -9), 3.0e-39, 0.0,
+                  1.00390625 + 2.0 ** -20])
+    r = kt.round_bf16(x)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                         # tie to even
+    assert r[2] == 1.0 + 4 * 2.0 ** -8         # tie to even (upwards)
+    assert r[3] == -1.0
+    assert r[4] == np.ldexp(np.round(3.0e-39 / 2.0 ** -133), -133)
+    assert r[5] == 0.0
+    assert r[6] == 1.0 + 2.0 ** -7             # above the tie -> up
+    # against float32 -> bfloat16 truncation semantics for values exactly representable in f32
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(1000).astype(np.float32).astype(np.float64)
+    bits = v.astype(np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (bits >> 16) & 1
+    rb = ((bits + 0x7FFF + lsb) >> 16) << 16
+    ref = rb.astype(np.uint32).view(np.float32).astype(np.float64)
+    assert np.array_equal(kt.round_bf16(v), ref)
+
+
+# ------------------------------------------------------------ index (eqs. sat, conj)
+def _golden_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "index_ties.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("geom"):
+                kv = dict(t.split("=") for t in line.split()[1:])
+                geom = dict(n=int(kv["n"]), beta=int(kv["beta"]), du=float(kv["du"]), n_w=int(kv["n_w"]),
+                            w_max=float(kv["w_max"]), support=[int(s) for s in kv["support"].split(",")])
+                continue
+            lhs, rhs = line.split("|")
+            vals = lhs.split()
+            inp = [float.fromhex(v) if v.startswith(("0x", "-0x")) else float(v) for v in vals[:4]] + [int(vals[4])]
+            rows.append((inp, rhs.split()))
+    return geom, rows
+
+
+def test_golden_index_ties(oracle_mod):
+    geom, rows = _golden_rows()
+    table = dict(support=np.array(geom["support"], np.int32),
+                 wbound=oracle_mod.ktable.w_bounds(geom["n_w"], geom["w_max"]))
+    for inp, exp in rows:
+        uvw = np.array([[[inp[0], inp[1], inp[2]]]])
+        out = oracle_mod.index(geom, table, uvw, np.array([inp[3]]), np.array([inp[4]], np.uint8))[0]
+        for o, e in zip(out, exp):
+            if e != "*":
+                assert o == int(e), (inp, list(out), exp)
+
+
+def _brute_fine(x: float) -> int:
+    """The integer t with t - 1/2 < x <= t + 1/2, by exact rational search."""
+    fx = Fraction(x)
+    t = math.floor(fx)
+    for cand in (t - 1, t, t + 1):
+        if Fraction(cand) - Fraction(1, 2) < fx <= Fraction(cand) + Fraction(1, 2):
+            return cand
+    raise AssertionError
+
+
+def _brute_pixel(t: int, beta: int) -> int:
+    """The integer X with X - 1/2 < t/beta <= X + 1/2."""
+    ft = Fraction(t, beta)
+    for cand in range(math.floor(ft) - 1, math.floor(ft) + 2):
+        if cand - Fraction(1, 2) < ft <= cand + Fraction(1, 2):
+            return cand
+    raise AssertionError
+
+
+def brute_runs(geom, support, uvw, il, vis, wt, flag, compress=True):
+    """Independent scan: per record choices by exact search, nearest plane by comparing
+    sqrt(w) distances, runs = a griddable record plus the following records of the same
+    segment whose griddable predecessor has the same key."""
+    nb, nt = uvw.shape[:2]
+    nc = il.shape[0]
+    n, beta, n_w, w_max = geom["n"], geom["beta"], geom["n_w"], geom["w_max"]
+    uvs = beta / geom["du"]
+    planes_sqrt = [math.sqrt(w_max) * (k / (n_w - 1)) if n_w > 1 else 0.0 for k in range(n_w)]
+    runs = []
+    stats = [nb * nc * nt, 0, 0, 0, 0, 0]
+    for b in range(nb):
+        for c in range(nc):
+            prev = None
+            for t in range(nt):
+                r = (b * nc + c) * nt + t
+                um, vm, wm = uvw[b, t]
+                psi = 1 if wm >= 0.0 else -1
+                uf, vf, wa = psi * (um * il[c]), psi * (vm * il[c]), psi * (wm * il[c])
+                pu, pv = uf * uvs, vf * uvs
+                key, ok = None, False
+                if abs(pu) < 2 ** 30 and abs(pv) < 2 ** 30 and math.isfinite(wa):
+                    tu, tv = _brute_fine(pu), _brute_fine(pv)
+                    X, Y = _brute_pixel(tu, beta), _brute_pixel(tv, beta)
+                    k = min(range(n_w), key=lambda j: (abs(math.sqrt(wa) - planes_sqrt[j]), -j))
+                    S = int(support[k])
+                    H = (S - 1) // 2
+                    a, row0 = X + n // 2 - H, Y + n // 2 - H
+                    ok = (flag[b, c, t] == 0) and a >= 0 and a + S <= n and row0 >= 0 and row0 + S <= n
+                    key = (X, Y, k, tu - beta * X, tv - beta * Y)
+                if ok:
+                    contrib = float(wt[b, c, t]) * complex(float(vis[b, c, t].real), psi * float(vis[b, c, t].imag))
+                    stats[1] += 1
+                    if compress and prev is not None and prev[0] and prev[1] == key:
+                        runs[-1][1] += 1
+                        runs[-1][3] += contrib
+                        stats[3] += 1
+                        stats[5] += S * S
+                    else:
+                        runs.append([r, 1, key, contrib])
+                        stats[2] += 1
+                        stats[4] += S * S
+                prev = (ok, key)
+    return runs, stats
+
+
+def _compare_runs(orc, runs, stats):
+    assert orc["n_runs"] == len(runs)
+    for i, (st, ln, key, gam) in enumerate(runs):
+        assert orc["start"][i] == st and orc["len"][i] == ln
+        assert (orc["x"][i], orc["y"][i], orc["plane"][i], orc["ou"][i], orc["ov"][i]) == key
+        assert orc["gamma"][i] == gam
+    assert list(orc["stats"]) == stats
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_runs_match_bruteforce_random(oracle_mod, seed):
+    """Index + compression + statistics vs the independent brute-force scan (random tracks
+    that move slowly so that runs form, plus flagged and off-grid records)."""
+    rng = np.random.default_rng(100 + seed)
+    geom = small_geom(n=48, beta=4, du=7.0, n_w=5, w_max=80.0)
+    support = np.array([3, 5, 7, 9, 11], np.int32)
+    nb, nc, nt = 5, 3, 40
+    start = rng.uniform(-160, 160, (nb, 1, 3))
+    start[..., 2] = rng.uniform(-80, 80, (nb, 1))
+    step = rng.uniform(-1.2, 1.2, (nb, 1, 3))
+    uvw = start + step * np.arange(nt)[None, :, None]
+    il = np.array([1.0, 1.01, 0.97])
+    vis = (rng.integers(-5, 6, (nb, nc, nt)) + 1j * rng.integers(-5, 6, (nb, nc, nt))).astype(np.complex64)
+    wt = rng.uniform(0.5, 2.0, (nb, nc, nt)).astype(np.float32)
+    flag = (rng.random((nb, nc, nt)) < 0.05).astype(np.uint8)
+    table = dict(support=support, wbound=oracle_mod.ktable.w_bounds(5, 80.0), zeta=np.zeros((5, 16)))
+    for comp in (True, False):
+        orc = oracle_mod.compress(geom, table, uvw, il, vis, wt, flag, compress=comp)
+        runs, stats = brute_runs(geom, support, uvw, il, vis, wt, flag, compress=comp)
+        _compare_runs(orc, runs, stats)
+
+
+def test_runs_adversarial(oracle_mod):
+    """All-equal records, alternating keys, a flagged predecessor with the same key (the
+    record after it starts a new run), and identical records across a segment boundary
+    (they do not merge)."""
+    geom = small_geom(n=32, beta=4, du=4.0, n_w=2, w_max=10.0)
+    support = np.array([3, 5], np.int32)
+    table = dict(support=support, wbound=oracle_mod.ktable.w_bounds(2, 10.0), zeta=np.zeros((2, 16)))
+    nt = 12
+    uvw = np.zeros((3, nt, 3))
+    uvw[0, :, :] = [5.0, -3.0, 1.0]                        # all equal -> one run per segment
+    uvw[1, :, 0] = np.where(np.arange(nt) % 2 == 0, 5.0, 9.0)  # alternating pixel
+    uvw[2, :, :] = [5.0, -3.0, 1.0]                        # same as baseline 0 -> no merge across
+    il = np.array([1.0])
+    vis = np.ones((3, 1, nt), np.complex64) * (2 + 1j)
+    wt = np.ones((3, 1, nt), np.float32)
+    flag = np.zeros((3, 1, nt), np.uint8)
+    flag[0, 0, 5] = 1
+    orc = oracle_mod.compress(geom, table, uvw, il, vis, wt, flag)
+    runs, stats = brute_runs(geom, support, uvw, il, vis, wt, flag)
+    _compare_runs(orc, runs, stats)
+    starts = list(orc["start"])
+    assert starts[:2] == [0, 6]                 # flagged record 5 splits baseline 0's run
+    assert list(orc["len"][:2]) == [5, 6]
+    assert orc["n_runs"] == 2 + nt + 1          # alternating -> no merges; baseline 2 -> one run
+    assert starts[-1] == 2 * nt
+
+
+def test_plane_is_nearest_in_sqrt_w(oracle_mod):
+    """w-plane choice = nearest plane in sqrt(w) (sqrt(w) sampling, w >= 0 tabulated only)."""
+    rng = np.random.default_rng(3)
+    n_w, w_max = 9, 500.0
+    geom = small_geom(n=4096, beta=8, du=1.0, n_w=n_w, w_max=w_max)
+    table = dict(support=np.full(n_w, 3, np.int32), wbound=oracle_mod.ktable.w_bounds(n_w, w_max))
+    w = rng.uniform(-700, 700, 2000)
+    uvw = np.zeros((1, w.size, 3))
+    uvw[0, :, 2] = w
+    out = oracle_mod.index(geom, table, uvw, np.array([1.0]))
+    ps = np.sqrt(w_max) * np.arange(n_w) / (n_w - 1)
+    near = np.argmin(np.abs(np.sqrt(np.abs(w))[:, None] - ps[None, :]), axis=1)
+    assert np.array_equal(out[:, 2], near)
+    assert np.array_equal(out[:, 5], np.where(w >= 0, 1, -1))
+
+
+# ------------------------------------------------------------------ gridding (A4, A16)
+def test_delta_kernel_is_nearest_cell_histogram(oracle_mod):
+    """Support 1, every sample 1+0j: gridding reduces to a histogram of weighted visibilities
+    at the nearest cell (eq. gridding with C = delta). Integer data -> exact."""
+    rng = np.random.default_rng(7)
+    geom = small_geom(n=32, beta=4, du=3.0, n_w=2, w_max=10.0)
+    table = fake_table(2, 4, [1, 1], values="ones")
+    table["wbound"] = oracle_mod.ktable.w_bounds(2, 10.0)
+    nb, nt = 6, 30
+    uvw = np.stack([rng.uniform(-35, 35, (nb, nt)), rng.uniform(-35, 35, (nb, nt)),
+                    rng.uniform(-10, 10, (nb, nt))], -1)
+    uvw[:, ::3, :2] = np.round(uvw[:, ::3, :2] * 8) / 8    # some exact half-sample positions
+    il = np.array([1.0, 1.25])
+    vis = (rng.integers(-4, 5, (nb, 2, nt)) + 1j * rng.integers(-4, 5, (nb, 2, nt))).astype(np.complex64)
+    wt = rng.integers(1, 3, (nb, 2, nt)).astype(np.float32)
+    runs = oracle_mod.compress(geom, table, uvw, il, vis, wt)
+    G = oracle_mod.grid(geom, table, runs)
+    H = np.zeros((32, 32), complex)
+    uvs = 4 / 3.0
+    for b in range(nb):
+        for c in range(2):
+            for t in range(nt):
+                um, vm, wm = uvw[b, t]
+                psi = 1 if wm >= 0 else -1
+                X = _brute_pixel(_brute_fine(psi * (um * il[c]) * uvs), 4)
+                Y = _brute_pixel(_brute_fine(psi * (vm * il[c]) * uvs), 4)
+                v = vis[b, c, t]
+                H[Y + 16, X + 16] += float(wt[b, c, t]) * complex(v.real, psi * v.imag)
+    assert np.array_equal(G, H)
+
+
+def test_grid_sum_invariant(oracle_mod):
+    """Sum over cells of the grid = sum over records of weight * (psi-conjugated vis) * kappa
+    when every kernel matrix sums to kappa = 1 (eq. gridding: no tap lost or doubled)."""
+    geom = small_geom(n=64, beta=4, du=5.0, n_w=3, w_max=40.0)
+    table = fake_table(3, 4, [3, 7, 11])
+    table["wbound"] = oracle_mod.ktable.w_bounds(3, 40.0)
+    uvw, il, vis, wt = random_records(7, 3, 25, geom, seed=11, spread=0.3)
+    runs = oracle_mod.compress(geom, table, uvw, il, vis, wt)
+    assert runs["stats"][1] == vis.size
+    G = oracle_mod.grid(geom, table, runs)
+    psi = np.where(uvw[..., 2] >= 0, 1.0, -1.0)[:, None, :]
+    v = vis.astype(np.complex128)
+    expect = np.sum(wt * (v.real + 1j * psi * v.imag))
+    assert abs(G.sum() - expect) < 1e-12 * np.sum(np.abs(v))
+
+
+def test_normaliser_is_real_part_sum_of_unit_grid(oracle_mod):
+    """eq. normalizer with zeta of eq. sum: N equals Re(sum of the grid) when every
+    visibility is 1 (the sums of real parts are what zeta pre-computes)."""
+    from oracle import ktable as kt
+    geom = small_geom(n=96, beta=8, m_img=64, n_w=3, w_max=300.0, s_lo=7, s_hi=11, du=6.0)
+    table = kt.build(geom, "f64")
+    uvw, il, vis, wt = random_records(4, 2, 30, geom, seed=3, spread=0.3)
+    ones = np.ones_like(vis)
+    runs = oracle_mod.compress(geom, table, uvw, il, ones, wt)
+    G = oracle_mod.grid(geom, table, runs)
+    assert abs(G.sum().real - runs["normaliser"]) < 1e-12 * abs(runs["normaliser"])
+
+
+def test_compressed_equals_uncompressed(oracle_mod):
+    """Compression only re-associates eq. gridding (eq. compression): same grid, same
+    normaliser; the update counters split exactly into real + saved."""
+    from oracle import ktable as kt
+    w = workloads.make(1, n_st=5, n_t=32, n_ch=2)
+    table = kt.build(w.geom, "f64")
+    rc = oracle_mod.compress(w.geom, table, w.uvw, w.inv_lambda, w.vis, w.weight)
+    ru = oracle_mod.compress(w.geom, table, w.uvw, w.inv_lambda, w.vis, w.weight, compress=False)
+    assert rc["stats"][3] > 0
+    Gc, Gu = oracle_mod.grid(w.geom, table, rc), oracle_mod.grid(w.geom, table, ru)
+    assert np.linalg.norm(Gc - Gu) <= 1e-12 * np.linalg.norm(Gu)
+    assert abs(rc["normaliser"] - ru["normaliser"]) <= 1e-12 * abs(ru["normaliser"])
+    assert rc["stats"][4] + rc["stats"][5] == ru["stats"][4]
+    assert rc["stats"][2] + rc["stats"][3] == ru["stats"][2]
+
+
+def test_hermitian_flip(oracle_mod):
+    """V(u,v,w) = conj V(-u,-v,-w) (eq. conj): negating uvw and conjugating vis leaves the
+    grid bit-identical."""
+    geom = small_geom(n=64, beta=4, du=5.0, n_w=3, w_max=40.0)
+    table = fake_table(3, 4, [3, 5, 7])
+    table["wbound"] = oracle_mod.ktable.w_bounds(3, 40.0)
+    uvw, il, vis, wt = random_records(5, 2, 20, geom, seed=5, spread=0.3)
+    uvw[..., 2][uvw[..., 2] == 0] = 1.0
+    ra = oracle_mod.compress(geom, table, uvw, il, vis, wt)
+    rb = oracle_mod.compress(geom, table, -uvw, il, np.conj(vis), wt)
+    assert np.array_equal(oracle_mod.grid(geom, table, ra), oracle_mod.grid(geom, table, rb))
+
+
+def test_translation_by_one_cell(oracle_mod):
+    """Shifting every record by exactly one cell in u shifts the grid by one column."""
+    from oracle import ktable as kt
+    geom = small_geom(n=64, beta=4, du=4.0, m_img=64, n_w=3, w_max=40.0, s_lo=5, s_hi=9)
+    table = kt.build(geom, "f64")
+    rng = np.random.default_rng(9)
+    uvw = np.stack([np.round(rng.uniform(-80, 80, (4, 30)) * 64) / 64,
+                    np.round(rng.uniform(-80, 80, (4, 30)) * 64) / 64,
+                    rng.uniform(0.1, 40, (4, 30))], -1)
+    il = np.array([1.0])
+    vis = (rng.standard_normal((4, 1, 30)) + 1j * rng.standard_normal((4, 1, 30))).astype(np.complex64)
+    ga = oracle_mod.grid(geom, table, oracle_mod.compress(geom, table, uvw, il, vis))
+    uvw2 = uvw.copy()
+    uvw2[..., 0] += geom["du"]
+    gb = oracle_mod.grid(geom, table, oracle_mod.compress(geom, table, uvw2, il, vis))
+    assert np.array_equal(gb[:, 1:], ga[:, :-1]) and not np.any(gb[:, 0])
+
+
+def test_gridding_plus_dft_matches_image_plane(oracle_mod):
+    """Gridding followed by an inverse DFT reproduces, at every image pixel, the direct sum
+    sum_r gamma_r e^{2 pi i (u_q l + v_q m)} c(l) c(m) e^{2 pi i w_k (n-1)} (eq. convgrid with
+    the w-projection kernel of eq. C_W; u_q, v_q the fine-grid positions of eq. sat, w_k the
+    plane's w). With the table built from M = N image samples this is exact up to the
+    truncation of each kernel to its support."""
+    from oracle import ktable as kt
+    N = 64
+    geom = dict(n=N, beta=8, n_w=4, s_lo=31, s_hi=31, m_img=N, du=12.0, w_max=250.0)
+    table = kt.build(geom, "f64")
+    uvw, il, vis, wt = random_records(3, 2, 10, geom, seed=21, spread=0.18)
+    runs = oracle_mod.compress(geom, table, uvw, il, vis, wt)
+    assert runs["stats"][1] == vis.size
+    G = oracle_mod.grid(geom, table, runs)
+    idx = np.arange(N) - N // 2
+    E = np.exp(2j * math.pi * np.outer(idx, idx) / N)          # [cell, pixel]
+    img = E.T @ G @ E                                          # [q (m), p (l)]
+    lm = idx / (N * geom["du"])
+    expect = np.zeros((N, N), complex)
+    planes = [kt.image_plane(geom, k) for k in range(geom["n_w"])]
+    for i in range(runs["n_runs"]):
+        uq = (8 * runs["x"][i] + runs["ou"][i]) * geom["du"] / 8
+        vq = (8 * runs["y"][i] + runs["ov"][i]) * geom["du"] / 8
+        ph = np.exp(2j * math.pi * (uq * lm[None, :] + vq * lm[:, None]))
+        expect += runs["gamma"][i] * ph * planes[runs["plane"][i]]
+    got = img * table["c00"] / N ** 2
+    err = np.max(np.abs(got - expect)) / np.max(np.abs(expect))
+    assert err < 2e-3, err
+
+
+# ------------------------------------------------------------- degridding (adjoint)
+def test_degrid_is_adjoint(oracle_mod):
+    """Re<G v, g> = Re<v, G^H g> for the real-linear gridding map including weights and the
+    conjugation of flipped records."""
+    from oracle import ktable as kt
+    geom = small_geom(n=96, beta=8, m_img=64, n_w=3, w_max=300.0, s_lo=7, s_hi=11, du=6.0)
+    table = kt.build(geom, "f64")
+    uvw, il, vis, wt = random_records(4, 3, 30, geom, seed=13, spread=0.3)
+    rng = np.random.default_rng(2)
+    runs = oracle_mod.compress(geom, table, uvw, il, vis, wt)
+    Gv = oracle_mod.grid(geom, table, runs)
+    g = rng.standard_normal((96, 96)) + 1j * rng.standard_normal((96, 96))
+    Ghg = oracle_mod.degrid(geom, table, runs, g, uvw, wt, vis.shape)
+    lhs = np.vdot(Gv, g).real
+    rhs = np.vdot(vis.astype(np.complex128), Ghg).real
+    assert abs(lhs - rhs) < 1e-13 * np.linalg.norm(Gv) * np.linalg.norm(g)
+    # records outside every run get exactly zero
+    flag = np.zeros(vis.shape, np.uint8)
+    flag[0, 0, :5] = 1
+    runs_f = oracle_mod.compress(geom, table, uvw, il, vis, wt, flag)
+    out = oracle_mod.degrid(geom, table, runs_f, g, uvw, wt, vis.shape)
+    assert np.all(out[0, 0, :5] == 0)
