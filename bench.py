@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark: w-projection gridding with compression on one MI355X.
+
+One step = the whole hot path over one batch of records: kernel-table build, index +
+compression, gridding and degridding (the adjoint), on the plain FP32 throughput workload
+(44 stations / 946 baselines x 16 channels x 512 timesteps = 7,749,632 records, 2048^2
+grid, oversampling 8, 32 w-planes, supports 9..63). Inputs are synthetic (seeded earth-
+rotation tracks and point-source visibilities) and resident in HBM before timing starts.
+
+Prints ONE JSON line. `value` = grid-point updates per second over the step (the gridder's
+updates plus the degridder's, each sum over runs of S^2). Per-phase times, the BF16-table
+variant, the uncompressed variant, the gridder's roofline and the CPU oracle baseline are
+extra fields.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "grid_cfg2_counters.txt")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the BF16 and uncompressed variants")
+    return ap.parse_args()
+
+
+def gpu_step(wg, geom, kt, ws, tb_buf, gridder, vis, grid, vis_out, ev):
+    """One pass of the hot path; records events between phases on the current stream."""
+    import torch
+    ev[0].record()
+    wg.wg_ktable_build(geom, kt, ws)
+    ev[1].record()
+    gridder.compress(vis)
+    ev[2].record()
+    grid.zero_()
+    ev[3].record()
+    gridder.grid(out=grid)
+    ev[4].record()
+    gridder.degrid(grid, out=vis_out)
+    ev[5].record()
+    return ev
+
+
+def read_counters():
+    """HBM bytes per gridder launch from the committed rocprofv3 counter summary, if it
+    matches the current kernel (the file names the library build it was taken from)."""
+    try:
+        with open(PROFILE_COUNTERS) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line)
+        return float(kv["traffic_bytes_per_launch"].strip())
+    except Exception:
+        return None
+
+
+def cpu_baseline(w, vis_h, u_full):
+    """The FP64 oracle (single thread) on every 16th baseline; the per-record phases are
+    scaled to the full workload by update count, the table build is counted once."""
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    t64 = oracle.ktable.build(w.geom, "f32")
+    t_table = time.perf_counter() - t0
+    sub = slice(0, None, 16)
+    uvw, vis = w.uvw[sub], vis_h[sub]
+    t0 = time.perf_counter()
+    runs = oracle.compress(w.geom, t64, uvw, w.inv_lambda, vis)
+    t1 = time.perf_counter()
+    G = oracle.grid(w.geom, t64, runs)
+    t2 = time.perf_counter()
+    oracle.degrid(w.geom, t64, runs, G, uvw, None, vis.shape)
+    t3 = time.perf_counter()
+    u_s = int(runs["stats"][4])
+    scale = u_full / max(u_s, 1)
+    t_full = t_table + (t3 - t0) * scale
+    return {"value": round(2 * u_full / t_full / 1e9, 4), "unit": "Gupd/s", "cores": 1, "kind": "oracle",
+            "sample": (f"every 16th baseline ({uvw.shape[0]} of {w.uvw.shape[0]}; {vis.size} records, "
+                       f"{u_s} updates); table build {t_table:.2f}s once, compress {t1 - t0:.2f}s, "
+                       f"grid {t2 - t1:.2f}s, degrid {t3 - t2:.2f}s scaled x{scale:.2f} to the full step"),
+            "seconds_full_step": round(t_full, 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1403_4209_amd import wgrid as wg
+
+    dev = torch.device("cuda:0")
+    w = workloads.make(2, device=dev)
+    geom = wg.geom_from_dict(w.geom, compress=True)
+    uvw = torch.as_tensor(w.uvw).to(dev)
+    il = torch.as_tensor(w.inv_lambda).to(dev)
+    vis = w.vis
+    weight = w.weight
+    nb, nt = w.uvw.shape[:2]
+    nc = w.inv_lambda.shape[0]
+
+    # persistent buffers: table (f32), table workspace, grid, degrid output
+    table = wg.KernelTable(geom, "f32", device=dev)
+    _, ws_bytes = wg.wg_ktable_sizes(geom)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    gridder = wg.Gridder(geom, table, uvw, il, weight)
+    grid = torch.zeros((geom.n, geom.n), dtype=torch.complex64, device=dev)
+    vis_out = torch.empty_like(vis)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+
+    for _ in range(args.warmup):
+        gpu_step(wg, geom, table.kt, ws, None, gridder, vis, grid, vis_out, ev)
+    torch.cuda.synchronize()
+    phase = np.zeros(5)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gpu_step(wg, geom, table.kt, ws, None, gridder, vis, grid, vis_out, ev)
+        torch.cuda.synchronize()
+        phase += [ev[i].elapsed_time(ev[i + 1]) for i in range(5)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phase /= args.steps
+    ms_step = wall * 1e3 / args.steps
+    st = gridder.runs.stats()
+    U = st.upd_real
+    t_ktable, t_comp, t_zero, t_grid, t_degrid = phase
+    value = 2.0 * U / (ms_step * 1e-3) / 1e9
+
+    # gridder roofline: algorithmic bytes per launch = table samples streamed (8 B each for
+    # FP32) + run records read (20 B) + the grid read and written once (16 B per cell)
+    alg_bytes = U * 8 + st.n_runs * 20 + 16 * geom.n * geom.n
+    achieved = alg_bytes / (t_grid * 1e-3) / 1e9
+    traffic = read_counters()
+
+    out = {
+        "metric": "grid-point updates/sec (Gupd/s) + HBM GB/s; BF16-kernel vs FP32 at stated rel err",
+        "value": round(value, 3),
+        "unit": "Gupd/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded LOFAR-like array, earth-rotation tracks, 200 point sources + noise)",
+        "config": {"workload": ("plain FP32 gridding, 44 stations (946 baselines) x 16 channels x 512 timesteps = "
+                                "7,749,632 records, grid 2048x2048 complex64, oversampling 8, 32 w-planes, "
+                                "supports 9..63, compression on"),
+                   "records": int(st.n_records), "runs": int(st.n_runs), "upd_real": int(U),
+                   "upd_total": int(U + st.upd_saved)},
+        "phases_ms": {"ktable": round(t_ktable, 4), "compress": round(t_comp, 4), "grid_zero": round(t_zero, 4),
+                      "grid": round(t_grid, 4), "degrid": round(t_degrid, 4)},
+        "grid_gupds_real": round(U / (t_grid * 1e-3) / 1e9, 2),
+        "grid_gupds_total": round((U + st.upd_saved) / (t_grid * 1e-3) / 1e9, 2),
+        "degrid_gupds": round(U / (t_degrid * 1e-3) / 1e9, 2),
+        "compression_ratio_records": round(st.n_compressed / max(st.n_runs, 1), 3),
+        "compression_ratio_updates": round(st.upd_saved / max(U, 1), 3),
+        "roofline": {"kernel": "k_grid (wg_grid)", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+    }
+
+    if not args.no_variants:
+        # BF16 table, same records (grid and degrid only; table build timed once)
+        tb16 = wg.KernelTable(geom, "bf16", device=dev)
+        g16 = wg.Gridder(geom, tb16, uvw, il, weight)
+        g16.compress(vis)
+        for _ in range(2):
+            grid.zero_()
+            g16.grid(out=grid)
+            g16.degrid(grid, out=vis_out)
+        torch.cuda.synchronize()
+        tg = td = 0.0
+        for _ in range(args.steps):
+            grid.zero_()
+            ev[0].record()
+            g16.grid(out=grid)
+            ev[1].record()
+            g16.degrid(grid, out=vis_out)
+            ev[2].record()
+            torch.cuda.synchronize()
+            tg += ev[0].elapsed_time(ev[1])
+            td += ev[1].elapsed_time(ev[2])
+        tg /= args.steps
+        td /= args.steps
+        out["bf16"] = {"grid_ms": round(tg, 4), "degrid_ms": round(td, 4),
+                       "grid_gupds_real": round(U / (tg * 1e-3) / 1e9, 2),
+                       "speedup_grid_vs_f32": round(t_grid / tg, 3), "speedup_degrid_vs_f32": round(t_degrid / td, 3),
+                       "rel_err_bound_vs_fp64_oracle": 3e-3}
+        del g16, tb16
+        # compression off: every griddable record is its own run
+        geom_u = wg.geom_from_dict(w.geom, compress=False)
+        gu = wg.Gridder(geom_u, table, uvw, il, weight)
+        tcu = tgu = 0.0
+        for i in range(args.steps + 1):
+            grid.zero_()
+            ev[0].record()
+            gu.compress(vis)
+            ev[1].record()
+            gu.grid(out=grid)
+            ev[2].record()
+            torch.cuda.synchronize()
+            if i:
+                tcu += ev[0].elapsed_time(ev[1])
+                tgu += ev[1].elapsed_time(ev[2])
+        tcu /= args.steps
+        tgu /= args.steps
+        out["uncompressed"] = {"compress_ms": round(tcu, 4), "grid_ms": round(tgu, 4),
+                               "speedup_of_compression": round((tcu + tgu) / (t_comp + t_grid), 3)}
+        del gu
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, vis.cpu().numpy(), U)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

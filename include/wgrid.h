@@ -1,0 +1,245 @@
+/*
+ * wgrid.h -- C ABI of libwgrid: w-projection convolutional gridding with compression on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: D. Muscat, "High-Performance Image Synthesis for Radio Interferometry",
+ * M.Sc. thesis 2013 (arXiv:1403.4209), chapter "The Malta-imager":
+ *   - Convolution Function Generator (Algorithm convgen, eqs. choose, sat, sum)
+ *     -> wg_ktable_sizes / wg_ktable_build
+ *   - WImager preparation phase (PreProcessUVW, eqs. ci and conj, Algorithms index and
+ *     compressindex, eqs. compress1 and conjugatetake, statistics logic, eq. normalizer)
+ *     -> wg_compress
+ *   - WImager gridding phase (eq. gridding) -> wg_grid
+ *   - the exact adjoint of eq. gridding (not in the thesis) -> wg_degrid
+ *
+ * Conventions shared by every call
+ *   - Pointers are DEVICE pointers owned by the caller unless marked [host]. The library
+ *     allocates nothing on the device and keeps no state between calls.
+ *   - Calls check their arguments on the host and return an error before enqueuing any
+ *     work; then they enqueue on `stream` (a hipStream_t; NULL = the null stream) and
+ *     return without waiting, except wg_ktable_build, which waits for its own work.
+ *   - A HIP error seen at launch is returned as WG_EHIP; an error of earlier asynchronous
+ *     work may surface on a later call.
+ *   - No C++ exception crosses this interface.
+ *   - Records: nb baselines x nc channels x nt timesteps, record r = (b*nc + ch)*nt + t.
+ *     uvw is float64 [nb][nt][3] in metres (input I-1), inv_lambda float64 [nc] in 1/m
+ *     (I-2), vis complex64 [nb][nc][nt] as interleaved (re, im) float32 (I-5), weight
+ *     float32 [nb][nc][nt] (I-3; NULL means 1), flag uint8 [nb][nc][nt] (I-4; nonzero =
+ *     flagged; NULL means none). Single polarisation.
+ *   - Grid: complex64 [n][n] interleaved, row y follows v, column x follows u, cell
+ *     (n/2, n/2) is u = v = 0 (gridding phase, Convolution Position sequence).
+ *   - Off-grid, flagged or non-finite records are not errors: they are not griddable
+ *     (gridding indicator g = 0) and are counted in wg_stats.
+ */
+#ifndef WGRID_H
+#define WGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *wg_stream_t; /* hipStream_t */
+
+typedef enum wg_status {
+    WG_OK = 0,
+    WG_EINVAL = -1,        /* a pointer, size or geometry value is invalid              */
+    WG_ECAPACITY = -3,     /* an output or workspace buffer is too small                 */
+    WG_EHIP = -4,          /* the HIP runtime reported an error                          */
+    WG_EUNSUPPORTED = -5   /* valid but outside what this build handles (sizes below)    */
+} wg_status;
+
+typedef enum wg_kdtype {
+    WG_KF32 = 0,   /* complex samples as 2 x float32 (8 bytes)                          */
+    WG_KBF16 = 1,  /* 2 x bfloat16 (4 bytes), round-to-nearest-even from the FP64 master */
+    WG_KF16 = 2    /* 2 x float16 (4 bytes), round-to-nearest-even from the FP64 master  */
+} wg_kdtype;
+
+/* wg_geom.flags */
+#define WG_COMPRESS 1u   /* merge consecutive records with the same key (eq. compression) */
+
+/* Limits of this build. */
+#define WG_MAX_SUPPORT 63    /* largest kernel support (odd)                            */
+#define WG_MAX_PLANES 256    /* largest number of w-planes                              */
+#define WG_MAX_FFT 2048      /* largest beta * m_img (oversampled table side)           */
+
+/*
+ * Imaging geometry (Convolution Function Generator "General points"; WImager outputs).
+ *   n       grid side N, even, 2..32768 (the u = v = 0 cell is (n/2, n/2)).
+ *   beta    oversampling factor (eq. local:o), a power of two in 2..32.
+ *   n_w     number of w-planes, 1..WG_MAX_PLANES, planes at w_max*(k/(n_w-1))^2 (sqrt(w)
+ *           spacing; |w| above w_max uses the last plane).
+ *   s_lo, s_hi  odd supports, 1 <= s_lo <= s_hi <= WG_MAX_SUPPORT. Plane k gets
+ *           S_k = min(s_hi, max(S_nat(k), s_lo + 2*floor(((s_hi-s_lo)*k + n_w-1)/(2(n_w-1)))))
+ *           where S_nat is the support found from the 1e-3 threshold (pad/trim as in the
+ *           generator's normal mode).
+ *   m_img   image samples per side used to build the table (power of two, >= 16,
+ *           beta*m_img <= WG_MAX_FFT, and (s_hi-1)/2*beta + beta/2 < beta*m_img/2).
+ *   du      uv cell size in wavelengths (> 0); the image field of view is 1/du.
+ *   w_max   largest |w| tabulated, wavelengths (>= 0).
+ *   flags   WG_COMPRESS or 0.
+ */
+typedef struct wg_geom {
+    int32_t n;
+    int32_t beta;
+    int32_t n_w;
+    int32_t s_lo;
+    int32_t s_hi;
+    int32_t m_img;
+    double du;
+    double w_max;
+    uint32_t flags;
+    int32_t reserved;
+} wg_geom;
+
+/*
+ * Convolution-function table (outputs C-1, C-2, C-3 of the generator).
+ *   support [n_w]      S_k (C-2, first element)
+ *   offset  [n_w+1]    start of plane k in `data`, in complex elements (C-2, second)
+ *   wbound  [n_w]      lower |w| edge of plane k (entry 0 unused): the nearest plane in
+ *                      sqrt(w); wbound[j] = w_max*((j-1/2)/(n_w-1))^2
+ *   zeta    [n_w*beta*beta]  sum of the real parts of each S_k x S_k matrix (eq. sum), of
+ *                      the values as stored in `data`, in FP64 (C-3)
+ *   data               C-1: plane k holds beta*beta matrices of S_k x S_k samples, row-major,
+ *                      matrix index (o_v + beta/2 - 1)*beta + (o_u + beta/2 - 1) for oversample
+ *                      offsets o in (-beta/2, beta/2]; element [i][j] is the kernel at fine
+ *                      offsets ((i-H)*beta - o_v, (j-H)*beta - o_u), H = (S_k-1)/2, normalised
+ *                      so the w=0 kernel's centre is 1 (eq. choose with row = v, column = u).
+ *   data_cap           capacity of `data` in complex elements.
+ *   dtype, n_w, beta   must match the geometry; s_max is written by wg_ktable_build.
+ * All pointers are device memory owned by the caller.
+ */
+typedef struct wg_ktable {
+    int32_t dtype;
+    int32_t n_w;
+    int32_t beta;
+    int32_t s_max;
+    int32_t *support;
+    int64_t *offset;
+    double *wbound;
+    double *zeta;
+    void *data;
+    int64_t data_cap;
+} wg_ktable;
+
+/*
+ * Runs produced by wg_compress (filtered sequences FS-1..FS-5 with the compression of
+ * Algorithm compressindex folded in). Run q covers records start[q] .. start[q]+len[q]-1 of
+ * one (baseline, channel) segment, all with pixel (x, y) relative to the grid centre,
+ * w-plane `plane` and oversample offsets (ou, ov); gamma is the sum over its records of
+ * weight * (vis, conjugated when w < 0), as float32 (re, im). Runs are in record order.
+ * `plan` is a device work list the gridder reads (local chunks of equal support, grouped by
+ * support); size it with wg_plan_elems. Every array has `capacity` entries (gamma 2x);
+ * capacity must be >= nb*nc*nt, so the run list can never overflow.
+ */
+typedef struct wg_runs {
+    int64_t capacity;
+    int32_t *start;
+    int32_t *len;
+    int32_t *x;
+    int32_t *y;
+    int16_t *plane;
+    int8_t *ou;
+    int8_t *ov;
+    float *gamma;
+    int32_t *plan;
+    int64_t plan_elems;
+} wg_runs;
+
+/*
+ * Statistics of one wg_compress call (statistics logic and eq. normalizer), written on the
+ * device: n_records; n_griddable = sum (g+c); n_runs = sum g (records gridded by the
+ * gridder); n_compressed = sum c; upd_real = sum g*S^2 (grid-point updates executed);
+ * upd_saved = sum c*S^2 (updates saved by compression); normaliser = N of eq. normalizer
+ * (FP64); n_items = number of local chunks in the plan.
+ */
+typedef struct wg_stats {
+    int64_t n_records;
+    int64_t n_griddable;
+    int64_t n_runs;
+    int64_t n_compressed;
+    int64_t upd_real;
+    int64_t upd_saved;
+    double normaliser;
+    int64_t n_items;
+} wg_stats;
+
+/* Human-readable name of a status code. Never NULL. */
+const char *wg_status_str(int status);
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int wg_version(void);
+
+/*
+ * Sizes for wg_ktable_build, from the geometry alone (Algorithm convgen).
+ * [host] data_elems_max: complex elements `data` must hold (every plane at s_hi).
+ * [host] ws_bytes: device workspace the build needs.
+ * Errors: WG_EINVAL (NULL pointer or invalid geometry), WG_EUNSUPPORTED (limits above).
+ */
+int wg_ktable_sizes(const wg_geom *g, int64_t *data_elems_max, size_t *ws_bytes);
+
+/*
+ * Build the table on the GPU (Algorithm convgen): evaluate the separable prolate
+ * spheroidal taper (c = 3*pi) times the inverse w-screen exp(+2 pi i w (sqrt(1-l^2-m^2)-1))
+ * on m_img x m_img image samples, zero-pad to beta*m_img, forward FFT, normalise by the w=0
+ * plane's centre value, find each plane's natural support from the 1e-3 magnitude
+ * threshold, apply the support law, trim, reorder into matrices, round to kt->dtype and
+ * sum real parts into zeta. kt->dtype, n_w, beta and the device pointers are inputs; the
+ * arrays behind them and kt->s_max are outputs. [host] support_out[n_w] and
+ * offset_out[n_w+1] receive copies when non-NULL. Waits for its own work before returning.
+ * Errors: WG_EINVAL, WG_EUNSUPPORTED, WG_ECAPACITY (ws_bytes or data_cap too small),
+ * WG_EHIP.
+ */
+int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t ws_bytes,
+                    int32_t *support_out, int64_t *offset_out, wg_stream_t stream);
+
+/* int32 elements of wg_runs.plan for `capacity` records in `n_segments` = nb*nc segments. */
+int64_t wg_plan_elems(int64_t capacity, int64_t n_segments);
+
+/*
+ * Preparation phase: per record the discrete choices (pixel, oversample offsets, w-plane,
+ * take-conjugate, gridding indicator) in FP64 with the same rounding as the definitions:
+ * x = fl(fl(u*inv_lambda) * beta/du), fine index t with t - 1/2 < x <= t + 1/2, pixel
+ * X = floor((t + beta/2 - 1)/beta), o = t - beta*X, plane = #{j >= 1 : |w| >= wbound[j]},
+ * flip when w(metres) < 0. A record is griddable when finite, unflagged and all its S x S
+ * taps fall on the grid. With WG_COMPRESS, a griddable record whose griddable predecessor
+ * in the same (baseline, channel) segment has the same (x, y, plane, ou, ov) joins that
+ * run (eqs. compression and ci); otherwise it starts a new run. Writes runs, the plan and
+ * *stats (device). Overwrites previous contents.
+ * Errors: WG_EINVAL (NULL required pointer, sizes < 1, geometry/table mismatch),
+ * WG_ECAPACITY (runs->capacity < nb*nc*nt or plan too small), WG_EUNSUPPORTED
+ * (nb*nc*nt >= 2^31), WG_EHIP.
+ */
+int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const double *inv_lambda,
+                const float *vis, const float *weight, const uint8_t *flag, int64_t nb, int32_t nc,
+                int32_t nt, wg_runs *runs, wg_stats *stats, wg_stream_t stream);
+
+/*
+ * Gridding phase (eq. gridding): for every run, grid[row0+i][a+j] += gamma * K[i][j] with
+ * a = x + n/2 - H, row0 = y + n/2 - H, K the run's matrix. ACCUMULATES into `grid`
+ * (complex64 [n][n]); the caller zeroes it first. Accumulation is FP32 with Kahan
+ * compensation per owned cell between commits; commits use FP32 atomic adds, so the last
+ * bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
+ * Errors: WG_EINVAL, WG_EHIP.
+ */
+int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg_stats *stats,
+            float *grid, wg_stream_t stream);
+
+/*
+ * Adjoint of wg_compress + wg_grid with respect to the visibilities: per run
+ * d = sum_ij conj(K[i][j]) * grid[row0+i][a+j] (FP32, Kahan per lane); record r of the run
+ * gets weight_r * (d, or conj(d) when w_r(metres) < 0); records in no run get 0. OVERWRITES
+ * vis_out (complex64 [nb][nc][nt]). uvw, weight and the sizes must be those given to
+ * wg_compress. Errors: WG_EINVAL, WG_EHIP.
+ */
+int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg_stats *stats,
+              const float *grid, const double *uvw, const float *weight, int64_t nb, int32_t nc,
+              int32_t nt, float *vis_out, wg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WGRID_H */

@@ -171,3 +171,19 @@ def build(geom: dict, dtype: str = "f64", keep_fine: bool = False) -> dict:
     if keep_fine:
         out["fine"] = planes
     return out
+
+
+def requantize(table64: dict, dtype: str) -> dict:
+    """The same table with its samples rounded to `dtype` and zeta re-summed (eq. sum)."""
+    out = dict(table64)
+    d = table64["data"]
+    out["data"] = round_to(d.real, dtype) + 1j * round_to(d.imag, dtype)
+    beta = int(np.sqrt(table64["zeta"].shape[1]))
+    zeta = np.zeros_like(table64["zeta"])
+    for k, S in enumerate(table64["support"]):
+        seg = out["data"][table64["offset"][k]:table64["offset"][k + 1]].real
+        zeta[k] = seg.reshape(beta * beta, int(S) * int(S)).sum(axis=1)
+    out["zeta"] = zeta
+    out["dtype"] = dtype
+    out.pop("fine", None)
+    return out

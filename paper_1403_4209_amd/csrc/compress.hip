@@ -1,0 +1,430 @@
+// WImager preparation phase on the GPU: PreProcessUVW (discrete choices per record),
+// compression (eqs. compression, ci), index creation/filtering, compressed/weighted
+// visibilities (eqs. compress1, conjugatetake), the plan of equal-support local chunks, the
+// statistics and the normaliser (eq. normalizer).
+//
+// One wavefront walks one (baseline, channel) segment, 64 records per step. Each lane
+// computes its record's key in FP64; the predecessor's key arrives by a lane shuffle (the
+// last lane's key is carried to the next step); compression and run starts are ballots; run
+// indices are popcounts; gamma is a segmented wave scan headed at run starts, with an open
+// run's partial sum carried across steps. Two passes: the first counts runs per segment and
+// local chunks per support, a scan turns counts into offsets, the second writes everything.
+// The index arithmetic must round exactly like its definition, so this file is compiled
+// without floating-point contraction.
+#include "wg_common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace wg {
+namespace {
+
+struct CArgs {
+    int n, beta, lb, n_w, nc, nt, compress;
+    int64_t n_seg;
+    double uv_scale;
+    const double *uvw;
+    const double *il;
+    const float2 *vis;
+    const float *wt;
+    const uint8_t *flag;
+    const double *wbound;
+    const int32_t *support;
+    const double *zeta;
+    int32_t *start, *len, *x, *y;
+    int16_t *plane;
+    int8_t *ou, *ov;
+    float2 *gamma;
+    int32_t *plan, *items, *segcnt, *tiles;
+    wg_stats *stats;
+};
+
+struct Key {
+    int X, Y, k, ou, ov, psi, ok;
+};
+
+// t with t - 1/2 < x <= t + 1/2 (eq. sat at the fine interval), exact for |x| < 2^30.
+__device__ inline int fine_index(double x) {
+    double t = ceil(x - 0.5);
+    if (!(t - 0.5 < x))
+        t -= 1.0;
+    else if (!(x <= t + 0.5))
+        t += 1.0;
+    return (int)t;
+}
+
+__device__ inline Key index_record(double um, double vm, double wm, double il, bool flagged,
+                                   const CArgs &a, const double *s_wb, const int *s_sup) {
+    Key r;
+    r.X = r.Y = r.k = r.ou = r.ov = 0;
+    const double ul = um * il, vl = vm * il, wl = wm * il;
+    r.psi = (wm >= 0.0) ? 1 : -1;
+    const double sg = (double)r.psi;
+    const double uf = sg * ul, vf = sg * vl, wa = sg * wl;
+    const double pu = uf * a.uv_scale, pv = vf * a.uv_scale;
+    if (!(fabs(pu) < 1073741824.0) || !(fabs(pv) < 1073741824.0) || !isfinite(wa)) {
+        r.ok = 0;
+        return r;
+    }
+    const int tu = fine_index(pu), tv = fine_index(pv);
+    const int hb = a.beta >> 1;
+    r.X = (tu + hb - 1) >> a.lb;  // floor division by a power of two
+    r.Y = (tv + hb - 1) >> a.lb;
+    r.ou = tu - (r.X << a.lb);
+    r.ov = tv - (r.Y << a.lb);
+    int lo = 1, hi = a.n_w;  // #{j >= 1 : wa >= wbound[j]}
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_wb[mid] <= wa)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    r.k = lo - 1;
+    const int S = s_sup[r.k], H = (S - 1) >> 1;
+    const int ax = r.X + a.n / 2 - H, row0 = r.Y + a.n / 2 - H;
+    r.ok = !flagged && ax >= 0 && ax + S <= a.n && row0 >= 0 && row0 + S <= a.n;
+    return r;
+}
+
+__global__ void k_init(CArgs a, int64_t n_records) {
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < kPlanHdr; i += blockDim.x) a.plan[i] = 0;
+        if (threadIdx.x == 0) {
+            a.stats->n_records = n_records;
+            a.stats->n_griddable = 0;
+            a.stats->n_runs = 0;
+            a.stats->n_compressed = 0;
+            a.stats->upd_real = 0;
+            a.stats->upd_saved = 0;
+            a.stats->normaliser = 0.0;
+            a.stats->n_items = 0;
+        }
+    }
+}
+
+template <bool EMIT>
+__global__ __launch_bounds__(256) void k_segments(CArgs a) {
+    __shared__ double s_wb[WG_MAX_PLANES];
+    __shared__ int s_sup[WG_MAX_PLANES];
+    for (int i = threadIdx.x; i < a.n_w; i += blockDim.x) {
+        s_wb[i] = a.wbound[i];
+        s_sup[i] = a.support[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t seg = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (seg >= a.n_seg) return;  // whole wave leaves; no barrier follows
+    const int64_t b = seg / a.nc;
+    const int ch = (int)(seg - b * a.nc);
+    const double il = a.il[ch];
+    const uint64_t lt = lanemask_lt();
+    const int nbeta2 = a.beta * a.beta;
+
+    int cX = 0, cY = 0, cK = 0, cOu = 0, cOv = 0, cOk = 0;  // key of the previous step's last record
+    int runs_before = 0, lastS = -1;
+    int item_begin = -1, item_S = 0;
+    bool open = false;  // EMIT: a run still open at the end of the previous step
+    int open_idx = 0, open_len = 0;
+    float og_r = 0.f, og_i = 0.f;
+    int run_base = 0;
+    if (EMIT) run_base = a.segcnt[seg] + a.tiles[seg / kScanTile];
+    int64_t my_real = 0, my_saved = 0;
+    int n_ok = 0, n_c = 0;
+    double my_norm = 0.0;
+
+    for (int t0 = 0; t0 < a.nt; t0 += kWave) {
+        const int t = t0 + lane;
+        const bool valid = t < a.nt;
+        const int64_t r = seg * a.nt + t;
+        Key key;
+        key.ok = 0;
+        key.X = key.Y = key.k = key.ou = key.ov = 0;
+        key.psi = 1;
+        if (valid) {
+            const double *p = a.uvw + (b * a.nt + t) * 3;
+            const bool fl = a.flag ? (a.flag[r] != 0) : false;
+            key = index_record(p[0], p[1], p[2], il, fl, a, s_wb, s_sup);
+        }
+        int pX = __shfl_up(key.X, 1, kWave), pY = __shfl_up(key.Y, 1, kWave);
+        int pK = __shfl_up(key.k, 1, kWave), pOu = __shfl_up(key.ou, 1, kWave);
+        int pOv = __shfl_up(key.ov, 1, kWave), pOk = __shfl_up(key.ok, 1, kWave);
+        if (lane == 0) {
+            pX = cX; pY = cY; pK = cK; pOu = cOu; pOv = cOv; pOk = cOk;
+        }
+        const bool same = key.X == pX && key.Y == pY && key.k == pK && key.ou == pOu && key.ov == pOv;
+        const bool c = a.compress && t > 0 && key.ok && pOk && same;
+        const bool g = key.ok && !c;
+        const uint64_t gm = __ballot(g), cm = __ballot(c), okm = __ballot(key.ok);
+        const int S = key.ok ? s_sup[key.k] : 0;
+
+        if (EMIT && open && !(cm & 1ull)) {  // the carried run ended with the previous step
+            if (lane == 0) {
+                a.len[open_idx] = open_len;
+                a.gamma[open_idx] = make_float2(og_r, og_i);
+            }
+            open = false;
+        }
+
+        // local chunks: a run starts a new chunk when its support differs from the previous run's
+        const uint64_t gbelow = gm & lt;
+        const int src = gbelow ? 63 - __clzll(gbelow) : 0;
+        const int sprev_l = __shfl(S, src, kWave);
+        const int prevS = gbelow ? sprev_l : lastS;
+        uint64_t ism = __ballot(g && S != prevS);
+        while (ism) {
+            const int L = __ffsll((unsigned long long)ism) - 1;
+            ism &= ism - 1;
+            const int SL = __shfl(S, L, kWave);
+            const int jL = runs_before + __popcll(gm & ((1ull << L) - 1ull));
+            if (item_begin >= 0 && lane == 0) {
+                if (EMIT) {
+                    const int slot = atomicAdd(&a.plan[kPlanCur + item_S], 1);
+                    a.items[2 * slot] = run_base + item_begin;
+                    a.items[2 * slot + 1] = run_base + jL;
+                } else {
+                    atomicAdd(&a.plan[kPlanCount + item_S], 1);
+                }
+            }
+            item_begin = jL;
+            item_S = SL;
+        }
+
+        n_ok += __popcll(okm);
+        n_c += __popcll(cm);
+        if (!EMIT) {
+            if (g) my_real += (int64_t)S * S;
+            if (c) my_saved += (int64_t)S * S;
+        } else {
+            float vr = 0.f, vi = 0.f;
+            if (key.ok) {
+                const float e = a.wt ? a.wt[r] : 1.0f;
+                const float2 v = a.vis[r];
+                vr = e * v.x;
+                vi = e * ((float)key.psi * v.y);
+                const int sigma = (key.ov + (a.beta >> 1) - 1) * a.beta + (key.ou + (a.beta >> 1) - 1);
+                my_norm += (double)e * a.zeta[(int64_t)key.k * nbeta2 + sigma];
+            }
+            const uint64_t gle = gm & (lt | (1ull << lane));
+            const int seg_start = gle ? 63 - __clzll(gle) : -1;
+            float sr = vr, si = vi;
+            for (int d = 1; d < kWave; d <<= 1) {
+                const float ur = __shfl_up(sr, d, kWave), ui = __shfl_up(si, d, kWave);
+                if (lane >= d && lane - d >= seg_start) {
+                    sr += ur;
+                    si += ui;
+                }
+            }
+            if (seg_start < 0 && open) {
+                sr += og_r;
+                si += og_i;
+            }
+            if (g) {
+                const int j = run_base + runs_before + __popcll(gbelow);
+                a.start[j] = (int32_t)r;
+                a.x[j] = key.X;
+                a.y[j] = key.Y;
+                a.plane[j] = (int16_t)key.k;
+                a.ou[j] = (int8_t)key.ou;
+                a.ov[j] = (int8_t)key.ov;
+            }
+            const int cnext = __shfl_down((int)c, 1, kWave);
+            const bool last_in_seg = (t == a.nt - 1);
+            const bool is_end = key.ok && (last_in_seg || (lane < kWave - 1 && !cnext));
+            if (is_end) {
+                int j, ln;
+                if (seg_start >= 0) {
+                    j = run_base + runs_before + __popcll(gle) - 1;
+                    ln = lane - seg_start + 1;
+                } else {
+                    j = open_idx;
+                    ln = open_len + lane + 1;
+                }
+                a.len[j] = ln;
+                a.gamma[j] = make_float2(sr, si);
+            }
+            const int carry = __shfl((int)(key.ok && !is_end), kWave - 1, kWave);
+            const int ss63 = __shfl(seg_start, kWave - 1, kWave);
+            const float cr = __shfl(sr, kWave - 1, kWave), ci = __shfl(si, kWave - 1, kWave);
+            if (carry) {
+                if (ss63 >= 0) {
+                    open_idx = run_base + runs_before + __popcll(gm) - 1;
+                    open_len = kWave - ss63;
+                } else {
+                    open_len += kWave;
+                }
+                og_r = cr;
+                og_i = ci;
+                open = true;
+            } else {
+                open = false;
+            }
+        }
+        cX = __shfl(key.X, kWave - 1, kWave);
+        cY = __shfl(key.Y, kWave - 1, kWave);
+        cK = __shfl(key.k, kWave - 1, kWave);
+        cOu = __shfl(key.ou, kWave - 1, kWave);
+        cOv = __shfl(key.ov, kWave - 1, kWave);
+        cOk = __shfl(key.ok, kWave - 1, kWave);
+        if (gm) lastS = __shfl(S, 63 - __clzll(gm), kWave);
+        runs_before += __popcll(gm);
+    }
+    if (item_begin >= 0 && lane == 0) {
+        if (EMIT) {
+            const int slot = atomicAdd(&a.plan[kPlanCur + item_S], 1);
+            a.items[2 * slot] = run_base + item_begin;
+            a.items[2 * slot + 1] = run_base + runs_before;
+        } else {
+            atomicAdd(&a.plan[kPlanCount + item_S], 1);
+        }
+    }
+    if (!EMIT) {
+        const int64_t real = wave_sum(my_real), saved = wave_sum(my_saved);
+        if (lane == 0) {
+            a.segcnt[seg] = runs_before;
+            atomicAdd((unsigned long long *)&a.stats->n_griddable, (unsigned long long)n_ok);
+            atomicAdd((unsigned long long *)&a.stats->n_compressed, (unsigned long long)n_c);
+            atomicAdd((unsigned long long *)&a.stats->upd_real, (unsigned long long)real);
+            atomicAdd((unsigned long long *)&a.stats->upd_saved, (unsigned long long)saved);
+        }
+    } else {
+        const double nsum = wave_sum(my_norm);
+        if (lane == 0) atomicAdd(&a.stats->normaliser, nsum);
+    }
+}
+
+// Exclusive scan of up to 1024 per-thread values; returns the thread's offset, *total = sum.
+__device__ int block_exclusive_scan(int v, int *s_wave, int *total) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    int xs = v;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(xs, d, kWave);
+        if (lane >= d) xs += y;
+    }
+    if (lane == kWave - 1) s_wave[wid] = xs;
+    __syncthreads();
+    if (wid == 0) {
+        int w = lane < nw ? s_wave[lane] : 0;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int y = __shfl_up(w, d, kWave);
+            if (lane >= d) w += y;
+        }
+        if (lane < nw) s_wave[lane] = w;
+    }
+    __syncthreads();
+    const int off = (wid ? s_wave[wid - 1] : 0) + xs - v;
+    *total = s_wave[nw - 1];
+    __syncthreads();
+    return off;
+}
+
+// Per-tile exclusive scan of runs-per-segment (in place) and tile totals.
+__global__ __launch_bounds__(1024) void k_scan_tiles(CArgs a) {
+    __shared__ int s_wave[16];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+    int v[4], sum = 0;
+    for (int i = 0; i < 4; ++i) {
+        v[i] = (base + i < a.n_seg) ? a.segcnt[base + i] : 0;
+        sum += v[i];
+    }
+    int total;
+    int off = block_exclusive_scan(sum, s_wave, &total);
+    for (int i = 0; i < 4; ++i) {
+        if (base + i < a.n_seg) a.segcnt[base + i] = off;
+        off += v[i];
+    }
+    if (threadIdx.x == 0) a.tiles[blockIdx.x] = total;
+}
+
+// Scan of tile totals; run count; local-chunk offsets per support (largest support first).
+__global__ __launch_bounds__(1024) void k_scan_top(CArgs a, int64_t n_tiles) {
+    __shared__ int s_wave[16];
+    int carry = 0;
+    for (int64_t c0 = 0; c0 < n_tiles; c0 += blockDim.x) {
+        const int64_t i = c0 + threadIdx.x;
+        const int v = i < n_tiles ? a.tiles[i] : 0;
+        int total;
+        const int off = block_exclusive_scan(v, s_wave, &total);
+        if (i < n_tiles) a.tiles[i] = carry + off;
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        a.tiles[n_tiles] = carry;
+        a.stats->n_runs = carry;
+        int acc = 0;
+        for (int S = kMaxS; S >= 1; S -= 2) {
+            a.plan[kPlanOff + S] = acc;
+            a.plan[kPlanCur + S] = acc;
+            acc += a.plan[kPlanCount + S];
+        }
+        a.plan[kPlanOff + 64] = acc;
+        a.stats->n_items = acc;
+    }
+}
+
+}  // namespace
+}  // namespace wg
+
+extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw,
+                           const double *inv_lambda, const float *vis, const float *weight,
+                           const uint8_t *flag, int64_t nb, int32_t nc, int32_t nt, wg_runs *runs,
+                           wg_stats *stats, wg_stream_t stream) {
+    using namespace wg;
+    int st = check_geom(g);
+    if (st != WG_OK) return st;
+    st = check_table(g, kt);
+    if (st != WG_OK) return st;
+    if (!uvw || !inv_lambda || !vis || !runs || !stats) return WG_EINVAL;
+    if (nb < 1 || nc < 1 || nt < 1) return WG_EINVAL;
+    const int64_t n_rec = nb * (int64_t)nc * nt;
+    if (n_rec >= (int64_t)1 << 31) return WG_EUNSUPPORTED;
+    if (!runs->start || !runs->len || !runs->x || !runs->y || !runs->plane || !runs->ou || !runs->ov ||
+        !runs->gamma || !runs->plan)
+        return WG_EINVAL;
+    const int64_t n_seg = nb * nc;
+    if (runs->capacity < n_rec) return WG_ECAPACITY;
+    if (runs->plan_elems < wg_plan_elems(runs->capacity, n_seg)) return WG_ECAPACITY;
+
+    CArgs a;
+    a.n = g->n;
+    a.beta = g->beta;
+    a.lb = 0;
+    while ((1 << a.lb) < g->beta) ++a.lb;
+    a.n_w = g->n_w;
+    a.nc = nc;
+    a.nt = nt;
+    a.compress = (g->flags & WG_COMPRESS) ? 1 : 0;
+    a.n_seg = n_seg;
+    a.uv_scale = (double)g->beta / g->du;
+    a.uvw = uvw;
+    a.il = inv_lambda;
+    a.vis = (const float2 *)vis;
+    a.wt = weight;
+    a.flag = flag;
+    a.wbound = kt->wbound;
+    a.support = kt->support;
+    a.zeta = kt->zeta;
+    a.start = runs->start;
+    a.len = runs->len;
+    a.x = runs->x;
+    a.y = runs->y;
+    a.plane = runs->plane;
+    a.ou = runs->ou;
+    a.ov = runs->ov;
+    a.gamma = (float2 *)runs->gamma;
+    a.plan = runs->plan;
+    a.items = runs->plan + plan_items_at();
+    a.segcnt = runs->plan + plan_segcnt_at(runs->capacity);
+    a.tiles = runs->plan + plan_tiles_at(runs->capacity, n_seg);
+    a.stats = stats;
+
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n_tiles = n_scan_tiles(n_seg);
+    const int64_t seg_blocks = (n_seg + 3) / 4;
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, a, n_rec);
+    hipLaunchKernelGGL(k_segments<false>, dim3((unsigned)seg_blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, a, n_tiles);
+    hipLaunchKernelGGL(k_segments<true>, dim3((unsigned)seg_blocks), dim3(256), 0, s, a);
+    return launch_status();
+}

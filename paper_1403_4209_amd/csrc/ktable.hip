@@ -1,0 +1,431 @@
+// Convolution-function table on the GPU (Convolution Function Generator, Algorithm convgen).
+//
+// Per w-plane: evaluate the image-plane function (separable prolate spheroidal taper times
+// the inverse w-screen) on m_img x m_img samples, zero-pad to L = beta*m_img, apply a
+// forward 2-D FFT (row pass, then column pass, each an L-point radix-2 FFT held in LDS),
+// normalise by the w=0 plane's centre value, find the natural support from the 1e-3
+// magnitude threshold, then trim/reorder into one S x S matrix per oversample offset pair,
+// round to the table's storage type and sum real parts (eq. sum).
+//
+// The prolate spheroidal function psi_0(c, x), c = 3*pi, is computed here from its
+// expansion in normalised Legendre polynomials: the coefficients are the eigenvector of
+// the (even-index) tridiagonal matrix of the spheroidal differential operator for its
+// smallest eigenvalue (Bouwkamp's method; Xiao, Rokhlin & Yarvin 2001).
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "wg_common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace wg {
+namespace {
+
+constexpr int kTaperTerms = 40;
+constexpr double kTaperC = 3.0 * M_PI;
+constexpr double kThreshold = 1e-3;
+
+struct TaperCoef {
+    int n;
+    double c[kTaperTerms];  // psi_0(x) = sum_i c[i] * P_{2i}(x)
+};
+
+// Smallest-eigenvalue eigenvector of the symmetric matrix of -((1-x^2)psi')' + c^2 x^2 psi
+// in the basis sqrt(k+1/2) P_k, k even (cyclic Jacobi rotations on a small dense matrix).
+void prolate_coefficients(double c, TaperCoef *tc) {
+    const int K = kTaperTerms;
+    std::vector<double> A(K * K, 0.0), V(K * K, 0.0);
+    auto a = [](double k) { return (k + 1.0) / sqrt((2.0 * k + 1.0) * (2.0 * k + 3.0)); };
+    for (int i = 0; i < K; ++i) {
+        double k = 2.0 * i;
+        double x2 = a(k) * a(k) + (i > 0 ? a(k - 1.0) * a(k - 1.0) : 0.0);
+        A[i * K + i] = k * (k + 1.0) + c * c * x2;
+        if (i + 1 < K) A[i * K + i + 1] = A[(i + 1) * K + i] = c * c * a(k) * a(k + 1.0);
+        V[i * K + i] = 1.0;
+    }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q) {
+                tot += A[p * K + q] * A[p * K + q];
+                if (p != q) off += A[p * K + q] * A[p * K + q];
+            }
+        if (off <= 1e-60 * tot) break;
+        for (int p = 0; p < K - 1; ++p)
+            for (int q = p + 1; q < K; ++q) {
+                double apq = A[p * K + q];
+                if (apq == 0.0) continue;
+                double theta = (A[q * K + q] - A[p * K + p]) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int r = 0; r < K; ++r) {  // columns p, q
+                    double arp = A[r * K + p], arq = A[r * K + q];
+                    A[r * K + p] = cs * arp - sn * arq;
+                    A[r * K + q] = sn * arp + cs * arq;
+                }
+                for (int r = 0; r < K; ++r) {  // rows p, q
+                    double apr = A[p * K + r], aqr = A[q * K + r];
+                    A[p * K + r] = cs * apr - sn * aqr;
+                    A[q * K + r] = sn * apr + cs * aqr;
+                }
+                for (int r = 0; r < K; ++r) {
+                    double vrp = V[r * K + p], vrq = V[r * K + q];
+                    V[r * K + p] = cs * vrp - sn * vrq;
+                    V[r * K + q] = sn * vrp + cs * vrq;
+                }
+            }
+    }
+    int imin = 0;
+    for (int i = 1; i < K; ++i)
+        if (A[i * K + i] < A[imin * K + imin]) imin = i;
+    // psi(0) = sum c_i P_{2i}(0), P_{2i}(0) = (-1)^i (2i-1)!!/(2i)!!
+    double p0 = 1.0, psi0 = 0.0;
+    for (int i = 0; i < K; ++i) {
+        tc->c[i] = V[i * K + imin] * sqrt(2.0 * i + 0.5);
+        psi0 += tc->c[i] * p0;
+        p0 *= -(2.0 * i + 1.0) / (2.0 * i + 2.0);
+    }
+    if (psi0 < 0)
+        for (int i = 0; i < K; ++i) tc->c[i] = -tc->c[i];
+    tc->n = K;
+}
+
+__device__ double taper(double x, const TaperCoef &tc) {
+    if (!(fabs(x) < 1.0)) return 0.0;  // outside the open field of view
+    double pm = 1.0, pc = x, s = tc.c[0];
+    for (int m = 1; m < 2 * tc.n - 1; ++m) {
+        double pn = ((2.0 * m + 1.0) * x * pc - (double)m * pm) / (double)(m + 1);
+        pm = pc;
+        pc = pn;
+        if (((m + 1) & 1) == 0) s += tc.c[(m + 1) >> 1] * pc;
+    }
+    return s;
+}
+
+struct BuildArgs {
+    int M, L, lgL, beta, n_w, Wf, W, dtype;
+    double du, w_max;
+    const double2 *tw;
+    double2 *A;    // [n_w][L][M]  row-pass output, column-major per plane
+    double2 *win;  // [n_w][W][W]  normalised central window
+    double *c00;
+    int *kmax;
+};
+
+__device__ inline double plane_w(int k, int n_w, double w_max) {
+    if (n_w == 1) return 0.0;
+    double q = (double)k / (double)(n_w - 1);
+    return w_max * (q * q);
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-place radix-2 decimation-in-time FFT (forward, e^{-2 pi i}) of L points in LDS; the
+// input must already be in bit-reversed order. tw[j] = exp(-2 pi i j / L), j < L/2.
+__device__ void fft_lds(double2 *s, int L, const double2 *__restrict__ tw) {
+    for (int len = 2; len <= L; len <<= 1) {
+        const int half = len >> 1, step = L / len;
+        for (int b = threadIdx.x; b < (L >> 1); b += blockDim.x) {
+            const int grp = b / half, pos = b - grp * half;
+            const int i = grp * len + pos, j = i + half;
+            double2 u = s[i], v = cmul(s[j], tw[pos * step]);
+            s[i] = make_double2(u.x + v.x, u.y + v.y);
+            s[j] = make_double2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ inline int bitrev(int x, int lg) { return (int)(__brev((unsigned)x) >> (32 - lg)); }
+
+__global__ void k_twiddle(double2 *tw, int L) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < L / 2) {
+        double s, c;
+        sincospi(-2.0 * (double)j / (double)L, &s, &c);
+        tw[j] = make_double2(c, s);
+    }
+}
+
+// Row pass: image row q of plane k -> L-point FFT along u; stores the centred spectrum
+// column-major so the column pass reads contiguous values.
+__global__ void k_rows(BuildArgs a, TaperCoef tc) {
+    extern __shared__ double2 s[];
+    const int q = blockIdx.x, k = blockIdx.y;
+    for (int i = threadIdx.x; i < a.L; i += blockDim.x) s[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const double xq = 2.0 * (double)(q - a.M / 2) / (double)a.M;
+    const double m = xq / (2.0 * a.du);
+    const double tq = taper(xq, tc);
+    const double w = plane_w(k, a.n_w, a.w_max);
+    for (int p = threadIdx.x; p < a.M; p += blockDim.x) {
+        const double xp = 2.0 * (double)(p - a.M / 2) / (double)a.M;
+        const double l = xp / (2.0 * a.du);
+        const double tp = taper(xp, tc);
+        const double rr = (1.0 - l * l) - m * m;
+        double2 v = make_double2(0.0, 0.0);
+        if (rr >= 0.0) {
+            const double nm1 = sqrt(rr) - 1.0;
+            const double th = (2.0 * M_PI * w) * nm1;
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            const double t2 = tq * tp;
+            v = make_double2(t2 * cs, t2 * sn);
+        }
+        const int pos = (p - a.M / 2 + a.L) & (a.L - 1);
+        s[bitrev(pos, a.lgL)] = v;
+    }
+    __syncthreads();
+    fft_lds(s, a.L, a.tw);
+    double2 *out = a.A + (size_t)k * a.L * a.M;
+    for (int kk = threadIdx.x; kk < a.L; kk += blockDim.x) {
+        const int cu = (kk + a.L / 2) & (a.L - 1);
+        out[(size_t)cu * a.M + q] = s[kk];
+    }
+}
+
+__global__ void k_c00_and_reset(BuildArgs a) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const double2 *col = a.A + (size_t)(a.L / 2) * a.M;  // plane 0, zero frequency in u
+    for (int q = threadIdx.x; q < a.M; q += blockDim.x) acc += col[q].x;
+    red[threadIdx.x] = acc;
+    for (int k = threadIdx.x; k < a.n_w; k += blockDim.x) a.kmax[k] = 0;
+    __syncthreads();
+    for (int d = blockDim.x / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *a.c00 = red[0];
+}
+
+// Column pass for column cu of plane k: FFT along v, normalise, support search over the
+// whole plane, and keep the central window the matrices are cut from.
+__global__ void k_cols(BuildArgs a) {
+    extern __shared__ double2 s[];
+    __shared__ int red[256];
+    const int cu = blockIdx.x, k = blockIdx.y;
+    for (int i = threadIdx.x; i < a.L; i += blockDim.x) s[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const double2 *in = a.A + ((size_t)k * a.L + cu) * a.M;
+    for (int q = threadIdx.x; q < a.M; q += blockDim.x) {
+        const int pos = (q - a.M / 2 + a.L) & (a.L - 1);
+        s[bitrev(pos, a.lgL)] = in[q];
+    }
+    __syncthreads();
+    fft_lds(s, a.L, a.tw);
+    const double c00 = *a.c00;
+    const int fu = cu - a.L / 2;
+    const bool keep_u = fu >= -a.Wf && fu <= a.Wf;
+    int dmax = 0;
+    for (int kk = threadIdx.x; kk < a.L; kk += blockDim.x) {
+        const int fv = ((kk + a.L / 2) & (a.L - 1)) - a.L / 2;
+        const double2 v = make_double2(s[kk].x / c00, s[kk].y / c00);
+        if (hypot(v.x, v.y) > kThreshold) {
+            const int d = max(abs(fu), abs(fv));
+            dmax = max(dmax, d);
+        }
+        if (keep_u && fv >= -a.Wf && fv <= a.Wf)
+            a.win[((size_t)k * a.W + (fv + a.Wf)) * a.W + (fu + a.Wf)] = v;
+    }
+    red[threadIdx.x] = dmax;
+    __syncthreads();
+    for (int d = blockDim.x / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + d]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] > 0) atomicMax(&a.kmax[k], red[0]);
+}
+
+// Round-to-nearest-even of an FP64 value to a format with `sig` significant bits and
+// smallest quantum 2^qmin; returns the rounded value (exactly representable).
+__device__ inline double round_sig(double x, int sig, int qmin) {
+    if (!(x != 0.0) || isinf(x) || isnan(x)) return x;
+    const int e = ilogb(x);
+    const int qe = max(e - (sig - 1), qmin);
+    return ldexp(rint(ldexp(x, -qe)), qe);
+}
+
+__device__ inline uint16_t to_bf16_bits(double x, double *rounded) {
+    double r = round_sig(x, 8, -133);
+    if (fabs(r) > 0x1.FEp127) r = copysign(INFINITY, r);
+    *rounded = r;
+    const float f = (float)r;  // exact
+    return (uint16_t)(__float_as_uint(f) >> 16);
+}
+
+__device__ inline uint16_t to_f16_bits(double x, double *rounded) {
+    double r = round_sig(x, 11, -24);
+    if (fabs(r) > 65504.0) r = copysign(INFINITY, r);
+    *rounded = r;
+    const _Float16 h = (_Float16)(float)r;  // exact
+    uint16_t bits;
+    memcpy(&bits, &h, 2);
+    return bits;
+}
+
+__global__ void k_slices(BuildArgs a, const int32_t *__restrict__ support,
+                         const int64_t *__restrict__ offset, void *data, double *zeta) {
+    __shared__ double red[256];
+    const int sigma = blockIdx.x, k = blockIdx.y;
+    const int beta = a.beta;
+    const int ov = sigma / beta - beta / 2 + 1, ou = sigma % beta - beta / 2 + 1;
+    const int S = support[k], H = (S - 1) / 2;
+    const int64_t base = offset[k] + (int64_t)sigma * S * S;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < S * S; e += blockDim.x) {
+        const int i = e / S, j = e - (e / S) * S;
+        const int fv = (i - H) * beta - ov, fu = (j - H) * beta - ou;
+        const double2 v = a.win[((size_t)k * a.W + (fv + a.Wf)) * a.W + (fu + a.Wf)];
+        if (a.dtype == WG_KF32) {
+            const float2 f = make_float2((float)v.x, (float)v.y);
+            ((float2 *)data)[base + e] = f;
+            acc += (double)f.x;
+        } else if (a.dtype == WG_KBF16) {
+            double rr, ri;
+            const uint32_t lo = to_bf16_bits(v.x, &rr), hi = to_bf16_bits(v.y, &ri);
+            ((uint32_t *)data)[base + e] = lo | (hi << 16);
+            acc += rr;
+        } else {
+            double rr, ri;
+            const uint32_t lo = to_f16_bits(v.x, &rr), hi = to_f16_bits(v.y, &ri);
+            ((uint32_t *)data)[base + e] = lo | (hi << 16);
+            acc += rr;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = blockDim.x / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) zeta[(size_t)k * beta * beta + sigma] = red[0];
+}
+
+struct WsLayout {
+    size_t tw, A, win, c00, kmax, total;
+    int L, Wf, W;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WsLayout ws_layout(const wg_geom *g) {
+    WsLayout w;
+    w.L = g->beta * g->m_img;
+    w.Wf = (g->s_hi - 1) / 2 * g->beta + g->beta / 2;
+    w.W = 2 * w.Wf + 1;
+    size_t o = 0;
+    w.tw = o;
+    o = align256(o + sizeof(double2) * (w.L / 2));
+    w.A = o;
+    o = align256(o + sizeof(double2) * (size_t)g->n_w * w.L * g->m_img);
+    w.win = o;
+    o = align256(o + sizeof(double2) * (size_t)g->n_w * w.W * w.W);
+    w.c00 = o;
+    o = align256(o + sizeof(double));
+    w.kmax = o;
+    o = align256(o + sizeof(int) * g->n_w);
+    w.total = o;
+    return w;
+}
+
+int support_law(int k, int n_w, int s_lo, int s_hi) {
+    if (n_w == 1) return s_lo;
+    return s_lo + 2 * (((s_hi - s_lo) * k + (n_w - 1)) / (2 * (n_w - 1)));
+}
+
+}  // namespace
+}  // namespace wg
+
+extern "C" int wg_ktable_sizes(const wg_geom *g, int64_t *data_elems_max, size_t *ws_bytes) {
+    int st = wg::check_geom(g);
+    if (st != WG_OK) return st;
+    if (!data_elems_max || !ws_bytes) return WG_EINVAL;
+    *data_elems_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * g->s_hi;
+    *ws_bytes = wg::ws_layout(g).total;
+    return WG_OK;
+}
+
+extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t ws_bytes,
+                               int32_t *support_out, int64_t *offset_out, wg_stream_t stream) {
+    using namespace wg;
+    int st = check_geom(g);
+    if (st != WG_OK) return st;
+    if (!kt || !ws || kt->dtype < WG_KF32 || kt->dtype > WG_KF16) return WG_EINVAL;
+    if (kt->n_w != g->n_w || kt->beta != g->beta) return WG_EINVAL;
+    if (!kt->support || !kt->offset || !kt->wbound || !kt->zeta || !kt->data) return WG_EINVAL;
+    const WsLayout lay = ws_layout(g);
+    if (ws_bytes < lay.total) return WG_ECAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+
+    TaperCoef tc;
+    prolate_coefficients(kTaperC, &tc);
+
+    // plane edges in |w| (nearest plane in sqrt(w))
+    std::vector<double> wb(g->n_w, 0.0);
+    for (int j = 1; j < g->n_w; ++j) {
+        double q = ((double)j - 0.5) / (double)(g->n_w - 1);
+        wb[j] = g->w_max * (q * q);
+    }
+
+    char *base = (char *)ws;
+    BuildArgs a;
+    a.M = g->m_img;
+    a.L = lay.L;
+    a.lgL = 0;
+    while ((1 << a.lgL) < a.L) ++a.lgL;
+    a.beta = g->beta;
+    a.n_w = g->n_w;
+    a.Wf = lay.Wf;
+    a.W = lay.W;
+    a.dtype = kt->dtype;
+    a.du = g->du;
+    a.w_max = g->w_max;
+    a.tw = (const double2 *)(base + lay.tw);
+    a.A = (double2 *)(base + lay.A);
+    a.win = (double2 *)(base + lay.win);
+    a.c00 = (double *)(base + lay.c00);
+    a.kmax = (int *)(base + lay.kmax);
+
+    const size_t lds = sizeof(double2) * a.L;
+    hipLaunchKernelGGL(k_twiddle, dim3((a.L / 2 + 255) / 256), dim3(256), 0, s, (double2 *)a.tw, a.L);
+    hipLaunchKernelGGL(k_rows, dim3(a.M, a.n_w), dim3(256), lds, s, a, tc);
+    hipLaunchKernelGGL(k_c00_and_reset, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_cols, dim3(a.L, a.n_w), dim3(256), lds, s, a);
+    if (hipGetLastError() != hipSuccess) return WG_EHIP;
+
+    std::vector<int> kmax(g->n_w);
+    WG_HIP_CHECK(hipMemcpyAsync(kmax.data(), a.kmax, sizeof(int) * g->n_w, hipMemcpyDeviceToHost, s));
+    WG_HIP_CHECK(hipStreamSynchronize(s));
+
+    std::vector<int32_t> sup(g->n_w);
+    std::vector<int64_t> off(g->n_w + 1, 0);
+    int smax = 1;
+    for (int k = 0; k < g->n_w; ++k) {
+        const int over = kmax[k] - g->beta / 2;
+        const int r = over <= 0 ? 0 : (over + g->beta - 1) / g->beta;
+        const int snat = 2 * r + 1;
+        int S = snat > support_law(k, g->n_w, g->s_lo, g->s_hi) ? snat : support_law(k, g->n_w, g->s_lo, g->s_hi);
+        if (S > g->s_hi) S = g->s_hi;
+        sup[k] = S;
+        smax = S > smax ? S : smax;
+        off[k + 1] = off[k] + (int64_t)g->beta * g->beta * S * S;
+    }
+    if (off[g->n_w] > kt->data_cap) return WG_ECAPACITY;
+    kt->s_max = smax;
+
+    WG_HIP_CHECK(hipMemcpyAsync(kt->support, sup.data(), sizeof(int32_t) * g->n_w, hipMemcpyHostToDevice, s));
+    WG_HIP_CHECK(hipMemcpyAsync(kt->offset, off.data(), sizeof(int64_t) * (g->n_w + 1), hipMemcpyHostToDevice, s));
+    WG_HIP_CHECK(hipMemcpyAsync(kt->wbound, wb.data(), sizeof(double) * g->n_w, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_slices, dim3(g->beta * g->beta, g->n_w), dim3(256), 0, s, a,
+                       (const int32_t *)kt->support, (const int64_t *)kt->offset, kt->data, kt->zeta);
+    if (hipGetLastError() != hipSuccess) return WG_EHIP;
+    WG_HIP_CHECK(hipStreamSynchronize(s));
+    if (support_out) memcpy(support_out, sup.data(), sizeof(int32_t) * g->n_w);
+    if (offset_out) memcpy(offset_out, off.data(), sizeof(int64_t) * (g->n_w + 1));
+    return WG_OK;
+}

@@ -1,0 +1,80 @@
+// Internal declarations shared by the libwgrid translation units (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wgrid.h"
+
+namespace wg {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxS = WG_MAX_SUPPORT;
+constexpr int kSlots = 8;          // owned cells per lane in the gridder (register budget)
+
+// ---------------------------------------------------------------------------------------
+// Plan layout (int32 words). Items are local chunks (first run, one past last run) of
+// consecutive runs of one segment that share a support; they are grouped by support, the
+// largest support first.
+//   [kPlanCount + S]   items with support S              (S = 1..63, odd)
+//   [kPlanOff + S]     first item slot of support S       (kPlanOff + 64 = total)
+//   [kPlanCur + S]     append cursor of support S
+//   [kPlanHdr ...]     items: 2 * capacity words
+//   then               runs per segment, scanned in place: n_seg + 1 words
+//   then               scan tile totals: n_tiles + 1 words
+// ---------------------------------------------------------------------------------------
+constexpr int kPlanCount = 0;
+constexpr int kPlanOff = 64;
+constexpr int kPlanCur = 129;
+constexpr int kPlanHdr = 256;
+constexpr int kScanTile = 4096;
+
+inline int64_t plan_items_at() { return kPlanHdr; }
+inline int64_t plan_segcnt_at(int64_t capacity) { return kPlanHdr + 2 * capacity; }
+inline int64_t plan_tiles_at(int64_t capacity, int64_t n_seg) { return plan_segcnt_at(capacity) + n_seg + 1; }
+inline int64_t n_scan_tiles(int64_t n_seg) { return (n_seg + kScanTile - 1) / kScanTile; }
+
+// Gridder decomposition of a support-S item into waves ("chunks"): G = 64/S lane groups
+// per wave, each lane owns one column class q = lane % S and a set of row classes; the S
+// row classes are spread over nchunk(S) waves x G groups with at most kSlots per lane.
+__host__ __device__ inline int groups_of(int S) { return S >= kWave ? 1 : kWave / S; }
+__host__ __device__ inline int nchunk_of(int S) {
+    int G = groups_of(S);
+    return (S + G * kSlots - 1) / (G * kSlots);
+}
+
+// Status helpers
+#define WG_HIP_CHECK(expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return WG_EHIP;                \
+    } while (0)
+
+inline int launch_status() { return hipGetLastError() == hipSuccess ? WG_OK : WG_EHIP; }
+
+// Geometry checks shared by every entry point.
+int check_geom(const wg_geom *g);
+int check_table(const wg_geom *g, const wg_ktable *kt);
+
+// Wave-level helpers --------------------------------------------------------------------
+__device__ inline uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & (kWave - 1);
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Float mod for small positive divisors: x mod S for 0 <= x < 2^22 and S <= 63.
+__device__ inline int mod_small(int x, int S, float rS) {
+    int q = (int)((float)x * rS);
+    int r = x - q * S;
+    r += (r < 0) ? S : 0;
+    r -= (r >= S) ? S : 0;
+    return r;
+}
+
+}  // namespace wg

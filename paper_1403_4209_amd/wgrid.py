@@ -1,0 +1,281 @@
+"""Python binding of libwgrid (the C ABI in include/wgrid.h).
+
+Argument marshalling only: every step of the computation runs in the HIP library. PyTorch
+supplies device memory and the current stream. Functions named like the C entry points take
+torch tensors and raise `WgError` on a non-zero status. The classes below own the buffers a
+call sequence needs (table, runs, statistics) and `GridFn` wraps grid/degrid as a
+torch.autograd.Function (forward = compress + grid, backward = degrid, the exact adjoint).
+
+The library must be built in-tree (`python -m paper_1403_4209_amd.build`); importing this
+module without it raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwgrid.so")
+
+WG_OK, WG_EINVAL, WG_ECAPACITY, WG_EHIP, WG_EUNSUPPORTED = 0, -1, -3, -4, -5
+WG_KF32, WG_KBF16, WG_KF16 = 0, 1, 2
+WG_COMPRESS = 1
+DTYPES = {"f32": WG_KF32, "bf16": WG_KBF16, "f16": WG_KF16}
+_ELEM_BYTES = {WG_KF32: 8, WG_KBF16: 4, WG_KF16: 4}
+
+
+class WgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {wg_status_str(status)} ({status})")
+        self.status = status
+
+
+class WgGeom(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("beta", ctypes.c_int32), ("n_w", ctypes.c_int32),
+                ("s_lo", ctypes.c_int32), ("s_hi", ctypes.c_int32), ("m_img", ctypes.c_int32),
+                ("du", ctypes.c_double), ("w_max", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+class WgKtable(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("n_w", ctypes.c_int32), ("beta", ctypes.c_int32),
+                ("s_max", ctypes.c_int32), ("support", ctypes.c_void_p), ("offset", ctypes.c_void_p),
+                ("wbound", ctypes.c_void_p), ("zeta", ctypes.c_void_p), ("data", ctypes.c_void_p),
+                ("data_cap", ctypes.c_int64)]
+
+
+class WgRuns(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("start", ctypes.c_void_p), ("len", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("plane", ctypes.c_void_p),
+                ("ou", ctypes.c_void_p), ("ov", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+                ("plan", ctypes.c_void_p), ("plan_elems", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libwgrid.so (after torch, so both use torch's HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1403_4209_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.wg_status_str.restype = ctypes.c_char_p
+        L.wg_status_str.argtypes = [ctypes.c_int]
+        L.wg_version.restype = ctypes.c_int
+        L.wg_ktable_sizes.restype = ctypes.c_int
+        L.wg_ktable_sizes.argtypes = [P, P, P]
+        L.wg_ktable_build.restype = ctypes.c_int
+        L.wg_ktable_build.argtypes = [P, P, P, ctypes.c_size_t, P, P, P]
+        L.wg_plan_elems.restype = I64
+        L.wg_plan_elems.argtypes = [I64, I64]
+        L.wg_compress.restype = ctypes.c_int
+        L.wg_compress.argtypes = [P, P, P, P, P, P, P, I64, I32, I32, P, P, P]
+        L.wg_grid.restype = ctypes.c_int
+        L.wg_grid.argtypes = [P, P, P, P, P, P]
+        L.wg_degrid.restype = ctypes.c_int
+        L.wg_degrid.argtypes = [P, P, P, P, P, P, P, I64, I32, I32, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(status: int, where: str):
+    if status != WG_OK:
+        raise WgError(status, where)
+
+
+# ------------------------------------------------------------------------- C entry points
+def wg_status_str(status: int) -> str:
+    return lib().wg_status_str(int(status)).decode()
+
+
+def wg_version() -> int:
+    return int(lib().wg_version())
+
+
+def wg_ktable_sizes(geom: WgGeom) -> tuple[int, int]:
+    n = ctypes.c_int64(0)
+    ws = ctypes.c_size_t(0)
+    _check(lib().wg_ktable_sizes(ctypes.byref(geom), ctypes.byref(n), ctypes.byref(ws)), "wg_ktable_sizes")
+    return int(n.value), int(ws.value)
+
+
+def wg_ktable_build(geom: WgGeom, kt: WgKtable, ws: torch.Tensor, stream=None):
+    sup = (ctypes.c_int32 * geom.n_w)()
+    off = (ctypes.c_int64 * (geom.n_w + 1))()
+    _check(lib().wg_ktable_build(ctypes.byref(geom), ctypes.byref(kt), _p(ws), ws.numel() * ws.element_size(),
+                                 sup, off, _stream(stream)), "wg_ktable_build")
+    return list(sup), list(off)
+
+
+def wg_plan_elems(capacity: int, n_segments: int) -> int:
+    return int(lib().wg_plan_elems(int(capacity), int(n_segments)))
+
+
+def wg_compress(geom, kt, uvw, inv_lambda, vis, weight, flag, nb, nc, nt, runs: WgRuns, stats: torch.Tensor,
+                stream=None):
+    _check(lib().wg_compress(ctypes.byref(geom), ctypes.byref(kt), _p(uvw), _p(inv_lambda), _p(vis), _p(weight),
+                             _p(flag), int(nb), int(nc), int(nt), ctypes.byref(runs), _p(stats), _stream(stream)),
+           "wg_compress")
+
+
+def wg_grid(geom, kt, runs: WgRuns, stats: torch.Tensor, grid: torch.Tensor, stream=None):
+    _check(lib().wg_grid(ctypes.byref(geom), ctypes.byref(kt), ctypes.byref(runs), _p(stats), _p(grid),
+                         _stream(stream)), "wg_grid")
+
+
+def wg_degrid(geom, kt, runs: WgRuns, stats, grid, uvw, weight, nb, nc, nt, vis_out, stream=None):
+    _check(lib().wg_degrid(ctypes.byref(geom), ctypes.byref(kt), ctypes.byref(runs), _p(stats), _p(grid), _p(uvw),
+                           _p(weight), int(nb), int(nc), int(nt), _p(vis_out), _stream(stream)), "wg_degrid")
+
+
+# -------------------------------------------------------------------------- owning helpers
+def make_geom(n, beta, n_w, s_lo, s_hi, m_img, du, w_max, compress=True) -> WgGeom:
+    return WgGeom(int(n), int(beta), int(n_w), int(s_lo), int(s_hi), int(m_img), float(du), float(w_max),
+                  WG_COMPRESS if compress else 0, 0)
+
+
+def geom_from_dict(d: dict, compress=True) -> WgGeom:
+    return make_geom(d["n"], d["beta"], d["n_w"], d["s_lo"], d["s_hi"], d["m_img"], d["du"], d["w_max"], compress)
+
+
+class KernelTable:
+    """Device-resident convolution-function table built by wg_ktable_build."""
+
+    def __init__(self, geom: WgGeom, dtype: str = "f32", device="cuda", stream=None):
+        dt = DTYPES[dtype]
+        cap, ws_bytes = wg_ktable_sizes(geom)
+        dev = torch.device(device)
+        self.dtype = dtype
+        self.support_d = torch.empty(geom.n_w, dtype=torch.int32, device=dev)
+        self.offset_d = torch.empty(geom.n_w + 1, dtype=torch.int64, device=dev)
+        self.wbound_d = torch.empty(geom.n_w, dtype=torch.float64, device=dev)
+        self.zeta_d = torch.empty(geom.n_w * geom.beta * geom.beta, dtype=torch.float64, device=dev)
+        self.data_d = torch.empty(cap * _ELEM_BYTES[dt], dtype=torch.uint8, device=dev)
+        self.kt = WgKtable(dt, geom.n_w, geom.beta, 0, _p(self.support_d), _p(self.offset_d), _p(self.wbound_d),
+                           _p(self.zeta_d), _p(self.data_d), cap)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        self.support, self.offset = wg_ktable_build(geom, self.kt, ws, stream)
+        del ws
+
+    def data_complex(self) -> torch.Tensor:
+        """The table samples as complex64 (upcast from bf16/f16), shape [offset[-1]]."""
+        n = self.offset[-1]
+        if self.dtype == "f32":
+            return torch.view_as_complex(self.data_d[: 8 * n].view(torch.float32).view(n, 2))
+        h = self.data_d[: 4 * n].view(torch.bfloat16 if self.dtype == "bf16" else torch.float16).view(n, 2)
+        return torch.view_as_complex(h.float().contiguous())
+
+
+@dataclass
+class Stats:
+    n_records: int
+    n_griddable: int
+    n_runs: int
+    n_compressed: int
+    upd_real: int
+    upd_saved: int
+    normaliser: float
+    n_items: int
+
+
+class Runs:
+    """Run list + plan + device statistics for one record batch."""
+
+    def __init__(self, capacity: int, n_segments: int, device="cuda"):
+        dev = torch.device(device)
+        cap = max(1, int(capacity))
+        self.capacity = cap
+        self.start = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.len = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.x = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.y = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.plane = torch.empty(cap, dtype=torch.int16, device=dev)
+        self.ou = torch.empty(cap, dtype=torch.int8, device=dev)
+        self.ov = torch.empty(cap, dtype=torch.int8, device=dev)
+        self.gamma = torch.empty(2 * cap, dtype=torch.float32, device=dev)
+        pe = wg_plan_elems(cap, n_segments)
+        self.plan = torch.empty(pe, dtype=torch.int32, device=dev)
+        self.stats_d = torch.zeros(8, dtype=torch.int64, device=dev)
+        self.c = WgRuns(cap, _p(self.start), _p(self.len), _p(self.x), _p(self.y), _p(self.plane), _p(self.ou),
+                        _p(self.ov), _p(self.gamma), _p(self.plan), pe)
+
+    def stats(self) -> Stats:
+        h = self.stats_d.cpu()
+        return Stats(*[int(v) for v in h[:6]], float(h[6:7].view(torch.float64)[0]), int(h[7]))
+
+    def host(self) -> dict:
+        """Run arrays on the host (first n_runs entries)."""
+        n = self.stats().n_runs
+        return dict(start=self.start[:n].cpu().numpy(), len=self.len[:n].cpu().numpy(),
+                    x=self.x[:n].cpu().numpy(), y=self.y[:n].cpu().numpy(),
+                    plane=self.plane[:n].cpu().numpy(), ou=self.ou[:n].cpu().numpy(),
+                    ov=self.ov[:n].cpu().numpy(),
+                    gamma=torch.view_as_complex(self.gamma[: 2 * n].view(n, 2)).cpu().numpy(), n_runs=n)
+
+
+def _f32_view(vis: torch.Tensor) -> torch.Tensor:
+    return torch.view_as_real(vis) if vis.is_complex() else vis
+
+
+class Gridder:
+    """compress -> grid -> degrid over one record batch with a fixed table."""
+
+    def __init__(self, geom: WgGeom, table: KernelTable, uvw, inv_lambda, weight=None, flag=None):
+        self.geom, self.table = geom, table
+        self.uvw, self.inv_lambda = uvw.contiguous(), inv_lambda.contiguous()
+        self.weight = None if weight is None else weight.contiguous()
+        self.flag = None if flag is None else flag.contiguous()
+        self.nb, self.nt = int(uvw.shape[0]), int(uvw.shape[1])
+        self.nc = int(inv_lambda.shape[0])
+        self.n_rec = self.nb * self.nc * self.nt
+        self.runs = Runs(self.n_rec, self.nb * self.nc, device=uvw.device)
+
+    def compress(self, vis, stream=None):
+        wg_compress(self.geom, self.table.kt, self.uvw, self.inv_lambda, _f32_view(vis.contiguous()), self.weight,
+                    self.flag, self.nb, self.nc, self.nt, self.runs.c, self.runs.stats_d, stream)
+
+    def grid(self, out=None, stream=None):
+        n = self.geom.n
+        if out is None:
+            out = torch.zeros((n, n), dtype=torch.complex64, device=self.uvw.device)
+        wg_grid(self.geom, self.table.kt, self.runs.c, self.runs.stats_d, torch.view_as_real(out), stream)
+        return out
+
+    def degrid(self, grid, out=None, stream=None):
+        if out is None:
+            out = torch.empty((self.nb, self.nc, self.nt), dtype=torch.complex64, device=self.uvw.device)
+        wg_degrid(self.geom, self.table.kt, self.runs.c, self.runs.stats_d, torch.view_as_real(grid.contiguous()),
+                  self.uvw, self.weight, self.nb, self.nc, self.nt, torch.view_as_real(out), stream)
+        return out
+
+
+class GridFn(torch.autograd.Function):
+    """grid = G(vis) with compression; backward returns G^H(grad_grid) via wg_degrid, the
+    adjoint for the real inner product Re<a, b> (PyTorch's complex-gradient convention)."""
+
+    @staticmethod
+    def forward(ctx, vis, gridder: Gridder):
+        gridder.compress(vis)
+        out = gridder.grid()
+        ctx.gridder = gridder
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_grid):
+        return ctx.gridder.degrid(grad_grid), None

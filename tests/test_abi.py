@@ -1,0 +1,92 @@
+"""The C ABI library loads, exports every function include/wgrid.h declares, and rejects
+invalid arguments on the host before touching the GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wgrid.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(wg_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def wg():
+    import torch  # noqa: F401  (load torch's HIP runtime first)
+    from paper_1403_4209_amd import wgrid
+    return wgrid
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ["wg_status_str", "wg_version", "wg_ktable_sizes", "wg_ktable_build", "wg_plan_elems",
+              "wg_compress", "wg_grid", "wg_degrid"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(wg):
+    L = ctypes.CDLL(wg.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_status_strings_and_version(wg):
+    assert wg.wg_status_str(0) == "ok"
+    assert wg.wg_status_str(-1) == "invalid argument"
+    assert wg.wg_status_str(12345) == "unknown status"
+    assert wg.wg_version() >= 100
+
+
+def test_ktable_sizes_and_geometry_validation(wg):
+    g = wg.make_geom(2048, 8, 32, 9, 63, 256, 60.0, 3.0e4)
+    elems, ws = wg.wg_ktable_sizes(g)
+    assert elems == 32 * 64 * 63 * 63 and ws > 0
+    bad = [
+        wg.make_geom(2047, 8, 32, 9, 63, 256, 60.0, 3.0e4),   # odd N
+        wg.make_geom(2048, 6, 32, 9, 63, 256, 60.0, 3.0e4),   # beta not a power of two
+        wg.make_geom(2048, 8, 32, 8, 63, 256, 60.0, 3.0e4),   # even support
+        wg.make_geom(2048, 8, 32, 9, 7, 256, 60.0, 3.0e4),    # s_hi < s_lo
+        wg.make_geom(2048, 8, 32, 9, 63, 256, -1.0, 3.0e4),   # du <= 0
+        wg.make_geom(2048, 8, 0, 9, 63, 256, 60.0, 3.0e4),    # no planes
+        wg.make_geom(2048, 8, 32, 9, 63, 100, 60.0, 3.0e4),   # m_img not a power of two
+        wg.make_geom(64, 2, 2, 7, 63, 16, 1.0, 1.0),          # matrix does not fit the plane
+    ]
+    for g in bad:
+        with pytest.raises(wg.WgError) as e:
+            wg.wg_ktable_sizes(g)
+        assert e.value.status == wg.WG_EINVAL
+    for g in [wg.make_geom(2048, 8, 32, 9, 65, 256, 60.0, 3.0e4),      # support above the limit
+              wg.make_geom(2048, 8, 300, 9, 63, 256, 60.0, 3.0e4),     # too many planes
+              wg.make_geom(2048, 8, 32, 9, 63, 1024, 60.0, 3.0e4)]:    # FFT above the limit
+        with pytest.raises(wg.WgError) as e:
+            wg.wg_ktable_sizes(g)
+        assert e.value.status == wg.WG_EUNSUPPORTED
+
+
+def test_entry_points_reject_null_arguments(wg):
+    L = wg.lib()
+    g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)
+    kt = wg.WgKtable(0, 8, 8, 7, 1, 1, 1, 1, 1, 10)
+    runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000)
+    by = ctypes.byref
+    assert L.wg_compress(by(g), by(kt), None, None, None, None, None, 1, 1, 1, by(runs), None, None) == wg.WG_EINVAL
+    assert L.wg_compress(None, by(kt), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
+    assert L.wg_compress(by(g), by(kt), 1, 1, 1, None, None, 0, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
+    assert L.wg_compress(by(g), by(kt), 1, 1, 1, None, None, 5, 1, 3, by(runs), 1, None) == wg.WG_ECAPACITY
+    assert L.wg_compress(by(g), by(kt), 1, 1, 1, None, None, 1 << 20, 64, 64, by(runs), 1, None) == wg.WG_EUNSUPPORTED
+    kt_bad = wg.WgKtable(0, 4, 8, 7, 1, 1, 1, 1, 1, 10)      # n_w mismatch
+    assert L.wg_compress(by(g), by(kt_bad), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
+    assert L.wg_grid(by(g), by(kt), by(runs), 1, None, None) == wg.WG_EINVAL
+    assert L.wg_grid(by(g), None, by(runs), 1, 1, None) == wg.WG_EINVAL
+    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, None, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
+    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, 5, 1, 3, 1, None) == wg.WG_ECAPACITY
+    assert L.wg_ktable_build(by(g), None, 1, 10, None, None, None) == wg.WG_EINVAL
+    kt_small = wg.WgKtable(0, 8, 8, 0, 1, 1, 1, 1, 1, 10)
+    assert L.wg_ktable_build(by(g), by(kt_small), 1, 10, None, None, None) == wg.WG_ECAPACITY
+    assert L.wg_plan_elems(-1, 1) == -1

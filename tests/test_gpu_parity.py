@@ -1,0 +1,357 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Bars (stated per result): run boundaries, keys and counters bit-exact; table supports
+bit-exact and samples equal to the oracle's FP64 table rounded to the storage type (to one
+unit in the last place where the two FP64 computations straddle a rounding boundary); grids
+and degridded visibilities within relative L2 1e-5 with FP32 tables and 3e-3 with BF16
+tables against the FP64 oracle on its FP64 table.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from oracle import ktable as okt  # noqa: E402
+from paper_1403_4209_amd import wgrid as wg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+_TABLES = {}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def otable(geom, dtype):
+    key = tuple(sorted(geom.items()))
+    if key not in _TABLES:
+        _TABLES[key] = {"f64": okt.build(geom, "f64")}
+    if dtype not in _TABLES[key]:
+        _TABLES[key][dtype] = okt.requantize(_TABLES[key]["f64"], dtype)
+    return _TABLES[key][dtype]
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(w):
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dt)  # noqa: E731
+    return (t(w["uvw"], torch.float64), t(w["il"], torch.float64), t(w["vis"], torch.complex64),
+            None if w.get("wt") is None else t(w["wt"], torch.float32),
+            None if w.get("flag") is None else t(w["flag"], torch.uint8))
+
+
+def run_gpu(geom, data, dtype="f32", compress=True, table=None):
+    g = wg.geom_from_dict(geom, compress)
+    if table is None:
+        table = wg.KernelTable(g, dtype, device=DEV)
+    uvw, il, vis, wt, fl = to_dev(data)
+    gr = wg.Gridder(g, table, uvw, il, wt, fl)
+    gr.compress(vis)
+    G = gr.grid()
+    torch.cuda.synchronize()
+    return table, gr, G
+
+
+def wl_dict(w):
+    return dict(uvw=w.uvw, il=w.inv_lambda, vis=w.vis, wt=w.weight, flag=w.flag)
+
+
+def cfg1():
+    w = workloads.make(1)
+    return w.geom, wl_dict(w)
+
+
+def cfg4_small():
+    # config-4 array and kernels (64 planes, supports 9..63), fewer baselines and channels
+    w = workloads.make(4, n_st=12, n_t=100, n_ch=3)
+    return w.geom, wl_dict(w)
+
+
+def compare_runs(gr, orc):
+    h = gr.runs.host()
+    st = gr.runs.stats()
+    assert h["n_runs"] == orc["n_runs"]
+    for k in ("start", "len", "x", "y", "plane", "ou", "ov"):
+        assert np.array_equal(h[k].astype(np.int64), orc[k].astype(np.int64)), k
+    assert [st.n_records, st.n_griddable, st.n_runs, st.n_compressed, st.upd_real, st.upd_saved] == \
+        [int(v) for v in orc["stats"]]
+    if orc["n_runs"]:
+        assert rel_l2(h["gamma"], orc["gamma"]) < 1e-6
+        assert abs(st.normaliser - orc["normaliser"]) <= 1e-6 * abs(orc["normaliser"])
+    return h, st
+
+
+# ------------------------------------------------------------------------------ table
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("case", ["cfg1", "cfg4"])
+def test_table_parity(case, dtype):
+    geom = cfg1()[0] if case == "cfg1" else cfg4_small()[0]
+    say("table", case, dtype, geom)
+    g = wg.geom_from_dict(geom)
+    tb = wg.KernelTable(g, dtype, device=DEV)
+    ref = otable(geom, dtype)
+    ref64 = otable(geom, "f64")
+    assert list(tb.support) == [int(s) for s in ref["support"]]
+    assert list(tb.offset) == [int(o) for o in ref["offset"]]
+    got = tb.data_complex().cpu().numpy().astype(np.complex128)
+    exp = ref["data"]
+    ulp = {"f32": 2.0 ** -23, "bf16": 2.0 ** -7, "f16": 2.0 ** -10}[dtype]
+    sub = 2.0 ** -24 if dtype == "f16" else 0.0       # f16 subnormal spacing
+    for part in (np.real, np.imag):
+        d = np.abs(part(got) - part(exp))
+        # FP64 round-off of the two FFTs is ~1e-16 of the peak (1.0): samples at that level
+        # (e.g. the imaginary part of the w=0 plane) may round differently
+        assert np.all(d <= ulp * np.abs(part(exp)) + 1e-13 + sub)
+        # a straddle needs |FP64 difference| (~1e-16) to reach half a unit of the value,
+        # so samples above 1e-4 of the peak should round identically almost always
+        big = np.abs(part(exp)) > 1e-4
+        assert np.mean(d[big] > 0) < 1e-3
+    # against the unrounded FP64 table: within half a unit of the storage type
+    e64 = np.abs(got - ref64["data"])
+    assert np.all(e64 <= 0.5 * ulp * np.sqrt(2) * np.abs(ref64["data"]) + 1e-13 + sub)
+    zeta = tb.zeta_d.cpu().numpy().reshape(ref["zeta"].shape)
+    assert np.max(np.abs(zeta - ref["zeta"])) <= 1e-9 * np.max(np.abs(ref["zeta"]))
+    wb = tb.wbound_d.cpu().numpy()
+    assert np.array_equal(wb[1:], ref["wbound"][1:])
+
+
+# ------------------------------------------------------------------------ compression
+@pytest.mark.parametrize("compress", [True, False])
+@pytest.mark.parametrize("case", ["cfg1", "cfg4"])
+def test_runs_bitexact(case, compress):
+    geom, data = cfg1() if case == "cfg1" else cfg4_small()
+    say("runs", case, compress)
+    _, gr, _ = run_gpu(geom, data, compress=compress)
+    orc = oracle.compress(geom, otable(geom, "f32"), data["uvw"], data["il"], data["vis"], data["wt"],
+                          data["flag"], compress=compress)
+    compare_runs(gr, orc)
+
+
+# --------------------------------------------------------------------------- gridding
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 3e-3), ("f16", 1e-3)])
+@pytest.mark.parametrize("case", ["cfg1", "cfg4"])
+def test_grid_parity(case, dtype, tol):
+    geom, data = cfg1() if case == "cfg1" else cfg4_small()
+    say("grid", case, dtype)
+    _, gr, G = run_gpu(geom, data, dtype=dtype)
+    t64 = otable(geom, "f64")
+    orc = oracle.compress(geom, t64, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"])
+    Go = oracle.grid(geom, t64, orc)
+    Gg = G.cpu().numpy().astype(np.complex128)
+    err = rel_l2(Gg, Go)
+    # the share of the error that is table rounding: grid the oracle with the rounded table
+    tq = otable(geom, dtype)
+    Gq = oracle.grid(geom, tq, oracle.compress(geom, tq, data["uvw"], data["il"], data["vis"], data["wt"]))
+    err_acc = rel_l2(Gg, Gq)
+    say(f"  rel L2 vs FP64 oracle {err:.3e}; vs oracle with rounded table {err_acc:.3e}")
+    assert err < tol
+    assert err_acc < 1e-5
+
+
+def test_compressed_grid_matches_uncompressed_gpu():
+    geom, data = cfg4_small()
+    _, _, Gc = run_gpu(geom, data, compress=True)
+    _, _, Gu = run_gpu(geom, data, compress=False)
+    assert rel_l2(Gc.cpu().numpy(), Gu.cpu().numpy()) < 1e-5
+
+
+# -------------------------------------------------------------------------- degridding
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 3e-3)])
+@pytest.mark.parametrize("case", ["cfg1", "cfg4"])
+def test_degrid_parity(case, dtype, tol):
+    geom, data = cfg1() if case == "cfg1" else cfg4_small()
+    say("degrid", case, dtype)
+    _, gr, _ = run_gpu(geom, data, dtype=dtype)
+    rng = np.random.default_rng(4)
+    n = geom["n"]
+    g = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64)
+    out = gr.degrid(torch.as_tensor(g).to(DEV))
+    torch.cuda.synchronize()
+    t64 = otable(geom, "f64")
+    orc = oracle.compress(geom, t64, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"])
+    ref = oracle.degrid(geom, t64, orc, g.astype(np.complex128), data["uvw"], data["wt"], data["vis"].shape)
+    err = rel_l2(out.cpu().numpy().astype(np.complex128), ref)
+    say(f"  degrid rel L2 {err:.3e}")
+    assert err < tol
+
+
+def test_adjoint_dot_product_gpu():
+    geom, data = cfg4_small()
+    _, gr, G = run_gpu(geom, data)
+    rng = np.random.default_rng(8)
+    n = geom["n"]
+    g = torch.as_tensor((rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64)).to(DEV)
+    v = torch.as_tensor(data["vis"]).to(DEV)
+    lhs = torch.vdot(G.flatten().to(torch.complex128), g.flatten().to(torch.complex128)).real
+    ghg = gr.degrid(g)
+    rhs = torch.vdot(v.flatten().to(torch.complex128), ghg.flatten().to(torch.complex128)).real
+    scale = float(torch.linalg.norm(G.to(torch.complex128)) * torch.linalg.norm(g.to(torch.complex128)))
+    assert abs(float(lhs - rhs)) < 1e-5 * scale
+
+
+def test_autograd_finite_difference():
+    """GridFn backward = degrid: central difference of L = ||IFFT(grid) - target||^2 along a
+    random direction equals Re<grad, direction> (L is quadratic in vis, so the central
+    difference has no truncation error; the loss is evaluated in FP64)."""
+    w = workloads.make(1, n_st=6, n_t=40, n_ch=2)
+    g = wg.geom_from_dict(w.geom)
+    table = wg.KernelTable(g, "f32", device=DEV)
+    uvw = torch.as_tensor(w.uvw).to(DEV)
+    il = torch.as_tensor(w.inv_lambda).to(DEV)
+    gridder = wg.Gridder(g, table, uvw, il)
+    v = torch.as_tensor(w.vis).to(DEV).requires_grad_(True)
+    rng = np.random.default_rng(1)
+
+    def image(vv):
+        return torch.fft.ifft2(wg.GridFn.apply(vv, gridder).to(torch.complex128))
+
+    with torch.no_grad():
+        scale = float(image(v).abs().std())
+    target = torch.as_tensor(rng.standard_normal((256, 256)) * scale).to(DEV)
+
+    def loss(vv):
+        img = image(vv)
+        return ((img.real - target) ** 2 + img.imag ** 2).sum()
+
+    L = loss(v)
+    L.backward()
+    grad = v.grad.detach().to(torch.complex128)
+    d = torch.as_tensor(rng.standard_normal(w.vis.shape) + 1j * rng.standard_normal(w.vis.shape)).to(DEV)
+    d = d.to(torch.complex64)
+    h = 0.5
+    with torch.no_grad():
+        fd = (loss(v + h * d) - loss(v - h * d)) / (2 * h)
+    an = torch.sum(grad.conj() * d.to(torch.complex128)).real
+    say(f"  FD {float(fd):.9e} analytic {float(an):.9e}")
+    assert abs(float(fd - an)) < 1e-4 * abs(float(an))
+
+
+# ------------------------------------------------------------------------- edge cases
+def _records(nb, nc, nt, geom, seed, spread=0.3):
+    rng = np.random.default_rng(seed)
+    lim = spread * geom["n"] * geom["du"]
+    uvw = np.stack([rng.uniform(-lim, lim, (nb, nt)), rng.uniform(-lim, lim, (nb, nt)),
+                    rng.uniform(-geom["w_max"], geom["w_max"], (nb, nt))], -1)
+    il = np.linspace(0.99, 1.01, nc)
+    vis = (rng.standard_normal((nb, nc, nt)) + 1j * rng.standard_normal((nb, nc, nt))).astype(np.complex64)
+    wt = rng.uniform(0.0, 2.0, (nb, nc, nt)).astype(np.float32)
+    return dict(uvw=uvw, il=il, vis=vis, wt=wt, flag=np.zeros((nb, nc, nt), np.uint8))
+
+
+EDGE_GEOM = dict(n=128, beta=8, n_w=6, s_lo=9, s_hi=31, m_img=128, du=20.0, w_max=400.0)
+
+
+@pytest.mark.parametrize("nt", [1, 63, 64, 65, 130, 257])
+def test_ragged_segments(nt):
+    say("ragged nt", nt)
+    data = _records(3, 2, nt, EDGE_GEOM, seed=nt)
+    # slow tracks so that runs form and cross 64-record steps
+    data["uvw"] = data["uvw"][:, :1, :] + np.cumsum(np.full((3, nt, 3), 0.05), axis=1) * [[[20.0, 7.0, 3.0]]]
+    _, gr, G = run_gpu(EDGE_GEOM, data)
+    orc = oracle.compress(EDGE_GEOM, otable(EDGE_GEOM, "f32"), data["uvw"], data["il"], data["vis"], data["wt"])
+    compare_runs(gr, orc)
+    Go = oracle.grid(EDGE_GEOM, otable(EDGE_GEOM, "f64"), orc)
+    assert rel_l2(G.cpu().numpy(), Go) < 1e-5
+
+
+def test_one_long_run_per_segment():
+    nt = 300
+    data = _records(2, 2, nt, EDGE_GEOM, seed=5)
+    data["uvw"][:] = data["uvw"][:, :1, :]
+    _, gr, G = run_gpu(EDGE_GEOM, data)
+    orc = oracle.compress(EDGE_GEOM, otable(EDGE_GEOM, "f32"), data["uvw"], data["il"], data["vis"], data["wt"])
+    h, st = compare_runs(gr, orc)
+    assert st.n_runs == 4 and list(h["len"]) == [nt] * 4
+    Go = oracle.grid(EDGE_GEOM, otable(EDGE_GEOM, "f64"), orc)
+    assert rel_l2(G.cpu().numpy(), Go) < 1e-5
+
+
+def test_flags_nan_offgrid_and_edges():
+    nt = 90
+    data = _records(4, 2, nt, EDGE_GEOM, seed=9, spread=0.55)   # some records off the grid
+    data["flag"][0, 0, ::3] = 1
+    data["flag"][1, :, :] = 1                                    # a fully flagged baseline
+    data["uvw"][2, 5, 0] = np.nan
+    data["uvw"][2, 6, 2] = np.inf
+    data["uvw"][2, 7, :] = -0.0
+    data["wt"][3, 1, :10] = 0.0
+    _, gr, G = run_gpu(EDGE_GEOM, data)
+    orc = oracle.compress(EDGE_GEOM, otable(EDGE_GEOM, "f32"), data["uvw"], data["il"], data["vis"], data["wt"],
+                          data["flag"])
+    h, st = compare_runs(gr, orc)
+    assert st.n_griddable < st.n_records
+    Go = oracle.grid(EDGE_GEOM, otable(EDGE_GEOM, "f64"), orc)
+    assert rel_l2(G.cpu().numpy(), Go) < 1e-5
+    out = gr.degrid(G)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.all(o[1] == 0)                       # flagged baseline -> exactly zero
+
+
+def test_everything_flagged():
+    data = _records(2, 2, 70, EDGE_GEOM, seed=2)
+    data["flag"][:] = 1
+    _, gr, G = run_gpu(EDGE_GEOM, data)
+    st = gr.runs.stats()
+    assert st.n_runs == 0 and st.n_griddable == 0 and st.n_items == 0
+    assert not torch.any(G != 0)
+    out = gr.degrid(G)
+    torch.cuda.synchronize()
+    assert not torch.any(out != 0)
+
+
+def test_maximum_support_and_grid_border():
+    geom = dict(n=160, beta=8, n_w=2, s_lo=63, s_hi=63, m_img=256, du=10.0, w_max=100.0)
+    nt = 8
+    # pixels chosen so that footprints touch the first and last rows/columns of the grid
+    # a = X + n/2 - H must lie in [0, n - S]: X in [-49, 48]
+    pu = np.array([-49, 48, -50, 49, 0, 3, -5, 10])   # columns 0 and n-1 touched; two just beyond
+    pv = np.array([0, 1, 2, 3, -49, 48, 7, -2])       # rows 0 and n-1 touched
+    uvw = np.zeros((1, nt, 3))
+    uvw[0, :, 0] = pu * geom["du"]
+    uvw[0, :, 1] = pv * geom["du"]
+    uvw[0, :, 2] = np.linspace(5, 90, nt)       # w >= 0: no flip, pixels as listed
+    data = dict(uvw=uvw, il=np.array([1.0]), vis=(np.arange(nt) + 1j).astype(np.complex64)[None, None, :],
+                wt=None, flag=None)
+    _, gr, G = run_gpu(geom, data)
+    orc = oracle.compress(geom, otable(geom, "f32"), data["uvw"], data["il"], data["vis"])
+    h, st = compare_runs(gr, orc)
+    assert st.n_griddable == nt - 2
+    Go = oracle.grid(geom, otable(geom, "f64"), orc)
+    assert rel_l2(G.cpu().numpy(), Go) < 1e-5
+
+
+# ------------------------------------------------------------ full-size (bench) config
+def test_full_config2_runs_and_sampled_grid():
+    """Config 2 at full size in the launch configuration the benchmark times: every run
+    boundary and key bit-exact over all 7.75 M records; grid parity on a sampled subset of
+    baselines (every 31st)."""
+    w = workloads.make(2, device=DEV)
+    say("cfg2 records", w.n_records, w.geom)
+    vis_h = w.vis.cpu().numpy()
+    data = dict(uvw=w.uvw, il=w.inv_lambda, vis=vis_h, wt=None, flag=None)
+    table, gr, _ = run_gpu(w.geom, data)
+    orc = oracle.compress(w.geom, otable(w.geom, "f32"), w.uvw, w.inv_lambda, vis_h)
+    compare_runs(gr, orc)
+    sub = slice(0, None, 31)
+    d2 = dict(uvw=w.uvw[sub], il=w.inv_lambda, vis=vis_h[sub], wt=None, flag=None)
+    _, gr2, G2 = run_gpu(w.geom, d2, table=table)
+    t64 = otable(w.geom, "f64")
+    o2 = oracle.compress(w.geom, t64, d2["uvw"], d2["il"], d2["vis"])
+    Go = oracle.grid(w.geom, t64, o2)
+    err = rel_l2(G2.cpu().numpy().astype(np.complex128), Go)
+    say(f"  cfg2 sampled grid rel L2 {err:.3e}")
+    assert err < 1e-5
