@@ -34,12 +34,25 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the BF16 and uncompressed variants")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (to scale HBM counters)")
     return ap.parse_args()
 
 
-def gpu_step(wg, geom, kt, ws, tb_buf, gridder, vis, grid, vis_out, ev):
-    """One pass of the hot path; records events between phases on the current stream."""
+def copy_calibration(nbytes: int):
+    """A plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE readings give the
+    factor between the counters and real HBM bytes."""
     import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "dispatches": 3}), flush=True)
+
+
+def gpu_step(wg, geom, kt, ws, gridder, vis, grid, vis_out, ev):
+    """One pass of the hot path; records events between phases on the current stream."""
     ev[0].record()
     wg.wg_ktable_build(geom, kt, ws)
     ev[1].record()
@@ -100,6 +113,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
 
@@ -126,12 +142,12 @@ def main():
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
 
     for _ in range(args.warmup):
-        gpu_step(wg, geom, table.kt, ws, None, gridder, vis, grid, vis_out, ev)
+        gpu_step(wg, geom, table.kt, ws, gridder, vis, grid, vis_out, ev)
     torch.cuda.synchronize()
     phase = np.zeros(5)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        gpu_step(wg, geom, table.kt, ws, None, gridder, vis, grid, vis_out, ev)
+        gpu_step(wg, geom, table.kt, ws, gridder, vis, grid, vis_out, ev)
         torch.cuda.synchronize()
         phase += [ev[i].elapsed_time(ev[i + 1]) for i in range(5)]
     torch.cuda.synchronize()

@@ -43,6 +43,42 @@ __device__ inline float2 load_k(const void *data, int64_t idx) {
     return make_float2((float)lo, (float)hi);
 }
 
+// Raw table sample as fetched (converted to float only when used, so that a wave can keep
+// several loads in flight).
+template <int DT> struct KRaw { using type = uint32_t; };
+template <> struct KRaw<WG_KF32> { using type = float2; };
+
+template <int DT>
+__device__ inline typename KRaw<DT>::type load_raw(const void *data, int64_t idx) {
+    if constexpr (DT == WG_KF32)
+        return ((const float2 *)data)[idx];
+    else
+        return ((const uint32_t *)data)[idx];
+}
+
+template <int DT>
+__device__ inline float2 to_float2(typename KRaw<DT>::type u) {
+    if constexpr (DT == WG_KF32) {
+        return u;
+    } else if constexpr (DT == WG_KBF16) {
+        return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xFFFF0000u));
+    } else {
+        _Float16 lo, hi;
+        const uint16_t l16 = (uint16_t)(u & 0xFFFFu), h16 = (uint16_t)(u >> 16);
+        __builtin_memcpy(&lo, &l16, 2);
+        __builtin_memcpy(&hi, &h16, 2);
+        return make_float2((float)lo, (float)hi);
+    }
+}
+
+template <int DT>
+__device__ inline typename KRaw<DT>::type raw_zero() {
+    if constexpr (DT == WG_KF32)
+        return make_float2(0.f, 0.f);
+    else
+        return 0u;
+}
+
 __device__ inline void kahan_add(float &s, float &c, float v) {
     const float y = v - c;
     const float t = s + y;
@@ -72,15 +108,79 @@ __device__ void build_units(const int32_t *plan, bool per_row_chunk, UnitTable *
     t->n = m;
 }
 
+// Run records of up to 64 consecutive runs, one per lane, with everything the per-run loop
+// needs precomputed in parallel; the loop then broadcasts run t with v_readlane.
+struct RunBatch {
+    int ax, row0, am, r0m, kb, ok;
+    float gr, gi;
+};
+
+__device__ inline int rl(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
+__device__ inline float rlf(float v, int t) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t)); }
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ inline RunBatch load_batch(const GArgs &a, int S, int j, bool valid, const int64_t *koff) {
+    RunBatch b;
+    b.ok = 0;
+    b.ax = b.row0 = b.am = b.r0m = b.kb = 0;
+    b.gr = b.gi = 0.f;
+    if (valid) {
+        const int H = (S - 1) >> 1, half = a.n >> 1, hb = a.beta >> 1;
+        const int X = a.x[j], Y = a.y[j], k = a.plane[j];
+        const int sigma = (a.ov[j] + hb - 1) * a.beta + (a.ou[j] + hb - 1);
+        const float2 g = a.gamma[j];
+        const int ax = X + half - H, row0 = Y + half - H;
+        const int64_t kbase = koff[k] + (int64_t)sigma * S * S;
+        // runs from wg_compress with the same geometry and table always pass; anything else
+        // is skipped rather than read or written out of bounds
+        if (ax >= 0 && ax + S <= a.n && row0 >= 0 && row0 + S <= a.n && kbase >= 0 &&
+            kbase + (int64_t)S * S <= a.data_cap) {
+            b.ok = 1;
+            b.ax = ax;
+            b.row0 = row0;
+            b.am = ax % S;
+            b.r0m = row0 % S;
+            b.kb = (int)kbase;
+            b.gr = g.x;
+            b.gi = g.y;
+        }
+    }
+    return b;
+}
+
+// Buffer resource for the table: 32-bit byte offsets, and reads beyond num_bytes return 0.
+__device__ inline __amdgpu_buffer_rsrc_t table_rsrc(const void *data, int64_t num_bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(data), (short)0, (int)num_bytes, 0x00020000);
+}
+
 template <int DT>
-__device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane,
-                           const int64_t *koff) {
+__device__ inline typename KRaw<DT>::type buf_load(__amdgpu_buffer_rsrc_t rs, int off) {
+    if constexpr (DT == WG_KF32) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        return make_float2(__int_as_float(v[0]), __int_as_float(v[1]));
+    } else {
+        return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    }
+}
+
+// Samples and cell rows of one run for the lane's slots, fetched one run ahead.
+template <int DT>
+struct Stage {
+    typename KRaw<DT>::type k[kSlots];
+    int yc[kSlots];
+};
+
+template <int DT>
+__device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
+    constexpr int esz = (DT == WG_KF32) ? 8 : 4;
     const int G = groups_of(S), R = nchunk_of(S) * G;
     const int grp = lane / S, q = lane - grp * S;
-    const bool active = grp < G;
     const int p0 = chunk * G + grp;
-    const float rS = 1.0f / (float)S;
-    const int H = (S - 1) >> 1, S2 = S * S, half = a.n >> 1, hb = a.beta >> 1;
+    const bool active = grp < G;
+    const int nslots = uni((S - chunk * G + R - 1) / R);  // slots of the fullest lane group
+    const bool last_ok = active && p0 + (nslots - 1) * R < S;
+    const int rowB = S * esz;
+    const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
 
     float acc_r[kSlots], acc_i[kSlots], cmp_r[kSlots], cmp_i[kSlots];
     int cur_y[kSlots];
@@ -98,49 +198,71 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
         acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
     };
 
-    for (int j = rb; j < re; ++j) {
-        const int X = a.x[j], Y = a.y[j], k = a.plane[j];
-        const int sigma = (a.ov[j] + hb - 1) * a.beta + (a.ou[j] + hb - 1);
-        const float2 gam = a.gamma[j];
-        const int ax = X + half - H, row0 = Y + half - H;
-        const int64_t kbase = koff[k] + (int64_t)sigma * S2;
-        // runs from wg_compress with the same geometry and table always pass; anything else
-        // is skipped rather than read or written out of bounds
-        if (ax < 0 || ax + S > a.n || row0 < 0 || row0 + S > a.n || kbase < 0 || kbase + S2 > a.data_cap)
-            continue;
-        const int am = mod_small(ax, S, rS), r0m = mod_small(row0, S, rS);
-        int jj = q - am;
-        jj += (jj < 0) ? S : 0;
-        const int xc = ax + jj;
-        if (active && xc != cur_x) {
+    for (int base = rb; base < re; base += kWave) {
+        const int n = min(kWave, re - base);
+        const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
+
+        // column of the lane's cells and their first row, for run t
+        auto fetch = [&](int t, Stage<DT> &st, int &xc) {
+            int jj = q - rl(b.am, t);
+            jj += (jj < 0) ? S : 0;
+            int ii = p0 - rl(b.r0m, t);
+            ii += (ii < 0) ? S : 0;
+            const int row0 = rl(b.row0, t);
+            const int colB = rl(b.kb, t) * esz + jj * esz;
+            xc = rl(b.ax, t) + jj;
 #pragma unroll
-            for (int m = 0; m < kSlots; ++m)
-                if (cur_y[m] >= 0) {
-                    commit(m);
-                    cur_y[m] = -1;
+            for (int m = 0; m < kSlots; ++m) {
+                if (m < nslots) {
+                    if (m > 0) {
+                        ii += R;
+                        ii -= (ii >= S) ? S : 0;
+                    }
+                    st.yc[m] = row0 + ii;
+                    st.k[m] = (m < nslots - 1 || last_ok) ? buf_load<DT>(rs, colB + ii * rowB) : raw_zero<DT>();
                 }
-            cur_x = xc;
-        }
-        int p = p0;
-        int ii = p0 - r0m;
-        ii += (ii < 0) ? S : 0;
-#pragma unroll
-        for (int m = 0; m < kSlots; ++m) {
-            if (active && p < S) {
-                const int yc = row0 + ii;
-                if (yc != cur_y[m]) {
-                    if (cur_y[m] >= 0) commit(m);
-                    cur_y[m] = yc;
-                }
-                const float2 kv = load_k<DT>(a.data, kbase + ii * S + jj);
-                const float pr = fmaf(gam.x, kv.x, -(gam.y * kv.y));
-                const float pi = fmaf(gam.x, kv.y, gam.y * kv.x);
-                kahan_add(acc_r[m], cmp_r[m], pr);
-                kahan_add(acc_i[m], cmp_i[m], pi);
             }
-            p += R;
-            ii += R;
-            ii -= (ii >= S) ? S : 0;
+        };
+        auto accumulate = [&](int t, const Stage<DT> &st, int xc) {
+            if (!rl(b.ok, t)) return;
+            const float gr = rlf(b.gr, t), gi = rlf(b.gi, t);
+            if (xc != cur_x) {
+#pragma unroll
+                for (int m = 0; m < kSlots; ++m)
+                    if (cur_y[m] >= 0) {
+                        commit(m);
+                        cur_y[m] = -1;
+                    }
+                cur_x = xc;
+            }
+#pragma unroll
+            for (int m = 0; m < kSlots; ++m) {
+                if (m < nslots && (m < nslots - 1 || last_ok)) {
+                    if (st.yc[m] != cur_y[m]) {
+                        if (cur_y[m] >= 0) commit(m);
+                        cur_y[m] = st.yc[m];
+                    }
+                    const float2 kv = to_float2<DT>(st.k[m]);
+                    const float pr = fmaf(gr, kv.x, -(gi * kv.y));
+                    const float pi = fmaf(gr, kv.y, gi * kv.x);
+                    kahan_add(acc_r[m], cmp_r[m], pr);
+                    kahan_add(acc_i[m], cmp_i[m], pi);
+                }
+            }
+        };
+
+        if (active) {
+            Stage<DT> sa, sb;
+            int xa, xb;
+            fetch(0, sa, xa);
+            for (int t = 0; t < n; t += 2) {
+                if (t + 1 < n) fetch(t + 1, sb, xb);
+                accumulate(t, sa, xa);
+                if (t + 1 < n) {
+                    if (t + 2 < n) fetch(t + 2, sa, xa);
+                    accumulate(t + 1, sb, xb);
+                }
+            }
         }
     }
     if (active) {
@@ -157,17 +279,17 @@ __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     if (threadIdx.x == 0) build_units(a.plan, true, &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
-    const int nunits = ut.first[ut.n];
+    const int nunits = uni(ut.first[ut.n]);
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
-    for (int u = blockIdx.x * wpb + threadIdx.x / kWave; u < nunits; u += gridDim.x * wpb) {
+    for (int u = uni(blockIdx.x * wpb + threadIdx.x / kWave); u < nunits; u += gridDim.x * wpb) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = ut.S[m], nch = nchunk_of(S);
-        const int rel = u - ut.first[m];
+        const int S = uni(ut.S[m]), nch = nchunk_of(S);
+        const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
-        const int slot = a.plan[kPlanOff + S] + item;
-        grid_chunk<DT>(a, S, chunk, a.items[2 * slot], a.items[2 * slot + 1], lane, koff);
+        const int slot = uni(a.plan[kPlanOff + S]) + item;
+        grid_chunk<DT>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
     }
 }
 
@@ -177,46 +299,62 @@ template <int DT>
 __device__ void degrid_chunk(const GArgs &a, int S, int rb, int re, int lane, const int64_t *koff) {
     const int G = groups_of(S);
     const int grp = lane / S, q = lane - grp * S;
-    const bool active = grp < G;
-    const float rS = 1.0f / (float)S;
-    const int H = (S - 1) >> 1, S2 = S * S, half = a.n >> 1, hb = a.beta >> 1;
+    const bool active = grp < G && grp < S;
     const int64_t seglen = (int64_t)a.nt * a.nc;
     const float2 *grid = (const float2 *)a.grid;
-    for (int j = rb; j < re; ++j) {
-        const int X = a.x[j], Y = a.y[j], k = a.plane[j];
-        const int sigma = (a.ov[j] + hb - 1) * a.beta + (a.ou[j] + hb - 1);
-        const int ax = X + half - H, row0 = Y + half - H;
-        const int64_t kbase = koff[k] + (int64_t)sigma * S2;
-        if (ax < 0 || ax + S > a.n || row0 < 0 || row0 + S > a.n || kbase < 0 || kbase + S2 > a.data_cap)
-            continue;
-        const int am = mod_small(ax, S, rS), r0m = mod_small(row0, S, rS);
-        int jj = q - am;
-        jj += (jj < 0) ? S : 0;
-        float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
-        if (active) {
-            int ii = grp - r0m;
-            ii += (ii < 0) ? S : 0;
-            for (int p = grp; p < S; p += G) {
-                const float2 kv = load_k<DT>(a.data, kbase + ii * S + jj);
-                const float2 gv = grid[(int64_t)(row0 + ii) * a.n + ax + jj];
-                const float pr = fmaf(kv.x, gv.x, kv.y * gv.y);
-                const float pi = fmaf(kv.x, gv.y, -(kv.y * gv.x));
-                kahan_add(sr, cr, pr);
-                kahan_add(si, ci, pi);
-                ii += G;
-                ii -= (ii >= S) ? S : 0;
-            }
+    for (int base = rb; base < re; base += kWave) {
+        const int n = min(kWave, re - base);
+        const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
+        int my_start = 0, my_len = 0;
+        if (lane < n) {
+            my_start = a.start[base + lane];
+            my_len = a.len[base + lane];
         }
-        const float dr = wave_sum(sr - cr), di = wave_sum(si - ci);
-        const int r0 = a.start[j], n = a.len[j];
-        for (int m = lane; m < n; m += kWave) {
-            const int64_t r = (int64_t)r0 + m;
-            if (r < 0 || r >= a.n_rec) break;
-            const int64_t b = r / seglen;
-            const int64_t t = r - (r / a.nt) * a.nt;
-            const double wm = a.uvw[(b * a.nt + t) * 3 + 2];
-            const float e = a.wt ? a.wt[r] : 1.0f;
-            a.vis_out[r] = make_float2(e * dr, e * ((wm >= 0.0) ? di : -di));
+        for (int t = 0; t < n; ++t) {
+            const int ok = rl(b.ok, t);
+            const int r0 = rl(my_start, t), cnt = rl(my_len, t);
+            // member weights and flip signs, fetched before the dot product is formed
+            float e = 0.f;
+            double wm = 0.0;
+            const int64_t r = (int64_t)r0 + lane;
+            const bool mine = lane < cnt && r < a.n_rec;
+            if (mine) {
+                const int64_t bb = r / seglen, tt = r - (r / a.nt) * a.nt;
+                wm = a.uvw[(bb * a.nt + tt) * 3 + 2];
+                e = a.wt ? a.wt[r] : 1.0f;
+            }
+            float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
+            if (ok && active) {
+                const int ax = rl(b.ax, t), row0 = rl(b.row0, t), kb = rl(b.kb, t);
+                int jj = q - rl(b.am, t);
+                jj += (jj < 0) ? S : 0;
+                int ii = grp - rl(b.r0m, t);
+                ii += (ii < 0) ? S : 0;
+                const float2 *gcol = grid + (int64_t)row0 * a.n + ax + jj;
+#pragma unroll 4
+                for (int p = grp; p < S; p += G) {
+                    const float2 kv = load_k<DT>(a.data, (int64_t)kb + ii * S + jj);
+                    const float2 gv = gcol[(int64_t)ii * a.n];
+                    const float pr = fmaf(kv.x, gv.x, kv.y * gv.y);
+                    const float pi = fmaf(kv.x, gv.y, -(kv.y * gv.x));
+                    kahan_add(sr, cr, pr);
+                    kahan_add(si, ci, pi);
+                    ii += G;
+                    ii -= (ii >= S) ? S : 0;
+                }
+            }
+            const float dr = wave_sum(sr - cr), di = wave_sum(si - ci);
+            if (ok) {
+                if (mine) a.vis_out[r] = make_float2(e * dr, e * ((wm >= 0.0) ? di : -di));
+                for (int m = kWave + lane; m < cnt; m += kWave) {  // runs longer than a wave
+                    const int64_t rr = (int64_t)r0 + m;
+                    if (rr >= a.n_rec) break;
+                    const int64_t bb = rr / seglen, tt = rr - (rr / a.nt) * a.nt;
+                    const double w2 = a.uvw[(bb * a.nt + tt) * 3 + 2];
+                    const float e2 = a.wt ? a.wt[rr] : 1.0f;
+                    a.vis_out[rr] = make_float2(e2 * dr, e2 * ((w2 >= 0.0) ? di : -di));
+                }
+            }
         }
     }
 }
@@ -228,15 +366,15 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     if (threadIdx.x == 0) build_units(a.plan, false, &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
-    const int nunits = ut.first[ut.n];
+    const int nunits = uni(ut.first[ut.n]);
     const int lane = threadIdx.x & (kWave - 1);
     const int wpb = blockDim.x / kWave;
-    for (int u = blockIdx.x * wpb + threadIdx.x / kWave; u < nunits; u += gridDim.x * wpb) {
+    for (int u = uni(blockIdx.x * wpb + threadIdx.x / kWave); u < nunits; u += gridDim.x * wpb) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = ut.S[m];
-        const int slot = a.plan[kPlanOff + S] + (u - ut.first[m]);
-        degrid_chunk<DT>(a, S, a.items[2 * slot], a.items[2 * slot + 1], lane, koff);
+        const int S = uni(ut.S[m]);
+        const int slot = uni(a.plan[kPlanOff + S]) + (u - uni(ut.first[m]));
+        degrid_chunk<DT>(a, S, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
     }
 }
 
@@ -292,6 +430,7 @@ extern "C" int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *run
     if ((st = check_table(g, kt)) != WG_OK) return st;
     if ((st = check_runs(runs)) != WG_OK) return st;
     if (!grid || !stats) return WG_EINVAL;
+    if (kt->data_cap >= ((int64_t)1 << 28)) return WG_EUNSUPPORTED;  // byte offsets stay 32-bit
     GArgs a = make_args(g, kt, runs);
     a.grid = grid;
     hipStream_t s = (hipStream_t)stream;
@@ -312,6 +451,7 @@ extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *r
     if ((st = check_table(g, kt)) != WG_OK) return st;
     if ((st = check_runs(runs)) != WG_OK) return st;
     if (!grid || !stats || !uvw || !vis_out || nb < 1 || nc < 1 || nt < 1) return WG_EINVAL;
+    if (kt->data_cap >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
     const int64_t n_rec = nb * (int64_t)nc * nt;
     if (n_rec > runs->capacity) return WG_ECAPACITY;
     GArgs a = make_args(g, kt, runs);
