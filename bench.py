@@ -54,7 +54,7 @@ def copy_calibration(nbytes: int):
 def gpu_step(wg, geom, kt, ws, gridder, vis, grid, vis_out, ev):
     """One pass of the hot path; records events between phases on the current stream."""
     ev[0].record()
-    wg.wg_ktable_build(geom, kt, ws)
+    wg.wg_ktable_build(geom, kt, ws, host_copies=False)
     ev[1].record()
     gridder.compress(vis)
     ev[2].record()

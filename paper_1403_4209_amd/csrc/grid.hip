@@ -1,13 +1,12 @@
 // Gridding phase (eq. gridding) and its adjoint on gfx950.
 //
 // Work unit = one local chunk (consecutive runs of one baseline/channel trajectory with a
-// common support S) x one slice of its rows. Inside a wavefront, lane l owns the column
-// class q = l mod S of every footprint and a few row classes p (cells with x = q mod S and
-// y = p mod S): as the footprint slides along the trajectory a lane keeps updating the same
-// cell, accumulating gamma*K in registers with Kahan compensation, and commits (one FP32
-// atomic add per component) only when its cell leaves the footprint -- the ownership idea of
-// Romein's gridder, applied per wavefront. Kernel samples are read straight into registers:
-// for a fixed row class the 64 lanes read a contiguous (rotated) row of the S x S matrix.
+// common support S) x one share of its S*S cell classes. A class (p, q) stands for the grid
+// cells with y = p mod S and x = q mod S; every footprint position holds exactly one cell of
+// each class. Lane l owns a few classes: as the footprint slides along the trajectory the
+// lane keeps updating the same cell, accumulating gamma*K in registers with Kahan
+// compensation, and commits (one FP32 atomic add per component) only when the cell leaves
+// the footprint -- the ownership idea of Romein's gridder, applied per wavefront.
 #include "wg_common.hpp"
 
 #pragma clang fp contract(off)
@@ -170,29 +169,46 @@ struct Stage {
     int yc[kSlots];
 };
 
+// Persistent walk over the support-sorted work list (largest supports first): wave w takes
+// units w, w + W, ... where W is the number of waves in the launch.
+template <typename F>
+__device__ inline void for_each_unit(int nunits, F &&body) {
+    const int wpb = blockDim.x / kWave;
+    const int stride = gridDim.x * wpb;
+    for (int u = uni(blockIdx.x * wpb + (int)(threadIdx.x / kWave)); u < nunits; u += stride) body(u);
+}
+
 template <int DT>
 __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
-    const int G = groups_of(S), R = nchunk_of(S) * G;
-    const int grp = lane / S, q = lane - grp * S;
-    const int p0 = chunk * G + grp;
-    const bool active = grp < G;
-    const int nslots = uni((S - chunk * G + R - 1) / R);  // slots of the fullest lane group
-    const bool last_ok = active && p0 + (nslots - 1) * R < S;
-    const int rowB = S * esz;
+    const int S2 = S * S, nch = nchunk_of(S);
+    const int cpc = (S2 + nch - 1) / nch;  // classes per wave
+    const int c0 = chunk * cpc, c1 = min(S2, c0 + cpc);
+    const int nslots = uni((c1 - c0 + kWave - 1) / kWave);
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
+    const float rS = 1.0f / (float)S;
 
+    int cp[kSlots], cq[kSlots];  // the lane's classes (row class, column class); -1 = none
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) {
+        const int c = c0 + m * kWave + lane;
+        cp[m] = -1;
+        cq[m] = 0;
+        if (m < nslots && c < c1) {
+            const int pp = (int)((float)c * rS + 0.5f * rS);
+            cp[m] = pp;
+            cq[m] = c - pp * S;
+        }
+    }
     float acc_r[kSlots], acc_i[kSlots], cmp_r[kSlots], cmp_i[kSlots];
-    int cur_y[kSlots];
+    int cur[kSlots];  // owned cell (y*n + x), -1 = none
 #pragma unroll
     for (int m = 0; m < kSlots; ++m) {
         acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
-        cur_y[m] = -1;
+        cur[m] = -1;
     }
-    int cur_x = -1;
-
     auto commit = [&](int m) {
-        float *cell = a.grid + 2 * ((int64_t)cur_y[m] * a.n + cur_x);
+        float *cell = a.grid + 2 * (int64_t)cur[m];
         unsafeAtomicAdd(cell, acc_r[m] - cmp_r[m]);
         unsafeAtomicAdd(cell + 1, acc_i[m] - cmp_i[m]);
         acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
@@ -202,45 +218,32 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
         const int n = min(kWave, re - base);
         const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
 
-        // column of the lane's cells and their first row, for run t
-        auto fetch = [&](int t, Stage<DT> &st, int &xc) {
-            int jj = q - rl(b.am, t);
-            jj += (jj < 0) ? S : 0;
-            int ii = p0 - rl(b.r0m, t);
-            ii += (ii < 0) ? S : 0;
-            const int row0 = rl(b.row0, t);
-            const int colB = rl(b.kb, t) * esz + jj * esz;
-            xc = rl(b.ax, t) + jj;
+        // cells and samples of the lane's classes for run t
+        auto fetch = [&](int t, Stage<DT> &st) {
+            const int am = rl(b.am, t), r0m = rl(b.r0m, t);
+            const int cell0 = rl(b.row0, t) * a.n + rl(b.ax, t);
+            const int kbB = rl(b.kb, t) * esz;
 #pragma unroll
             for (int m = 0; m < kSlots; ++m) {
                 if (m < nslots) {
-                    if (m > 0) {
-                        ii += R;
-                        ii -= (ii >= S) ? S : 0;
-                    }
-                    st.yc[m] = row0 + ii;
-                    st.k[m] = (m < nslots - 1 || last_ok) ? buf_load<DT>(rs, colB + ii * rowB) : raw_zero<DT>();
+                    int ii = cp[m] - r0m;
+                    ii += (ii < 0) ? S : 0;
+                    int jj = cq[m] - am;
+                    jj += (jj < 0) ? S : 0;
+                    st.yc[m] = cell0 + ii * a.n + jj;
+                    st.k[m] = cp[m] >= 0 ? buf_load<DT>(rs, kbB + (ii * S + jj) * esz) : raw_zero<DT>();
                 }
             }
         };
-        auto accumulate = [&](int t, const Stage<DT> &st, int xc) {
+        auto accumulate = [&](int t, const Stage<DT> &st) {
             if (!rl(b.ok, t)) return;
             const float gr = rlf(b.gr, t), gi = rlf(b.gi, t);
-            if (xc != cur_x) {
-#pragma unroll
-                for (int m = 0; m < kSlots; ++m)
-                    if (cur_y[m] >= 0) {
-                        commit(m);
-                        cur_y[m] = -1;
-                    }
-                cur_x = xc;
-            }
 #pragma unroll
             for (int m = 0; m < kSlots; ++m) {
-                if (m < nslots && (m < nslots - 1 || last_ok)) {
-                    if (st.yc[m] != cur_y[m]) {
-                        if (cur_y[m] >= 0) commit(m);
-                        cur_y[m] = st.yc[m];
+                if (m < nslots && cp[m] >= 0) {
+                    if (st.yc[m] != cur[m]) {
+                        if (cur[m] >= 0) commit(m);
+                        cur[m] = st.yc[m];
                     }
                     const float2 kv = to_float2<DT>(st.k[m]);
                     const float pr = fmaf(gr, kv.x, -(gi * kv.y));
@@ -251,25 +254,20 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
             }
         };
 
-        if (active) {
-            Stage<DT> sa, sb;
-            int xa, xb;
-            fetch(0, sa, xa);
-            for (int t = 0; t < n; t += 2) {
-                if (t + 1 < n) fetch(t + 1, sb, xb);
-                accumulate(t, sa, xa);
-                if (t + 1 < n) {
-                    if (t + 2 < n) fetch(t + 2, sa, xa);
-                    accumulate(t + 1, sb, xb);
-                }
+        Stage<DT> sa, sb;
+        fetch(0, sa);
+        for (int t = 0; t < n; t += 2) {
+            if (t + 1 < n) fetch(t + 1, sb);
+            accumulate(t, sa);
+            if (t + 1 < n) {
+                if (t + 2 < n) fetch(t + 2, sa);
+                accumulate(t + 1, sb);
             }
         }
     }
-    if (active) {
 #pragma unroll
-        for (int m = 0; m < kSlots; ++m)
-            if (cur_y[m] >= 0) commit(m);
-    }
+    for (int m = 0; m < kSlots; ++m)
+        if (cur[m] >= 0) commit(m);
 }
 
 template <int DT>
@@ -281,8 +279,7 @@ __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
     const int lane = threadIdx.x & (kWave - 1);
-    const int wpb = blockDim.x / kWave;
-    for (int u = uni(blockIdx.x * wpb + threadIdx.x / kWave); u < nunits; u += gridDim.x * wpb) {
+    for_each_unit(nunits, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
         const int S = uni(ut.S[m]), nch = nchunk_of(S);
@@ -290,18 +287,49 @@ __global__ __launch_bounds__(256) void k_grid(GArgs a) {
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;
         grid_chunk<DT>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
-    }
+    });
 }
 
-// Adjoint: one wavefront per local chunk; per run the S x S dot product with conj(K) is
-// accumulated per lane (Kahan), reduced across the wave, and broadcast to the run's records.
+// Sum over the 64 lanes with DPP moves (quad permutes, row mirrors, row broadcasts);
+// the total is left in lane 63 and returned to every lane through v_readlane.
+template <int CTRL, int ROW_MASK>
+__device__ inline float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+__device__ inline float wave_total(float v) {
+    v += dpp_f<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_f<0x140, 0xF>(v);  // row_mirror
+    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Adjoint: one wavefront per local chunk. The adjoint needs no cell ownership, so the S x S
+// footprint is enumerated flat: lane l takes cells c = l, l+64, ... (row c/S, column c%S).
+// The slice offset of a cell is c itself (coalesced table reads) and its grid offset from
+// the footprint's top-left cell is c + (c/S)(n - S). Per run each lane sums conj(K)*G over
+// its cells, the wave reduces, and every member record receives weight * (d, or conj d when
+// flipped). The (run, block of 8 cells per lane) steps are software-pipelined: the next
+// step's 16 loads are issued before the current one is summed. Each block's 8 products are
+// summed pairwise and added to the run's total with Kahan compensation.
+template <int DT>
+struct DStep {
+    typename KRaw<DT>::type k[8];
+    float2 g[8];
+};
+
 template <int DT>
 __device__ void degrid_chunk(const GArgs &a, int S, int rb, int re, int lane, const int64_t *koff) {
-    const int G = groups_of(S);
-    const int grp = lane / S, q = lane - grp * S;
-    const bool active = grp < G && grp < S;
+    constexpr int esz = (DT == WG_KF32) ? 8 : 4;
+    constexpr int kBlk = 8;
+    const int S2 = S * S;
+    const int nblk = uni((S2 + kBlk * kWave - 1) / (kBlk * kWave));
+    const float rS = 1.0f / (float)S;
+    const int gskip = a.n - S;  // grid cells between the end of one footprint row and the next
+    const __amdgpu_buffer_rsrc_t rk = table_rsrc(a.data, a.data_cap * esz);
     const int64_t seglen = (int64_t)a.nt * a.nc;
-    const float2 *grid = (const float2 *)a.grid;
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
         const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
@@ -310,50 +338,82 @@ __device__ void degrid_chunk(const GArgs &a, int S, int rb, int re, int lane, co
             my_start = a.start[base + lane];
             my_len = a.len[base + lane];
         }
-        for (int t = 0; t < n; ++t) {
+        // issue the loads of step (t, bi) into st
+        auto issue = [&](int t, int bi, DStep<DT> &st) {
+            const int ax = rl(b.ax, t), row0 = rl(b.row0, t);
+            const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.grid + 2 * ((int64_t)row0 * a.n + ax)), (short)0, S * a.n * 8, 0x00020000);
+            const int kbB = rl(b.kb, t) * esz;
+#pragma unroll
+            for (int u = 0; u < kBlk; ++u) {
+                const int c = (bi * kBlk + u) * kWave + lane;
+                if (c < S2) {
+                    const int i = (int)((float)c * rS + 0.5f * rS);
+                    st.k[u] = buf_load<DT>(rk, kbB + c * esz);
+                    const auto g2 = __builtin_amdgcn_raw_buffer_load_b64(rg, (c + i * gskip) * 8, 0, 0);
+                    st.g[u] = make_float2(__int_as_float(g2[0]), __int_as_float(g2[1]));
+                } else {
+                    st.k[u] = raw_zero<DT>();
+                    st.g[u] = make_float2(0.f, 0.f);
+                }
+            }
+        };
+        // steps s = t*nblk + bi, two per iteration with ping-pong buffers
+        float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
+        float e = 0.f;
+        double wm = 0.0;
+        auto consume = [&](int sidx, const DStep<DT> &st) {
+            const int t = sidx / nblk, bi = sidx - t * nblk;
             const int ok = rl(b.ok, t);
             const int r0 = rl(my_start, t), cnt = rl(my_len, t);
-            // member weights and flip signs, fetched before the dot product is formed
-            float e = 0.f;
-            double wm = 0.0;
             const int64_t r = (int64_t)r0 + lane;
-            const bool mine = lane < cnt && r < a.n_rec;
-            if (mine) {
+            const bool mine = ok && lane < cnt && r < a.n_rec;
+            if (bi == 0 && mine) {  // member weight and flip sign, fetched while the dot product forms
                 const int64_t bb = r / seglen, tt = r - (r / a.nt) * a.nt;
                 wm = a.uvw[(bb * a.nt + tt) * 3 + 2];
                 e = a.wt ? a.wt[r] : 1.0f;
             }
-            float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
-            if (ok && active) {
-                const int ax = rl(b.ax, t), row0 = rl(b.row0, t), kb = rl(b.kb, t);
-                int jj = q - rl(b.am, t);
-                jj += (jj < 0) ? S : 0;
-                int ii = grp - rl(b.r0m, t);
-                ii += (ii < 0) ? S : 0;
-                const float2 *gcol = grid + (int64_t)row0 * a.n + ax + jj;
-#pragma unroll 4
-                for (int p = grp; p < S; p += G) {
-                    const float2 kv = load_k<DT>(a.data, (int64_t)kb + ii * S + jj);
-                    const float2 gv = gcol[(int64_t)ii * a.n];
-                    const float pr = fmaf(kv.x, gv.x, kv.y * gv.y);
-                    const float pi = fmaf(kv.x, gv.y, -(kv.y * gv.x));
-                    kahan_add(sr, cr, pr);
-                    kahan_add(si, ci, pi);
-                    ii += G;
-                    ii -= (ii >= S) ? S : 0;
+            float br[kBlk], bim[kBlk];
+#pragma unroll
+            for (int u = 0; u < kBlk; ++u) {
+                const float2 k2 = to_float2<DT>(st.k[u]);
+                br[u] = fmaf(k2.x, st.g[u].x, k2.y * st.g[u].y);
+                bim[u] = fmaf(k2.x, st.g[u].y, -(k2.y * st.g[u].x));
+            }
+#pragma unroll
+            for (int w = kBlk / 2; w >= 1; w >>= 1)
+#pragma unroll
+                for (int u = 0; u < w; ++u) {
+                    br[u] += br[u + w];
+                    bim[u] += bim[u + w];
+                }
+            kahan_add(sr, cr, br[0]);
+            kahan_add(si, ci, bim[0]);
+            if (bi == nblk - 1) {  // run complete: reduce and hand d to its records
+                const float dr = wave_total(sr - cr), di = wave_total(si - ci);
+                sr = si = cr = ci = 0.f;
+                if (ok) {
+                    if (mine) a.vis_out[r] = make_float2(e * dr, e * ((wm >= 0.0) ? di : -di));
+                    for (int m = kWave + lane; m < cnt; m += kWave) {  // runs longer than a wave
+                        const int64_t rr = (int64_t)r0 + m;
+                        if (rr >= a.n_rec) break;
+                        const int64_t bb = rr / seglen, tt = rr - (rr / a.nt) * a.nt;
+                        const double w2 = a.uvw[(bb * a.nt + tt) * 3 + 2];
+                        const float e2 = a.wt ? a.wt[rr] : 1.0f;
+                        a.vis_out[rr] = make_float2(e2 * dr, e2 * ((w2 >= 0.0) ? di : -di));
+                    }
                 }
             }
-            const float dr = wave_sum(sr - cr), di = wave_sum(si - ci);
-            if (ok) {
-                if (mine) a.vis_out[r] = make_float2(e * dr, e * ((wm >= 0.0) ? di : -di));
-                for (int m = kWave + lane; m < cnt; m += kWave) {  // runs longer than a wave
-                    const int64_t rr = (int64_t)r0 + m;
-                    if (rr >= a.n_rec) break;
-                    const int64_t bb = rr / seglen, tt = rr - (rr / a.nt) * a.nt;
-                    const double w2 = a.uvw[(bb * a.nt + tt) * 3 + 2];
-                    const float e2 = a.wt ? a.wt[rr] : 1.0f;
-                    a.vis_out[rr] = make_float2(e2 * dr, e2 * ((w2 >= 0.0) ? di : -di));
-                }
+        };
+        const int nsteps = n * nblk;
+        DStep<DT> sa, sb;
+        issue(0, 0, sa);
+        for (int sidx = 0; sidx < nsteps; sidx += 2) {
+            if (sidx + 1 < nsteps) issue((sidx + 1) / nblk, (sidx + 1) % nblk, sb);
+            consume(sidx, sa);
+            if (sidx + 1 < nsteps) {
+                if (sidx + 2 < nsteps) issue((sidx + 2) / nblk, (sidx + 2) % nblk, sa);
+                consume(sidx + 1, sb);
             }
         }
     }
@@ -368,14 +428,13 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
     const int lane = threadIdx.x & (kWave - 1);
-    const int wpb = blockDim.x / kWave;
-    for (int u = uni(blockIdx.x * wpb + threadIdx.x / kWave); u < nunits; u += gridDim.x * wpb) {
+    for_each_unit(nunits, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
         const int S = uni(ut.S[m]);
         const int slot = uni(a.plan[kPlanOff + S]) + (u - uni(ut.first[m]));
         degrid_chunk<DT>(a, S, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
-    }
+    });
 }
 
 __global__ void k_zero(float2 *p, int64_t n) {
@@ -451,7 +510,7 @@ extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *r
     if ((st = check_table(g, kt)) != WG_OK) return st;
     if ((st = check_runs(runs)) != WG_OK) return st;
     if (!grid || !stats || !uvw || !vis_out || nb < 1 || nc < 1 || nt < 1) return WG_EINVAL;
-    if (kt->data_cap >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
+    if (kt->data_cap >= ((int64_t)1 << 28)) return WG_EUNSUPPORTED;  // byte offsets stay 32-bit
     const int64_t n_rec = nb * (int64_t)nc * nt;
     if (n_rec > runs->capacity) return WG_ECAPACITY;
     GArgs a = make_args(g, kt, runs);

@@ -32,58 +32,89 @@ struct TaperCoef {
     double c[kTaperTerms];  // psi_0(x) = sum_i c[i] * P_{2i}(x)
 };
 
-// Smallest-eigenvalue eigenvector of the symmetric matrix of -((1-x^2)psi')' + c^2 x^2 psi
-// in the basis sqrt(k+1/2) P_k, k even (cyclic Jacobi rotations on a small dense matrix).
+// Smallest-eigenvalue eigenvector of the symmetric tridiagonal matrix of the operator
+// -((1-x^2)psi')' + c^2 x^2 psi in the basis sqrt(k+1/2) P_k, k even: the eigenvalue by
+// bisection on the Sturm count, the eigenvector by inverse iteration (banded Gaussian
+// elimination with partial pivoting).
 void prolate_coefficients(double c, TaperCoef *tc) {
     const int K = kTaperTerms;
-    std::vector<double> A(K * K, 0.0), V(K * K, 0.0);
+    double d[kTaperTerms], e[kTaperTerms];
     auto a = [](double k) { return (k + 1.0) / sqrt((2.0 * k + 1.0) * (2.0 * k + 3.0)); };
     for (int i = 0; i < K; ++i) {
-        double k = 2.0 * i;
-        double x2 = a(k) * a(k) + (i > 0 ? a(k - 1.0) * a(k - 1.0) : 0.0);
-        A[i * K + i] = k * (k + 1.0) + c * c * x2;
-        if (i + 1 < K) A[i * K + i + 1] = A[(i + 1) * K + i] = c * c * a(k) * a(k + 1.0);
-        V[i * K + i] = 1.0;
+        const double k = 2.0 * i;
+        d[i] = k * (k + 1.0) + c * c * (a(k) * a(k) + (i > 0 ? a(k - 1.0) * a(k - 1.0) : 0.0));
+        e[i] = (i + 1 < K) ? c * c * a(k) * a(k + 1.0) : 0.0;
     }
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int p = 0; p < K; ++p)
-            for (int q = 0; q < K; ++q) {
-                tot += A[p * K + q] * A[p * K + q];
-                if (p != q) off += A[p * K + q] * A[p * K + q];
-            }
-        if (off <= 1e-60 * tot) break;
-        for (int p = 0; p < K - 1; ++p)
-            for (int q = p + 1; q < K; ++q) {
-                double apq = A[p * K + q];
-                if (apq == 0.0) continue;
-                double theta = (A[q * K + q] - A[p * K + p]) / (2.0 * apq);
-                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
-                for (int r = 0; r < K; ++r) {  // columns p, q
-                    double arp = A[r * K + p], arq = A[r * K + q];
-                    A[r * K + p] = cs * arp - sn * arq;
-                    A[r * K + q] = sn * arp + cs * arq;
-                }
-                for (int r = 0; r < K; ++r) {  // rows p, q
-                    double apr = A[p * K + r], aqr = A[q * K + r];
-                    A[p * K + r] = cs * apr - sn * aqr;
-                    A[q * K + r] = sn * apr + cs * aqr;
-                }
-                for (int r = 0; r < K; ++r) {
-                    double vrp = V[r * K + p], vrq = V[r * K + q];
-                    V[r * K + p] = cs * vrp - sn * vrq;
-                    V[r * K + q] = sn * vrp + cs * vrq;
-                }
-            }
+    double lo = d[0], hi = d[0];
+    for (int i = 0; i < K; ++i) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < K ? fabs(e[i]) : 0.0);
+        lo = fmin(lo, d[i] - r);
+        hi = fmax(hi, d[i] + r);
     }
-    int imin = 0;
-    for (int i = 1; i < K; ++i)
-        if (A[i * K + i] < A[imin * K + imin]) imin = i;
+    auto count_below = [&](double x) {
+        int cnt = 0;
+        double q = 1.0;
+        for (int i = 0; i < K; ++i) {
+            q = d[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / q : 0.0);
+            if (q == 0.0) q = -1e-300;
+            if (q < 0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(1.0, fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_below(mid) >= 1)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    const double lam = 0.5 * (lo + hi);
+    double v[kTaperTerms];
+    for (int i = 0; i < K; ++i) v[i] = 1.0;
+    for (int iter = 0; iter < 4; ++iter) {
+        double A[kTaperTerms][3], b[kTaperTerms], sub[kTaperTerms], x[kTaperTerms];
+        for (int i = 0; i < K; ++i) {
+            A[i][0] = d[i] - lam;
+            A[i][1] = (i + 1 < K) ? e[i] : 0.0;
+            A[i][2] = 0.0;
+            sub[i] = (i > 0) ? e[i - 1] : 0.0;
+            b[i] = v[i];
+        }
+        for (int i = 0; i < K - 1; ++i) {
+            if (fabs(sub[i + 1]) > fabs(A[i][0])) {  // swap rows i and i+1, then eliminate
+                const double r0 = sub[i + 1], r1 = A[i + 1][0], r2 = A[i + 1][1], rb = b[i + 1];
+                const double s0 = A[i][0], s1 = A[i][1], s2 = A[i][2], sb = b[i];
+                A[i][0] = r0;
+                A[i][1] = r1;
+                A[i][2] = r2;
+                b[i] = rb;
+                const double f = s0 / r0;
+                A[i + 1][0] = s1 - f * r1;
+                A[i + 1][1] = s2 - f * r2;
+                b[i + 1] = sb - f * rb;
+            } else {
+                const double f = sub[i + 1] / A[i][0];
+                A[i + 1][0] -= f * A[i][1];
+                A[i + 1][1] -= f * A[i][2];
+                b[i + 1] -= f * b[i];
+            }
+        }
+        for (int i = K - 1; i >= 0; --i) {
+            double sacc = b[i];
+            if (i + 1 < K) sacc -= A[i][1] * x[i + 1];
+            if (i + 2 < K) sacc -= A[i][2] * x[i + 2];
+            const double piv = A[i][0] == 0.0 ? 1e-300 : A[i][0];
+            x[i] = sacc / piv;
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < K; ++i) nrm += x[i] * x[i];
+        nrm = sqrt(nrm);
+        for (int i = 0; i < K; ++i) v[i] = x[i] / nrm;
+    }
     // psi(0) = sum c_i P_{2i}(0), P_{2i}(0) = (-1)^i (2i-1)!!/(2i)!!
     double p0 = 1.0, psi0 = 0.0;
     for (int i = 0; i < K; ++i) {
-        tc->c[i] = V[i * K + imin] * sqrt(2.0 * i + 0.5);
+        tc->c[i] = v[i] * sqrt(2.0 * i + 0.5);
         psi0 += tc->c[i] * p0;
         p0 *= -(2.0 * i + 1.0) / (2.0 * i + 2.0);
     }
@@ -188,8 +219,17 @@ __global__ void k_rows(BuildArgs a, TaperCoef tc) {
     }
 }
 
-__global__ void k_c00_and_reset(BuildArgs a) {
+__global__ void k_c00_and_reset(BuildArgs a, double *wbound) {
     __shared__ double red[256];
+    // lower |w| edge of every plane: nearest plane in sqrt(w)
+    for (int j = threadIdx.x; j < a.n_w; j += blockDim.x) {
+        double wb = 0.0;
+        if (j > 0) {
+            const double q = ((double)j - 0.5) / (double)(a.n_w - 1);
+            wb = a.w_max * (q * q);
+        }
+        wbound[j] = wb;
+    }
     double acc = 0.0;
     const double2 *col = a.A + (size_t)(a.L / 2) * a.M;  // plane 0, zero frequency in u
     for (int q = threadIdx.x; q < a.M; q += blockDim.x) acc += col[q].x;
@@ -239,6 +279,24 @@ __global__ void k_cols(BuildArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0 && red[0] > 0) atomicMax(&a.kmax[k], red[0]);
+}
+
+// Supports from the natural support (1e-3 threshold) and the configured law, and plane
+// offsets in complex elements.
+__global__ void k_supports(BuildArgs a, int s_lo, int s_hi, int32_t *support, int64_t *offset) {
+    if (threadIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int k = 0; k < a.n_w; ++k) {
+        const int over = a.kmax[k] - a.beta / 2;
+        const int r = over <= 0 ? 0 : (over + a.beta - 1) / a.beta;
+        const int snat = 2 * r + 1;
+        const int law = a.n_w == 1 ? s_lo : s_lo + 2 * (((s_hi - s_lo) * k + (a.n_w - 1)) / (2 * (a.n_w - 1)));
+        const int S = min(s_hi, max(snat, law));
+        support[k] = S;
+        offset[k] = acc;
+        acc += (int64_t)a.beta * a.beta * S * S;
+    }
+    offset[a.n_w] = acc;
 }
 
 // Round-to-nearest-even of an FP64 value to a format with `sig` significant bits and
@@ -333,10 +391,6 @@ WsLayout ws_layout(const wg_geom *g) {
     return w;
 }
 
-int support_law(int k, int n_w, int s_lo, int s_hi) {
-    if (n_w == 1) return s_lo;
-    return s_lo + 2 * (((s_hi - s_lo) * k + (n_w - 1)) / (2 * (n_w - 1)));
-}
 
 }  // namespace
 }  // namespace wg
@@ -365,13 +419,6 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
     TaperCoef tc;
     prolate_coefficients(kTaperC, &tc);
 
-    // plane edges in |w| (nearest plane in sqrt(w))
-    std::vector<double> wb(g->n_w, 0.0);
-    for (int j = 1; j < g->n_w; ++j) {
-        double q = ((double)j - 0.5) / (double)(g->n_w - 1);
-        wb[j] = g->w_max * (q * q);
-    }
-
     char *base = (char *)ws;
     BuildArgs a;
     a.M = g->m_img;
@@ -394,38 +441,33 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
     const size_t lds = sizeof(double2) * a.L;
     hipLaunchKernelGGL(k_twiddle, dim3((a.L / 2 + 255) / 256), dim3(256), 0, s, (double2 *)a.tw, a.L);
     hipLaunchKernelGGL(k_rows, dim3(a.M, a.n_w), dim3(256), lds, s, a, tc);
-    hipLaunchKernelGGL(k_c00_and_reset, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_c00_and_reset, dim3(1), dim3(256), 0, s, a, kt->wbound);
     hipLaunchKernelGGL(k_cols, dim3(a.L, a.n_w), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_supports, dim3(1), dim3(64), 0, s, a, g->s_lo, g->s_hi, kt->support, kt->offset);
     if (hipGetLastError() != hipSuccess) return WG_EHIP;
 
-    std::vector<int> kmax(g->n_w);
-    WG_HIP_CHECK(hipMemcpyAsync(kmax.data(), a.kmax, sizeof(int) * g->n_w, hipMemcpyDeviceToHost, s));
-    WG_HIP_CHECK(hipStreamSynchronize(s));
-
-    std::vector<int32_t> sup(g->n_w);
-    std::vector<int64_t> off(g->n_w + 1, 0);
-    int smax = 1;
-    for (int k = 0; k < g->n_w; ++k) {
-        const int over = kmax[k] - g->beta / 2;
-        const int r = over <= 0 ? 0 : (over + g->beta - 1) / g->beta;
-        const int snat = 2 * r + 1;
-        int S = snat > support_law(k, g->n_w, g->s_lo, g->s_hi) ? snat : support_law(k, g->n_w, g->s_lo, g->s_hi);
-        if (S > g->s_hi) S = g->s_hi;
-        sup[k] = S;
-        smax = S > smax ? S : smax;
-        off[k + 1] = off[k] + (int64_t)g->beta * g->beta * S * S;
+    // With room for every plane at s_hi and no host copies requested, nothing waits: the
+    // matrices are cut on the device right away and s_max reports the upper bound s_hi.
+    const int64_t cap_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * g->s_hi;
+    const bool sync = support_out || offset_out || kt->data_cap < cap_max;
+    if (sync) {
+        std::vector<int32_t> sup(g->n_w);
+        std::vector<int64_t> off(g->n_w + 1);
+        WG_HIP_CHECK(hipMemcpyAsync(sup.data(), kt->support, sizeof(int32_t) * g->n_w, hipMemcpyDeviceToHost, s));
+        WG_HIP_CHECK(hipMemcpyAsync(off.data(), kt->offset, sizeof(int64_t) * (g->n_w + 1), hipMemcpyDeviceToHost, s));
+        WG_HIP_CHECK(hipStreamSynchronize(s));
+        if (off[g->n_w] > kt->data_cap) return WG_ECAPACITY;
+        int smax = 1;
+        for (int k = 0; k < g->n_w; ++k) smax = sup[k] > smax ? sup[k] : smax;
+        kt->s_max = smax;
+        if (support_out) memcpy(support_out, sup.data(), sizeof(int32_t) * g->n_w);
+        if (offset_out) memcpy(offset_out, off.data(), sizeof(int64_t) * (g->n_w + 1));
+    } else {
+        kt->s_max = g->s_hi;
     }
-    if (off[g->n_w] > kt->data_cap) return WG_ECAPACITY;
-    kt->s_max = smax;
-
-    WG_HIP_CHECK(hipMemcpyAsync(kt->support, sup.data(), sizeof(int32_t) * g->n_w, hipMemcpyHostToDevice, s));
-    WG_HIP_CHECK(hipMemcpyAsync(kt->offset, off.data(), sizeof(int64_t) * (g->n_w + 1), hipMemcpyHostToDevice, s));
-    WG_HIP_CHECK(hipMemcpyAsync(kt->wbound, wb.data(), sizeof(double) * g->n_w, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_slices, dim3(g->beta * g->beta, g->n_w), dim3(256), 0, s, a,
                        (const int32_t *)kt->support, (const int64_t *)kt->offset, kt->data, kt->zeta);
     if (hipGetLastError() != hipSuccess) return WG_EHIP;
-    WG_HIP_CHECK(hipStreamSynchronize(s));
-    if (support_out) memcpy(support_out, sup.data(), sizeof(int32_t) * g->n_w);
-    if (offset_out) memcpy(offset_out, off.data(), sizeof(int64_t) * (g->n_w + 1));
+    if (sync) WG_HIP_CHECK(hipStreamSynchronize(s));
     return WG_OK;
 }

@@ -34,14 +34,10 @@ inline int64_t plan_segcnt_at(int64_t capacity) { return kPlanHdr + 2 * capacity
 inline int64_t plan_tiles_at(int64_t capacity, int64_t n_seg) { return plan_segcnt_at(capacity) + n_seg + 1; }
 inline int64_t n_scan_tiles(int64_t n_seg) { return (n_seg + kScanTile - 1) / kScanTile; }
 
-// Gridder decomposition of a support-S item into waves ("chunks"): G = 64/S lane groups
-// per wave, each lane owns one column class q = lane % S and a set of row classes; the S
-// row classes are spread over nchunk(S) waves x G groups with at most kSlots per lane.
-__host__ __device__ inline int groups_of(int S) { return S >= kWave ? 1 : kWave / S; }
-__host__ __device__ inline int nchunk_of(int S) {
-    int G = groups_of(S);
-    return (S + G * kSlots - 1) / (G * kSlots);
-}
+// Gridder decomposition of a support-S local chunk into waves: the S*S cell classes
+// (y mod S, x mod S) are numbered c = p*S + q and spread evenly over nchunk_of(S) waves,
+// at most kSlots classes per lane.
+__host__ __device__ inline int nchunk_of(int S) { return (S * S + kWave * kSlots - 1) / (kWave * kSlots); }
 
 // Status helpers
 #define WG_HIP_CHECK(expr)                                   \

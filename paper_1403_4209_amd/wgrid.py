@@ -115,7 +115,14 @@ def wg_ktable_sizes(geom: WgGeom) -> tuple[int, int]:
     return int(n.value), int(ws.value)
 
 
-def wg_ktable_build(geom: WgGeom, kt: WgKtable, ws: torch.Tensor, stream=None):
+def wg_ktable_build(geom: WgGeom, kt: WgKtable, ws: torch.Tensor, stream=None, host_copies=True):
+    """Build the table into kt's device arrays. With host_copies the call waits and returns
+    (supports, offsets); without, it only enqueues work (kt.data_cap must hold every plane
+    at s_hi) and returns None."""
+    if not host_copies:
+        _check(lib().wg_ktable_build(ctypes.byref(geom), ctypes.byref(kt), _p(ws), ws.numel() * ws.element_size(),
+                                     None, None, _stream(stream)), "wg_ktable_build")
+        return None
     sup = (ctypes.c_int32 * geom.n_w)()
     off = (ctypes.c_int64 * (geom.n_w + 1))()
     _check(lib().wg_ktable_build(ctypes.byref(geom), ctypes.byref(kt), _p(ws), ws.numel() * ws.element_size(),

@@ -128,6 +128,26 @@ def test_table_parity(case, dtype):
     assert np.array_equal(wb[1:], ref["wbound"][1:])
 
 
+def test_table_async_build_matches_oracle():
+    """The build without host copies (supports computed on the device, nothing waits) gives
+    the oracle's supports and samples too."""
+    geom = cfg4_small()[0]
+    g = wg.geom_from_dict(geom)
+    tb = wg.KernelTable(g, "f32", device=DEV)
+    _, ws_bytes = wg.wg_ktable_sizes(g)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=DEV)
+    tb.data_d.zero_()
+    tb.support_d.zero_()
+    wg.wg_ktable_build(g, tb.kt, ws, host_copies=False)
+    torch.cuda.synchronize()
+    assert tb.kt.s_max == geom["s_hi"]
+    ref = otable(geom, "f32")
+    assert np.array_equal(tb.support_d.cpu().numpy(), ref["support"])
+    assert np.array_equal(tb.offset_d.cpu().numpy(), ref["offset"])
+    got = tb.data_complex().cpu().numpy().astype(np.complex128)
+    assert np.all(np.abs(got - ref["data"]) <= 2.0 ** -23 * np.abs(ref["data"]) + 1e-13)
+
+
 # ------------------------------------------------------------------------ compression
 @pytest.mark.parametrize("compress", [True, False])
 @pytest.mark.parametrize("case", ["cfg1", "cfg4"])
