@@ -67,12 +67,20 @@ def gpu_step(wg, geom, kt, ws, gridder, vis, grid, vis_out, ev):
     return ev
 
 
+def grid_source_hash() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1403_4209_amd", "csrc", "grid.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def read_counters():
-    """HBM bytes per gridder launch from the committed rocprofv3 counter summary, if it
-    matches the current kernel (the file names the library build it was taken from)."""
+    """HBM bytes per gridder launch from the committed rocprofv3 counter summary, or None
+    when the gridder source has changed since the counters were taken."""
     try:
         with open(PROFILE_COUNTERS) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line)
+        if kv["grid_hip_sha256_16"].strip() != grid_source_hash():
+            return None
         return float(kv["traffic_bytes_per_launch"].strip())
     except Exception:
         return None

@@ -188,18 +188,17 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
     const float rS = 1.0f / (float)S;
 
-    int cp[kSlots], cq[kSlots];  // the lane's classes (row class, column class); -1 = none
+    // The lane's classes (row class, column class). Every slot but the last is full for
+    // every lane; the last one may be partial.
+    int cp[kSlots], cq[kSlots];
 #pragma unroll
     for (int m = 0; m < kSlots; ++m) {
-        const int c = c0 + m * kWave + lane;
-        cp[m] = -1;
-        cq[m] = 0;
-        if (m < nslots && c < c1) {
-            const int pp = (int)((float)c * rS + 0.5f * rS);
-            cp[m] = pp;
-            cq[m] = c - pp * S;
-        }
+        const int c = min(c0 + m * kWave + lane, c1 - 1);
+        const int pp = (int)((float)c * rS + 0.5f * rS);
+        cp[m] = pp;
+        cq[m] = c - pp * S;
     }
+    const bool last_ok = c0 + (nslots - 1) * kWave + lane < c1;
     float acc_r[kSlots], acc_i[kSlots], cmp_r[kSlots], cmp_i[kSlots];
     int cur[kSlots];  // owned cell (y*n + x), -1 = none
 #pragma unroll
@@ -213,6 +212,8 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
         unsafeAtomicAdd(cell + 1, acc_i[m] - cmp_i[m]);
         acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
     };
+    // (d mod S) for d in (-S, S): unsigned min of d and d + S
+    auto wrap = [&](int d) { return (int)min((unsigned)d, (unsigned)(d + S)); };
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
@@ -226,12 +227,9 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
 #pragma unroll
             for (int m = 0; m < kSlots; ++m) {
                 if (m < nslots) {
-                    int ii = cp[m] - r0m;
-                    ii += (ii < 0) ? S : 0;
-                    int jj = cq[m] - am;
-                    jj += (jj < 0) ? S : 0;
-                    st.yc[m] = cell0 + ii * a.n + jj;
-                    st.k[m] = cp[m] >= 0 ? buf_load<DT>(rs, kbB + (ii * S + jj) * esz) : raw_zero<DT>();
+                    const int ii = wrap(cp[m] - r0m), jj = wrap(cq[m] - am);
+                    st.yc[m] = (int)__umul24(ii, a.n) + cell0 + jj;
+                    st.k[m] = buf_load<DT>(rs, kbB + (int)(__umul24(ii, S) + jj) * esz);
                 }
             }
         };
@@ -240,16 +238,21 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
             const float gr = rlf(b.gr, t), gi = rlf(b.gi, t);
 #pragma unroll
             for (int m = 0; m < kSlots; ++m) {
-                if (m < nslots && cp[m] >= 0) {
+                if (m < nslots && (m < nslots - 1 || last_ok)) {
                     if (st.yc[m] != cur[m]) {
                         if (cur[m] >= 0) commit(m);
                         cur[m] = st.yc[m];
                     }
+                    // Kahan step with the product fused into the compensation:
+                    // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t
                     const float2 kv = to_float2<DT>(st.k[m]);
-                    const float pr = fmaf(gr, kv.x, -(gi * kv.y));
-                    const float pi = fmaf(gr, kv.y, gi * kv.x);
-                    kahan_add(acc_r[m], cmp_r[m], pr);
-                    kahan_add(acc_i[m], cmp_i[m], pi);
+                    const float yr = fmaf(gr, kv.x, -fmaf(gi, kv.y, cmp_r[m]));
+                    const float yi = fmaf(gr, kv.y, fmaf(gi, kv.x, -cmp_i[m]));
+                    const float tr = acc_r[m] + yr, ti = acc_i[m] + yi;
+                    cmp_r[m] = (tr - acc_r[m]) - yr;
+                    cmp_i[m] = (ti - acc_i[m]) - yi;
+                    acc_r[m] = tr;
+                    acc_i[m] = ti;
                 }
             }
         };
