@@ -131,8 +131,9 @@ typedef struct wg_ktable {
  * w-plane `plane` and oversample offsets (ou, ov); gamma is the sum over its records of
  * weight * (vis, conjugated when w < 0), as float32 (re, im). Runs are in record order.
  * `plan` is a device work list the gridder reads (local chunks of equal support, grouped by
- * support); size it with wg_plan_elems. Every array has `capacity` entries (gamma 2x);
- * capacity must be >= nb*nc*nt, so the run list can never overflow.
+ * support); size it with wg_plan_elems. `work` is scratch that wg_degrid overwrites (one
+ * complex float per run). Every array has `capacity` entries (gamma and work 2x); capacity
+ * must be >= nb*nc*nt, so the run list can never overflow.
  */
 typedef struct wg_runs {
     int64_t capacity;
@@ -146,6 +147,7 @@ typedef struct wg_runs {
     float *gamma;
     int32_t *plan;
     int64_t plan_elems;
+    float *work;
 } wg_runs;
 
 /*
@@ -229,10 +231,12 @@ int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg
 
 /*
  * Adjoint of wg_compress + wg_grid with respect to the visibilities: per run
- * d = sum_ij conj(K[i][j]) * grid[row0+i][a+j] (FP32, Kahan per lane); record r of the run
- * gets weight_r * (d, or conj(d) when w_r(metres) < 0); records in no run get 0. OVERWRITES
- * vis_out (complex64 [nb][nc][nt]). uvw, weight and the sizes must be those given to
- * wg_compress. Errors: WG_EINVAL, WG_EHIP.
+ * d = sum_ij conj(K[i][j]) * grid[row0+i][a+j] (FP32, pairwise/tree summation; partial sums
+ * of the waves sharing a run are combined with FP32 atomic adds into runs->work, so the last
+ * bits depend on scheduling); record r of the run gets weight_r * (d, or conj(d) when
+ * w_r(metres) < 0); records in no run get 0. OVERWRITES vis_out (complex64 [nb][nc][nt]) and
+ * runs->work. uvw, weight and the sizes must be those given to wg_compress.
+ * Errors: WG_EINVAL (runs->work NULL among others), WG_ECAPACITY, WG_EUNSUPPORTED, WG_EHIP.
  */
 int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg_stats *stats,
               const float *grid, const double *uvw, const float *weight, int64_t nb, int32_t nc,

@@ -26,6 +26,8 @@ struct GArgs {
     const void *data;
     float *grid;        // grid (wg_grid, accumulate) or input grid (wg_degrid)
     float2 *vis_out;    // wg_degrid output
+    float2 *work;       // wg_degrid per-run dot products
+    const wg_stats *stats;
     const double *uvw;
     const float *wt;
 };
@@ -178,13 +180,11 @@ __device__ inline void for_each_unit(int nunits, F &&body) {
     for (int u = uni(blockIdx.x * wpb + (int)(threadIdx.x / kWave)); u < nunits; u += stride) body(u);
 }
 
-template <int DT>
-__device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
+template <int DT, int NS>
+__device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
+                              const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
-    const int S2 = S * S, nch = nchunk_of(S);
-    const int cpc = (S2 + nch - 1) / nch;  // classes per wave
-    const int c0 = chunk * cpc, c1 = min(S2, c0 + cpc);
-    const int nslots = uni((c1 - c0 + kWave - 1) / kWave);
+    constexpr int nslots = NS;
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
     const float rS = 1.0f / (float)S;
 
@@ -192,7 +192,7 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
     // every lane; the last one may be partial.
     int cp[kSlots], cq[kSlots];
 #pragma unroll
-    for (int m = 0; m < kSlots; ++m) {
+    for (int m = 0; m < NS; ++m) {
         const int c = min(c0 + m * kWave + lane, c1 - 1);
         const int pp = (int)((float)c * rS + 0.5f * rS);
         cp[m] = pp;
@@ -202,7 +202,7 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
     float acc_r[kSlots], acc_i[kSlots], cmp_r[kSlots], cmp_i[kSlots];
     int cur[kSlots];  // owned cell (y*n + x), -1 = none
 #pragma unroll
-    for (int m = 0; m < kSlots; ++m) {
+    for (int m = 0; m < NS; ++m) {
         acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
         cur[m] = -1;
     }
@@ -225,7 +225,7 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
             const int cell0 = rl(b.row0, t) * a.n + rl(b.ax, t);
             const int kbB = rl(b.kb, t) * esz;
 #pragma unroll
-            for (int m = 0; m < kSlots; ++m) {
+            for (int m = 0; m < NS; ++m) {
                 if (m < nslots) {
                     const int ii = wrap(cp[m] - r0m), jj = wrap(cq[m] - am);
                     st.yc[m] = (int)__umul24(ii, a.n) + cell0 + jj;
@@ -237,7 +237,7 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
             if (!rl(b.ok, t)) return;
             const float gr = rlf(b.gr, t), gi = rlf(b.gi, t);
 #pragma unroll
-            for (int m = 0; m < kSlots; ++m) {
+            for (int m = 0; m < NS; ++m) {
                 if (m < nslots && (m < nslots - 1 || last_ok)) {
                     if (st.yc[m] != cur[m]) {
                         if (cur[m] >= 0) commit(m);
@@ -269,8 +269,34 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
         }
     }
 #pragma unroll
-    for (int m = 0; m < kSlots; ++m)
+    for (int m = 0; m < NS; ++m)
         if (cur[m] >= 0) commit(m);
+}
+
+// Classes [c0, c1) of a support-S chunk, split evenly over the chunk's waves; the slot
+// count per lane is a template parameter so the unrolled slot loops carry no guards.
+__device__ inline void chunk_classes(int S, int chunk, int &c0, int &c1, int &ns) {
+    const int S2 = S * S, nch = nchunk_of(S);
+    const int cpc = (S2 + nch - 1) / nch;
+    c0 = chunk * cpc;
+    c1 = min(S2, c0 + cpc);
+    ns = uni((c1 - c0 + kWave - 1) / kWave);
+}
+
+template <int DT>
+__device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
+    int c0, c1, ns;
+    chunk_classes(S, chunk, c0, c1, ns);
+    switch (ns) {
+    case 1: grid_chunk_ns<DT, 1>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 2: grid_chunk_ns<DT, 2>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 3: grid_chunk_ns<DT, 3>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 4: grid_chunk_ns<DT, 4>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 5: grid_chunk_ns<DT, 5>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 6: grid_chunk_ns<DT, 6>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 7: grid_chunk_ns<DT, 7>(a, S, c0, c1, rb, re, lane, koff); break;
+    default: grid_chunk_ns<DT, 8>(a, S, c0, c1, rb, re, lane, koff); break;
+    }
 }
 
 template <int DT>
@@ -309,116 +335,118 @@ __device__ inline float wave_total(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// Adjoint: one wavefront per local chunk. The adjoint needs no cell ownership, so the S x S
-// footprint is enumerated flat: lane l takes cells c = l, l+64, ... (row c/S, column c%S).
-// The slice offset of a cell is c itself (coalesced table reads) and its grid offset from
-// the footprint's top-left cell is c + (c/S)(n - S). Per run each lane sums conj(K)*G over
-// its cells, the wave reduces, and every member record receives weight * (d, or conj d when
-// flipped). The (run, block of 8 cells per lane) steps are software-pipelined: the next
-// step's 16 loads are issued before the current one is summed. Each block's 8 products are
-// summed pairwise and added to the run's total with Kahan compensation.
+// Adjoint, with the gridder's decomposition: a wave owns the same cell classes of a local
+// chunk, keeps the grid value of each owned cell in a register and reloads it only when the
+// footprint moves the cell, and forms per run the partial dot product of conj(K) with those
+// values (a short FMA chain per lane, then a DPP tree over the wave). The waves sharing a
+// chunk add their partial sums into work[run]; k_degrid_finish hands d to the run's records.
 template <int DT>
-struct DStep {
-    typename KRaw<DT>::type k[8];
-    float2 g[8];
+struct DStage {
+    typename KRaw<DT>::type k[kSlots];
+    int yc[kSlots];
+    float2 g[kSlots];
+    unsigned ld;  // bit m: g[m] holds a newly loaded cell value
 };
 
-template <int DT>
-__device__ void degrid_chunk(const GArgs &a, int S, int rb, int re, int lane, const int64_t *koff) {
+template <int DT, int NS>
+__device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
+                                const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
-    constexpr int kBlk = 8;
-    const int S2 = S * S;
-    const int nblk = uni((S2 + kBlk * kWave - 1) / (kBlk * kWave));
+    constexpr int nslots = NS;
+    const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
     const float rS = 1.0f / (float)S;
-    const int gskip = a.n - S;  // grid cells between the end of one footprint row and the next
-    const __amdgpu_buffer_rsrc_t rk = table_rsrc(a.data, a.data_cap * esz);
-    const int64_t seglen = (int64_t)a.nt * a.nc;
+    const float2 *grid = (const float2 *)a.grid;
+    int cp[kSlots], cq[kSlots];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        const int c = min(c0 + m * kWave + lane, c1 - 1);
+        const int pp = (int)((float)c * rS + 0.5f * rS);
+        cp[m] = pp;
+        cq[m] = c - pp * S;
+    }
+    const bool last_ok = c0 + (nslots - 1) * kWave + lane < c1;
+    auto wrap = [&](int d) { return (int)min((unsigned)d, (unsigned)(d + S)); };
+    int pyc[kSlots];      // cells of the most recently fetched run
+    float2 gv[kSlots];    // grid values of the owned cells
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        pyc[m] = -1;
+        gv[m] = make_float2(0.f, 0.f);
+    }
+
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
         const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
-        int my_start = 0, my_len = 0;
-        if (lane < n) {
-            my_start = a.start[base + lane];
-            my_len = a.len[base + lane];
-        }
-        // issue the loads of step (t, bi) into st
-        auto issue = [&](int t, int bi, DStep<DT> &st) {
-            const int ax = rl(b.ax, t), row0 = rl(b.row0, t);
-            const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(a.grid + 2 * ((int64_t)row0 * a.n + ax)), (short)0, S * a.n * 8, 0x00020000);
+
+        auto fetch = [&](int t, DStage<DT> &st) {
+            const int am = rl(b.am, t), r0m = rl(b.r0m, t);
+            const int cell0 = rl(b.row0, t) * a.n + rl(b.ax, t);
             const int kbB = rl(b.kb, t) * esz;
+            st.ld = 0;
 #pragma unroll
-            for (int u = 0; u < kBlk; ++u) {
-                const int c = (bi * kBlk + u) * kWave + lane;
-                if (c < S2) {
-                    const int i = (int)((float)c * rS + 0.5f * rS);
-                    st.k[u] = buf_load<DT>(rk, kbB + c * esz);
-                    const auto g2 = __builtin_amdgcn_raw_buffer_load_b64(rg, (c + i * gskip) * 8, 0, 0);
-                    st.g[u] = make_float2(__int_as_float(g2[0]), __int_as_float(g2[1]));
-                } else {
-                    st.k[u] = raw_zero<DT>();
-                    st.g[u] = make_float2(0.f, 0.f);
+            for (int m = 0; m < NS; ++m) {
+                if (m < nslots) {
+                    const int ii = wrap(cp[m] - r0m), jj = wrap(cq[m] - am);
+                    const int yc = (int)__umul24(ii, a.n) + cell0 + jj;
+                    st.yc[m] = yc;
+                    st.k[m] = buf_load<DT>(rs, kbB + (int)(__umul24(ii, S) + jj) * esz);
+                    if (yc != pyc[m]) {
+                        st.ld |= 1u << m;
+                        st.g[m] = grid[yc];
+                    }
+                    pyc[m] = yc;
                 }
             }
         };
-        // steps s = t*nblk + bi, two per iteration with ping-pong buffers
-        float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
-        float e = 0.f;
-        double wm = 0.0;
-        auto consume = [&](int sidx, const DStep<DT> &st) {
-            const int t = sidx / nblk, bi = sidx - t * nblk;
-            const int ok = rl(b.ok, t);
-            const int r0 = rl(my_start, t), cnt = rl(my_len, t);
-            const int64_t r = (int64_t)r0 + lane;
-            const bool mine = ok && lane < cnt && r < a.n_rec;
-            if (bi == 0 && mine) {  // member weight and flip sign, fetched while the dot product forms
-                const int64_t bb = r / seglen, tt = r - (r / a.nt) * a.nt;
-                wm = a.uvw[(bb * a.nt + tt) * 3 + 2];
-                e = a.wt ? a.wt[r] : 1.0f;
-            }
-            float br[kBlk], bim[kBlk];
+        auto consume = [&](int t, const DStage<DT> &st) {
+            float pr = 0.f, pim = 0.f;
 #pragma unroll
-            for (int u = 0; u < kBlk; ++u) {
-                const float2 k2 = to_float2<DT>(st.k[u]);
-                br[u] = fmaf(k2.x, st.g[u].x, k2.y * st.g[u].y);
-                bim[u] = fmaf(k2.x, st.g[u].y, -(k2.y * st.g[u].x));
-            }
-#pragma unroll
-            for (int w = kBlk / 2; w >= 1; w >>= 1)
-#pragma unroll
-                for (int u = 0; u < w; ++u) {
-                    br[u] += br[u + w];
-                    bim[u] += bim[u + w];
-                }
-            kahan_add(sr, cr, br[0]);
-            kahan_add(si, ci, bim[0]);
-            if (bi == nblk - 1) {  // run complete: reduce and hand d to its records
-                const float dr = wave_total(sr - cr), di = wave_total(si - ci);
-                sr = si = cr = ci = 0.f;
-                if (ok) {
-                    if (mine) a.vis_out[r] = make_float2(e * dr, e * ((wm >= 0.0) ? di : -di));
-                    for (int m = kWave + lane; m < cnt; m += kWave) {  // runs longer than a wave
-                        const int64_t rr = (int64_t)r0 + m;
-                        if (rr >= a.n_rec) break;
-                        const int64_t bb = rr / seglen, tt = rr - (rr / a.nt) * a.nt;
-                        const double w2 = a.uvw[(bb * a.nt + tt) * 3 + 2];
-                        const float e2 = a.wt ? a.wt[rr] : 1.0f;
-                        a.vis_out[rr] = make_float2(e2 * dr, e2 * ((w2 >= 0.0) ? di : -di));
+            for (int m = 0; m < NS; ++m) {
+                if (m < nslots) {
+                    if ((st.ld >> m) & 1u) gv[m] = st.g[m];
+                    if (m < nslots - 1 || last_ok) {
+                        const float2 kv = to_float2<DT>(st.k[m]);
+                        pr = fmaf(kv.x, gv[m].x, fmaf(kv.y, gv[m].y, pr));
+                        pim = fmaf(kv.x, gv[m].y, fmaf(-kv.y, gv[m].x, pim));
                     }
                 }
             }
+            if (rl(b.ok, t)) {
+                const float dr = wave_total(pr), di = wave_total(pim);
+                if (lane == 0) {
+                    float *w = (float *)(a.work + base + t);
+                    unsafeAtomicAdd(w, dr);
+                    unsafeAtomicAdd(w + 1, di);
+                }
+            }
         };
-        const int nsteps = n * nblk;
-        DStep<DT> sa, sb;
-        issue(0, 0, sa);
-        for (int sidx = 0; sidx < nsteps; sidx += 2) {
-            if (sidx + 1 < nsteps) issue((sidx + 1) / nblk, (sidx + 1) % nblk, sb);
-            consume(sidx, sa);
-            if (sidx + 1 < nsteps) {
-                if (sidx + 2 < nsteps) issue((sidx + 2) / nblk, (sidx + 2) % nblk, sa);
-                consume(sidx + 1, sb);
+
+        DStage<DT> sa, sb;
+        fetch(0, sa);
+        for (int t = 0; t < n; t += 2) {
+            if (t + 1 < n) fetch(t + 1, sb);
+            consume(t, sa);
+            if (t + 1 < n) {
+                if (t + 2 < n) fetch(t + 2, sa);
+                consume(t + 1, sb);
             }
         }
+    }
+}
+
+template <int DT>
+__device__ void degrid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
+    int c0, c1, ns;
+    chunk_classes(S, chunk, c0, c1, ns);
+    switch (ns) {
+    case 1: degrid_chunk_ns<DT, 1>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 2: degrid_chunk_ns<DT, 2>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 3: degrid_chunk_ns<DT, 3>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 4: degrid_chunk_ns<DT, 4>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 5: degrid_chunk_ns<DT, 5>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 6: degrid_chunk_ns<DT, 6>(a, S, c0, c1, rb, re, lane, koff); break;
+    case 7: degrid_chunk_ns<DT, 7>(a, S, c0, c1, rb, re, lane, koff); break;
+    default: degrid_chunk_ns<DT, 8>(a, S, c0, c1, rb, re, lane, koff); break;
     }
 }
 
@@ -426,7 +454,7 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, false, &ut);
+    if (threadIdx.x == 0) build_units(a.plan, true, &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -434,10 +462,38 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     for_each_unit(nunits, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]);
-        const int slot = uni(a.plan[kPlanOff + S]) + (u - uni(ut.first[m]));
-        degrid_chunk<DT>(a, S, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
+        const int S = uni(ut.S[m]), nch = nchunk_of(S);
+        const int rel = u - uni(ut.first[m]);
+        const int item = rel / nch, chunk = rel - item * nch;
+        const int slot = uni(a.plan[kPlanOff + S]) + item;
+        degrid_chunk<DT>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
     });
+}
+
+// Clears the per-run accumulators (n_runs entries, read on the device).
+__global__ void k_zero_work(GArgs a) {
+    const int64_t n = a.stats->n_runs;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        a.work[j] = make_float2(0.f, 0.f);
+}
+
+// Hands each run's dot product to its records: weight * (d, or conj d when w < 0).
+__global__ void k_degrid_finish(GArgs a) {
+    const int64_t n = a.stats->n_runs;
+    const int64_t seglen = (int64_t)a.nt * a.nc;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const float2 d = a.work[j];
+        const int64_t r0 = a.start[j];
+        const int cnt = a.len[j];
+        for (int m = 0; m < cnt; ++m) {
+            const int64_t r = r0 + m;
+            if (r < 0 || r >= a.n_rec) break;
+            const int64_t bb = r / seglen, tt = r - (r / a.nt) * a.nt;
+            const double wm = a.uvw[(bb * a.nt + tt) * 3 + 2];
+            const float e = a.wt ? a.wt[r] : 1.0f;
+            a.vis_out[r] = make_float2(e * d.x, e * ((wm >= 0.0) ? d.y : -d.y));
+        }
+    }
 }
 
 __global__ void k_zero(float2 *p, int64_t n) {
@@ -467,6 +523,8 @@ GArgs make_args(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs) {
     a.data = kt->data;
     a.grid = nullptr;
     a.vis_out = nullptr;
+    a.work = (float2 *)runs->work;
+    a.stats = nullptr;
     a.uvw = nullptr;
     a.wt = nullptr;
     return a;
@@ -512,7 +570,7 @@ extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *r
     if (st != WG_OK) return st;
     if ((st = check_table(g, kt)) != WG_OK) return st;
     if ((st = check_runs(runs)) != WG_OK) return st;
-    if (!grid || !stats || !uvw || !vis_out || nb < 1 || nc < 1 || nt < 1) return WG_EINVAL;
+    if (!grid || !stats || !uvw || !vis_out || !runs->work || nb < 1 || nc < 1 || nt < 1) return WG_EINVAL;
     if (kt->data_cap >= ((int64_t)1 << 28)) return WG_EUNSUPPORTED;  // byte offsets stay 32-bit
     const int64_t n_rec = nb * (int64_t)nc * nt;
     if (n_rec > runs->capacity) return WG_ECAPACITY;
@@ -524,13 +582,16 @@ extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *r
     a.nc = nc;
     a.nt = nt;
     a.n_rec = n_rec;
+    a.stats = stats;
     hipStream_t s = (hipStream_t)stream;
-    // records in no run get 0: clear the output first
+    // records in no run get 0: clear the output and the per-run accumulators first
     hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, s, (float2 *)vis_out, n_rec);
+    hipLaunchKernelGGL(k_zero_work, dim3(2048), dim3(256), 0, s, a);
     switch (kt->dtype) {
     case WG_KF32: hipLaunchKernelGGL(k_degrid<WG_KF32>, dim3(kPersistentBlocks), dim3(256), 0, s, a); break;
     case WG_KBF16: hipLaunchKernelGGL(k_degrid<WG_KBF16>, dim3(kPersistentBlocks), dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL(k_degrid<WG_KF16>, dim3(kPersistentBlocks), dim3(256), 0, s, a); break;
     }
+    hipLaunchKernelGGL(k_degrid_finish, dim3(2048), dim3(256), 0, s, a);
     return launch_status();
 }

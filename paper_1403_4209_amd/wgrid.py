@@ -51,7 +51,7 @@ class WgRuns(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("start", ctypes.c_void_p), ("len", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("plane", ctypes.c_void_p),
                 ("ou", ctypes.c_void_p), ("ov", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
-                ("plan", ctypes.c_void_p), ("plan_elems", ctypes.c_int64)]
+                ("plan", ctypes.c_void_p), ("plan_elems", ctypes.c_int64), ("work", ctypes.c_void_p)]
 
 
 _lib = None
@@ -218,9 +218,10 @@ class Runs:
         self.gamma = torch.empty(2 * cap, dtype=torch.float32, device=dev)
         pe = wg_plan_elems(cap, n_segments)
         self.plan = torch.empty(pe, dtype=torch.int32, device=dev)
+        self.work = torch.empty(2 * cap, dtype=torch.float32, device=dev)
         self.stats_d = torch.zeros(8, dtype=torch.int64, device=dev)
         self.c = WgRuns(cap, _p(self.start), _p(self.len), _p(self.x), _p(self.y), _p(self.plane), _p(self.ou),
-                        _p(self.ov), _p(self.gamma), _p(self.plan), pe)
+                        _p(self.ov), _p(self.gamma), _p(self.plan), pe, _p(self.work))
 
     def stats(self) -> Stats:
         h = self.stats_d.cpu()

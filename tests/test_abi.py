@@ -73,7 +73,7 @@ def test_entry_points_reject_null_arguments(wg):
     L = wg.lib()
     g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)
     kt = wg.WgKtable(0, 8, 8, 7, 1, 1, 1, 1, 1, 10)
-    runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000)
+    runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, 1)
     by = ctypes.byref
     assert L.wg_compress(by(g), by(kt), None, None, None, None, None, 1, 1, 1, by(runs), None, None) == wg.WG_EINVAL
     assert L.wg_compress(None, by(kt), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
@@ -86,6 +86,8 @@ def test_entry_points_reject_null_arguments(wg):
     assert L.wg_grid(by(g), None, by(runs), 1, 1, None) == wg.WG_EINVAL
     assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, None, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
     assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, 5, 1, 3, 1, None) == wg.WG_ECAPACITY
+    runs_nowork = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, None)
+    assert L.wg_degrid(by(g), by(kt), by(runs_nowork), 1, 1, 1, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
     assert L.wg_ktable_build(by(g), None, 1, 10, None, None, None) == wg.WG_EINVAL
     kt_small = wg.WgKtable(0, 8, 8, 0, 1, 1, 1, 1, 1, 10)
     assert L.wg_ktable_build(by(g), by(kt_small), 1, 10, None, None, None) == wg.WG_ECAPACITY
