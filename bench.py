@@ -196,8 +196,8 @@ def main():
         "grid_gupds_real": round(U / (t_grid * 1e-3) / 1e9, 2),
         "grid_gupds_total": round((U + st.upd_saved) / (t_grid * 1e-3) / 1e9, 2),
         "degrid_gupds": round(U / (t_degrid * 1e-3) / 1e9, 2),
-        "compression_ratio_records": round(st.n_compressed / max(st.n_runs, 1), 3),
-        "compression_ratio_updates": round(st.upd_saved / max(U, 1), 3),
+        "compression_ratio_records": round(st.n_griddable / max(st.n_runs, 1), 3),
+        "compression_ratio_updates": round((U + st.upd_saved) / max(U, 1), 3),
         "roofline": {"kernel": "k_grid (wg_grid)", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},

@@ -102,18 +102,93 @@ __global__ void k_init(CArgs a, int64_t n_records) {
     }
 }
 
+// Local chunks and statistics are gathered per workgroup in LDS and published with one
+// global atomic per counter (per-support counters and the statistics words are shared by
+// every wave of the launch, so per-wave atomics would serialise on a few addresses). In the
+// emit pass the chunk records are staged in LDS and given slots per support at the end; a
+// chunk that does not fit the stage takes its slot directly.
+constexpr int kStage = 1024;
+
+struct BlockAgg {
+    int cnt[64];       // chunks per support
+    int fill[64];      // emit: slots handed out per support
+    int base[64];      // emit: first slot reserved per support
+    int nstaged;
+    int2 items[kStage];
+    int itemS[kStage];
+    unsigned long long st[4];
+    double norm;
+};
+
+template <bool EMIT>
+__device__ inline void close_item(const CArgs &a, BlockAgg &agg, int S, int begin, int end) {
+    if (!EMIT) {
+        atomicAdd(&agg.cnt[S], 1);
+        return;
+    }
+    const int i = atomicAdd(&agg.nstaged, 1);
+    if (i < kStage) {
+        agg.items[i] = make_int2(begin, end);
+        agg.itemS[i] = S;
+        atomicAdd(&agg.cnt[S], 1);
+    } else {
+        const int slot = atomicAdd(&a.plan[kPlanCur + S], 1);
+        a.items[2 * slot] = begin;
+        a.items[2 * slot + 1] = end;
+    }
+}
+
+template <bool EMIT>
+__device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, const int *s_sup, BlockAgg &agg);
+
 template <bool EMIT>
 __global__ __launch_bounds__(256) void k_segments(CArgs a) {
     __shared__ double s_wb[WG_MAX_PLANES];
     __shared__ int s_sup[WG_MAX_PLANES];
+    __shared__ BlockAgg agg;
     for (int i = threadIdx.x; i < a.n_w; i += blockDim.x) {
         s_wb[i] = a.wbound[i];
         s_sup[i] = a.support[i];
     }
+    if (threadIdx.x < 64) {
+        agg.cnt[threadIdx.x] = 0;
+        agg.fill[threadIdx.x] = 0;
+    }
+    if (threadIdx.x < 4) agg.st[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        agg.nstaged = 0;
+        agg.norm = 0.0;
+    }
     __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1);
     const int64_t seg = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (seg >= a.n_seg) return;  // whole wave leaves; no barrier follows
+    if (seg < a.n_seg) walk_segment<EMIT>(a, seg, s_wb, s_sup, agg);
+    __syncthreads();
+    if (!EMIT) {
+        if (threadIdx.x < 64 && agg.cnt[threadIdx.x]) atomicAdd(&a.plan[kPlanCount + threadIdx.x], agg.cnt[threadIdx.x]);
+        if (threadIdx.x == 0) {
+            if (agg.st[0]) atomicAdd((unsigned long long *)&a.stats->n_griddable, agg.st[0]);
+            if (agg.st[1]) atomicAdd((unsigned long long *)&a.stats->n_compressed, agg.st[1]);
+            if (agg.st[2]) atomicAdd((unsigned long long *)&a.stats->upd_real, agg.st[2]);
+            if (agg.st[3]) atomicAdd((unsigned long long *)&a.stats->upd_saved, agg.st[3]);
+        }
+    } else {
+        if (threadIdx.x < 64 && agg.cnt[threadIdx.x])
+            agg.base[threadIdx.x] = atomicAdd(&a.plan[kPlanCur + threadIdx.x], agg.cnt[threadIdx.x]);
+        if (threadIdx.x == 0 && agg.norm != 0.0) atomicAdd(&a.stats->normaliser, agg.norm);
+        __syncthreads();
+        const int nst = min(agg.nstaged, kStage);
+        for (int i = threadIdx.x; i < nst; i += blockDim.x) {
+            const int S = agg.itemS[i];
+            const int slot = agg.base[S] + atomicAdd(&agg.fill[S], 1);
+            a.items[2 * slot] = agg.items[i].x;
+            a.items[2 * slot + 1] = agg.items[i].y;
+        }
+    }
+}
+
+template <bool EMIT>
+__device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, const int *s_sup, BlockAgg &agg) {
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t b = seg / a.nc;
     const int ch = (int)(seg - b * a.nc);
     const double il = a.il[ch];
@@ -176,15 +251,7 @@ __global__ __launch_bounds__(256) void k_segments(CArgs a) {
             ism &= ism - 1;
             const int SL = __shfl(S, L, kWave);
             const int jL = runs_before + __popcll(gm & ((1ull << L) - 1ull));
-            if (item_begin >= 0 && lane == 0) {
-                if (EMIT) {
-                    const int slot = atomicAdd(&a.plan[kPlanCur + item_S], 1);
-                    a.items[2 * slot] = run_base + item_begin;
-                    a.items[2 * slot + 1] = run_base + jL;
-                } else {
-                    atomicAdd(&a.plan[kPlanCount + item_S], 1);
-                }
-            }
+            if (item_begin >= 0 && lane == 0) close_item<EMIT>(a, agg, item_S, run_base + item_begin, run_base + jL);
             item_begin = jL;
             item_S = SL;
         }
@@ -268,27 +335,19 @@ __global__ __launch_bounds__(256) void k_segments(CArgs a) {
         if (gm) lastS = __shfl(S, 63 - __clzll(gm), kWave);
         runs_before += __popcll(gm);
     }
-    if (item_begin >= 0 && lane == 0) {
-        if (EMIT) {
-            const int slot = atomicAdd(&a.plan[kPlanCur + item_S], 1);
-            a.items[2 * slot] = run_base + item_begin;
-            a.items[2 * slot + 1] = run_base + runs_before;
-        } else {
-            atomicAdd(&a.plan[kPlanCount + item_S], 1);
-        }
-    }
+    if (item_begin >= 0 && lane == 0) close_item<EMIT>(a, agg, item_S, run_base + item_begin, run_base + runs_before);
     if (!EMIT) {
         const int64_t real = wave_sum(my_real), saved = wave_sum(my_saved);
         if (lane == 0) {
             a.segcnt[seg] = runs_before;
-            atomicAdd((unsigned long long *)&a.stats->n_griddable, (unsigned long long)n_ok);
-            atomicAdd((unsigned long long *)&a.stats->n_compressed, (unsigned long long)n_c);
-            atomicAdd((unsigned long long *)&a.stats->upd_real, (unsigned long long)real);
-            atomicAdd((unsigned long long *)&a.stats->upd_saved, (unsigned long long)saved);
+            atomicAdd(&agg.st[0], (unsigned long long)n_ok);
+            atomicAdd(&agg.st[1], (unsigned long long)n_c);
+            atomicAdd(&agg.st[2], (unsigned long long)real);
+            atomicAdd(&agg.st[3], (unsigned long long)saved);
         }
     } else {
         const double nsum = wave_sum(my_norm);
-        if (lane == 0) atomicAdd(&a.stats->normaliser, nsum);
+        if (lane == 0) atomicAdd(&agg.norm, nsum);
     }
 }
 

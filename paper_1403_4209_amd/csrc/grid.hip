@@ -112,7 +112,7 @@ __device__ void build_units(const int32_t *plan, bool per_row_chunk, UnitTable *
 // Run records of up to 64 consecutive runs, one per lane, with everything the per-run loop
 // needs precomputed in parallel; the loop then broadcasts run t with v_readlane.
 struct RunBatch {
-    int ax, row0, am, r0m, kb, ok;
+    int cell0, ph, kb, ok;  // ph: footprint origin phases, (row0 mod S) << 16 | (ax mod S)
     float gr, gi;
 };
 
@@ -123,7 +123,7 @@ __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ inline RunBatch load_batch(const GArgs &a, int S, int j, bool valid, const int64_t *koff) {
     RunBatch b;
     b.ok = 0;
-    b.ax = b.row0 = b.am = b.r0m = b.kb = 0;
+    b.cell0 = b.ph = b.kb = 0;
     b.gr = b.gi = 0.f;
     if (valid) {
         const int H = (S - 1) >> 1, half = a.n >> 1, hb = a.beta >> 1;
@@ -137,10 +137,8 @@ __device__ inline RunBatch load_batch(const GArgs &a, int S, int j, bool valid, 
         if (ax >= 0 && ax + S <= a.n && row0 >= 0 && row0 + S <= a.n && kbase >= 0 &&
             kbase + (int64_t)S * S <= a.data_cap) {
             b.ok = 1;
-            b.ax = ax;
-            b.row0 = row0;
-            b.am = ax % S;
-            b.r0m = row0 % S;
+            b.cell0 = row0 * a.n + ax;
+            b.ph = (row0 % S) << 16 | (ax % S);
             b.kb = (int)kbase;
             b.gr = g.x;
             b.gi = g.y;
@@ -161,6 +159,35 @@ __device__ inline typename KRaw<DT>::type buf_load(__amdgpu_buffer_rsrc_t rs, in
         return make_float2(__int_as_float(v[0]), __int_as_float(v[1]));
     } else {
         return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    }
+}
+
+// Class positions are handled as two 16-bit halves, column in the low half and row in the
+// high half, so that both wraps take three packed integer ops and each linear index one
+// v_dot2_u32_u16.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline u16x2 as_u16x2(unsigned v) { return __builtin_bit_cast(u16x2, v); }
+
+// Position (column jj, row ii) of the class cls = (q, p) in a footprint whose origin has the
+// phases ph = (ax mod S, row0 mod S): ((q - ax) mod S, (p - row0) mod S).
+__device__ inline u16x2 footprint_pos(u16x2 cls, u16x2 ph, u16x2 ss) {
+    const u16x2 d = cls - ph;
+    return __builtin_elementwise_min(d, d + ss);
+}
+
+// w.x * m.x + w.y * m.y + c (v_dot2_u32_u16)
+__device__ inline unsigned dot2(u16x2 w, u16x2 m, unsigned c) { return __builtin_amdgcn_udot2(w, m, c, false); }
+
+// The lane's classes of a chunk: slot m holds class min(c0 + 64 m + lane, c1 - 1) as (q, p).
+template <int NS>
+__device__ inline void lane_classes(int S, int c0, int c1, int lane, u16x2 *cls) {
+    const float rS = 1.0f / (float)S;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+        const int c = min(c0 + m * kWave + lane, c1 - 1);
+        const int pp = (int)((float)c * rS + 0.5f * rS);
+        cls[m] = u16x2{(unsigned short)(c - pp * S), (unsigned short)pp};
     }
 }
 
@@ -186,34 +213,26 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
     constexpr int nslots = NS;
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
-    const float rS = 1.0f / (float)S;
 
-    // The lane's classes (row class, column class). Every slot but the last is full for
-    // every lane; the last one may be partial.
-    int cp[kSlots], cq[kSlots];
-#pragma unroll
-    for (int m = 0; m < NS; ++m) {
-        const int c = min(c0 + m * kWave + lane, c1 - 1);
-        const int pp = (int)((float)c * rS + 0.5f * rS);
-        cp[m] = pp;
-        cq[m] = c - pp * S;
-    }
+    // The lane's classes. Every slot but the last is full for every lane; the last one may
+    // be partial.
+    u16x2 cls[kSlots];
+    lane_classes<NS>(S, c0, c1, lane, cls);
     const bool last_ok = c0 + (nslots - 1) * kWave + lane < c1;
+    const u16x2 ss = {(unsigned short)S, (unsigned short)S};
+    const u16x2 mul_k = {(unsigned short)esz, (unsigned short)(S * esz)};  // byte offset in a matrix
+    const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};           // cell offset in the grid
     float acc_r[kSlots], acc_i[kSlots], cmp_r[kSlots], cmp_i[kSlots];
-    int cur[kSlots];  // owned cell (y*n + x), -1 = none
+    int cur[kSlots];  // owned cell (y*n + x); set from the chunk's first run
 #pragma unroll
-    for (int m = 0; m < NS; ++m) {
-        acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
-        cur[m] = -1;
-    }
+    for (int m = 0; m < NS; ++m) acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
     auto commit = [&](int m) {
         float *cell = a.grid + 2 * (int64_t)cur[m];
         unsafeAtomicAdd(cell, acc_r[m] - cmp_r[m]);
         unsafeAtomicAdd(cell + 1, acc_i[m] - cmp_i[m]);
         acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
     };
-    // (d mod S) for d in (-S, S): unsigned min of d and d + S
-    auto wrap = [&](int d) { return (int)min((unsigned)d, (unsigned)(d + S)); };
+    bool first = true;
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
@@ -221,16 +240,14 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
 
         // cells and samples of the lane's classes for run t
         auto fetch = [&](int t, Stage<DT> &st) {
-            const int am = rl(b.am, t), r0m = rl(b.r0m, t);
-            const int cell0 = rl(b.row0, t) * a.n + rl(b.ax, t);
-            const int kbB = rl(b.kb, t) * esz;
+            const u16x2 ph = as_u16x2((unsigned)rl(b.ph, t));
+            const unsigned cell0 = (unsigned)rl(b.cell0, t);
+            const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
-                if (m < nslots) {
-                    const int ii = wrap(cp[m] - r0m), jj = wrap(cq[m] - am);
-                    st.yc[m] = (int)__umul24(ii, a.n) + cell0 + jj;
-                    st.k[m] = buf_load<DT>(rs, kbB + (int)(__umul24(ii, S) + jj) * esz);
-                }
+                const u16x2 w = footprint_pos(cls[m], ph, ss);
+                st.yc[m] = (int)dot2(w, mul_c, cell0);
+                st.k[m] = buf_load<DT>(rs, (int)dot2(w, mul_k, kbB));
             }
         };
         auto accumulate = [&](int t, const Stage<DT> &st) {
@@ -238,9 +255,9 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
             const float gr = rlf(b.gr, t), gi = rlf(b.gi, t);
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
-                if (m < nslots && (m < nslots - 1 || last_ok)) {
+                if (m < nslots - 1 || last_ok) {
                     if (st.yc[m] != cur[m]) {
-                        if (cur[m] >= 0) commit(m);
+                        commit(m);
                         cur[m] = st.yc[m];
                     }
                     // Kahan step with the product fused into the compensation:
@@ -259,6 +276,11 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
 
         Stage<DT> sa, sb;
         fetch(0, sa);
+        if (first) {
+#pragma unroll
+            for (int m = 0; m < NS; ++m) cur[m] = sa.yc[m];
+            first = false;
+        }
         for (int t = 0; t < n; t += 2) {
             if (t + 1 < n) fetch(t + 1, sb);
             accumulate(t, sa);
@@ -270,7 +292,7 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
     }
 #pragma unroll
     for (int m = 0; m < NS; ++m)
-        if (cur[m] >= 0) commit(m);
+        if (!first && (m < nslots - 1 || last_ok)) commit(m);
 }
 
 // Classes [c0, c1) of a support-S chunk, split evenly over the chunk's waves; the slot
@@ -354,18 +376,13 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
     constexpr int nslots = NS;
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
-    const float rS = 1.0f / (float)S;
     const float2 *grid = (const float2 *)a.grid;
-    int cp[kSlots], cq[kSlots];
-#pragma unroll
-    for (int m = 0; m < NS; ++m) {
-        const int c = min(c0 + m * kWave + lane, c1 - 1);
-        const int pp = (int)((float)c * rS + 0.5f * rS);
-        cp[m] = pp;
-        cq[m] = c - pp * S;
-    }
+    u16x2 cls[kSlots];
+    lane_classes<NS>(S, c0, c1, lane, cls);
     const bool last_ok = c0 + (nslots - 1) * kWave + lane < c1;
-    auto wrap = [&](int d) { return (int)min((unsigned)d, (unsigned)(d + S)); };
+    const u16x2 ss = {(unsigned short)S, (unsigned short)S};
+    const u16x2 mul_k = {(unsigned short)esz, (unsigned short)(S * esz)};
+    const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};
     int pyc[kSlots];      // cells of the most recently fetched run
     float2 gv[kSlots];    // grid values of the owned cells
 #pragma unroll
@@ -379,23 +396,21 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
         const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
 
         auto fetch = [&](int t, DStage<DT> &st) {
-            const int am = rl(b.am, t), r0m = rl(b.r0m, t);
-            const int cell0 = rl(b.row0, t) * a.n + rl(b.ax, t);
-            const int kbB = rl(b.kb, t) * esz;
+            const u16x2 ph = as_u16x2((unsigned)rl(b.ph, t));
+            const unsigned cell0 = (unsigned)rl(b.cell0, t);
+            const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
             st.ld = 0;
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
-                if (m < nslots) {
-                    const int ii = wrap(cp[m] - r0m), jj = wrap(cq[m] - am);
-                    const int yc = (int)__umul24(ii, a.n) + cell0 + jj;
-                    st.yc[m] = yc;
-                    st.k[m] = buf_load<DT>(rs, kbB + (int)(__umul24(ii, S) + jj) * esz);
-                    if (yc != pyc[m]) {
-                        st.ld |= 1u << m;
-                        st.g[m] = grid[yc];
-                    }
-                    pyc[m] = yc;
+                const u16x2 w = footprint_pos(cls[m], ph, ss);
+                const int yc = (int)dot2(w, mul_c, cell0);
+                st.yc[m] = yc;
+                st.k[m] = buf_load<DT>(rs, (int)dot2(w, mul_k, kbB));
+                if (yc != pyc[m]) {
+                    st.ld |= 1u << m;
+                    st.g[m] = grid[yc];
                 }
+                pyc[m] = yc;
             }
         };
         auto consume = [&](int t, const DStage<DT> &st) {

@@ -143,6 +143,7 @@ struct BuildArgs {
     double2 *win;  // [n_w][W][W]  normalised central window
     double *c00;
     int *kmax;
+    double *tap;   // [M] taper at the image samples
 };
 
 __device__ inline double plane_w(int k, int n_w, double w_max) {
@@ -156,8 +157,8 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 }
 
 // In-place radix-2 decimation-in-time FFT (forward, e^{-2 pi i}) of L points in LDS; the
-// input must already be in bit-reversed order. tw[j] = exp(-2 pi i j / L), j < L/2.
-__device__ void fft_lds(double2 *s, int L, const double2 *__restrict__ tw) {
+// input must already be in bit-reversed order. tw[j] = exp(-2 pi i j / L), j < L/2, also in LDS.
+__device__ void fft_lds(double2 *s, int L, const double2 *tw) {
     for (int len = 2; len <= L; len <<= 1) {
         const int half = len >> 1, step = L / len;
         for (int b = threadIdx.x; b < (L >> 1); b += blockDim.x) {
@@ -182,21 +183,35 @@ __global__ void k_twiddle(double2 *tw, int L) {
     }
 }
 
+// The taper at the M image samples, x_p = 2(p - M/2)/M.
+__global__ void k_taper(BuildArgs a, TaperCoef tc) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < a.M) a.tap[p] = taper(2.0 * (double)(p - a.M / 2) / (double)a.M, tc);
+}
+
+// Twiddles of an L-point transform into LDS (after the data block).
+__device__ inline double2 *load_twiddles(double2 *s, const BuildArgs &a) {
+    double2 *tw = s + a.L;
+    for (int j = threadIdx.x; j < a.L / 2; j += blockDim.x) tw[j] = a.tw[j];
+    return tw;
+}
+
 // Row pass: image row q of plane k -> L-point FFT along u; stores the centred spectrum
 // column-major so the column pass reads contiguous values.
-__global__ void k_rows(BuildArgs a, TaperCoef tc) {
+__global__ void k_rows(BuildArgs a) {
     extern __shared__ double2 s[];
     const int q = blockIdx.x, k = blockIdx.y;
+    double2 *tw = load_twiddles(s, a);
     for (int i = threadIdx.x; i < a.L; i += blockDim.x) s[i] = make_double2(0.0, 0.0);
     __syncthreads();
     const double xq = 2.0 * (double)(q - a.M / 2) / (double)a.M;
     const double m = xq / (2.0 * a.du);
-    const double tq = taper(xq, tc);
+    const double tq = a.tap[q];
     const double w = plane_w(k, a.n_w, a.w_max);
     for (int p = threadIdx.x; p < a.M; p += blockDim.x) {
         const double xp = 2.0 * (double)(p - a.M / 2) / (double)a.M;
         const double l = xp / (2.0 * a.du);
-        const double tp = taper(xp, tc);
+        const double tp = a.tap[p];
         const double rr = (1.0 - l * l) - m * m;
         double2 v = make_double2(0.0, 0.0);
         if (rr >= 0.0) {
@@ -211,7 +226,7 @@ __global__ void k_rows(BuildArgs a, TaperCoef tc) {
         s[bitrev(pos, a.lgL)] = v;
     }
     __syncthreads();
-    fft_lds(s, a.L, a.tw);
+    fft_lds(s, a.L, tw);
     double2 *out = a.A + (size_t)k * a.L * a.M;
     for (int kk = threadIdx.x; kk < a.L; kk += blockDim.x) {
         const int cu = (kk + a.L / 2) & (a.L - 1);
@@ -249,6 +264,7 @@ __global__ void k_cols(BuildArgs a) {
     extern __shared__ double2 s[];
     __shared__ int red[256];
     const int cu = blockIdx.x, k = blockIdx.y;
+    double2 *tw = load_twiddles(s, a);
     for (int i = threadIdx.x; i < a.L; i += blockDim.x) s[i] = make_double2(0.0, 0.0);
     __syncthreads();
     const double2 *in = a.A + ((size_t)k * a.L + cu) * a.M;
@@ -257,7 +273,7 @@ __global__ void k_cols(BuildArgs a) {
         s[bitrev(pos, a.lgL)] = in[q];
     }
     __syncthreads();
-    fft_lds(s, a.L, a.tw);
+    fft_lds(s, a.L, tw);
     const double c00 = *a.c00;
     const int fu = cu - a.L / 2;
     const bool keep_u = fu >= -a.Wf && fu <= a.Wf;
@@ -365,7 +381,7 @@ __global__ void k_slices(BuildArgs a, const int32_t *__restrict__ support,
 }
 
 struct WsLayout {
-    size_t tw, A, win, c00, kmax, total;
+    size_t tw, A, win, c00, kmax, tap, total;
     int L, Wf, W;
 };
 
@@ -387,6 +403,8 @@ WsLayout ws_layout(const wg_geom *g) {
     o = align256(o + sizeof(double));
     w.kmax = o;
     o = align256(o + sizeof(int) * g->n_w);
+    w.tap = o;
+    o = align256(o + sizeof(double) * g->m_img);
     w.total = o;
     return w;
 }
@@ -437,10 +455,12 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
     a.win = (double2 *)(base + lay.win);
     a.c00 = (double *)(base + lay.c00);
     a.kmax = (int *)(base + lay.kmax);
+    a.tap = (double *)(base + lay.tap);
 
-    const size_t lds = sizeof(double2) * a.L;
+    const size_t lds = sizeof(double2) * (a.L + a.L / 2);  // data + twiddles
     hipLaunchKernelGGL(k_twiddle, dim3((a.L / 2 + 255) / 256), dim3(256), 0, s, (double2 *)a.tw, a.L);
-    hipLaunchKernelGGL(k_rows, dim3(a.M, a.n_w), dim3(256), lds, s, a, tc);
+    hipLaunchKernelGGL(k_taper, dim3((a.M + 255) / 256), dim3(256), 0, s, a, tc);
+    hipLaunchKernelGGL(k_rows, dim3(a.M, a.n_w), dim3(256), lds, s, a);
     hipLaunchKernelGGL(k_c00_and_reset, dim3(1), dim3(256), 0, s, a, kt->wbound);
     hipLaunchKernelGGL(k_cols, dim3(a.L, a.n_w), dim3(256), lds, s, a);
     hipLaunchKernelGGL(k_supports, dim3(1), dim3(64), 0, s, a, g->s_lo, g->s_hi, kt->support, kt->offset);

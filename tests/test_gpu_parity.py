@@ -321,6 +321,28 @@ def test_flags_nan_offgrid_and_edges():
     assert np.all(o[1] == 0)                       # flagged baseline -> exactly zero
 
 
+def test_many_local_chunks_per_workgroup():
+    """w alternating across a plane edge with different supports: every record is a run and
+    every run its own local chunk (> 1024 chunks per 4-segment workgroup exercises the
+    emit pass's direct-slot path)."""
+    nt = 600
+    data = _records(4, 1, nt, EDGE_GEOM, seed=12, spread=0.2)
+    wb = okt.w_bounds(EDGE_GEOM["n_w"], EDGE_GEOM["w_max"])
+    data["uvw"][:, :, 2] = np.where(np.arange(nt) % 2 == 0, 0.5 * wb[1], 1.5 * wb[1])
+    _, gr, G = run_gpu(EDGE_GEOM, data)
+    st = gr.runs.stats()
+    orc = oracle.compress(EDGE_GEOM, otable(EDGE_GEOM, "f32"), data["uvw"], data["il"], data["vis"], data["wt"])
+    compare_runs(gr, orc)
+    assert st.n_items == st.n_runs == 4 * nt
+    Go = oracle.grid(EDGE_GEOM, otable(EDGE_GEOM, "f64"), orc)
+    assert rel_l2(G.cpu().numpy(), Go) < 1e-5
+    g = torch.as_tensor(Go.astype(np.complex64)).to(DEV)
+    out = gr.degrid(g)
+    torch.cuda.synchronize()
+    ref = oracle.degrid(EDGE_GEOM, otable(EDGE_GEOM, "f64"), orc, Go, data["uvw"], data["wt"], data["vis"].shape)
+    assert rel_l2(out.cpu().numpy().astype(np.complex128), ref) < 1e-5
+
+
 def test_everything_flagged():
     data = _records(2, 2, 70, EDGE_GEOM, seed=2)
     data["flag"][:] = 1
@@ -375,3 +397,133 @@ def test_full_config2_runs_and_sampled_grid():
     err = rel_l2(G2.cpu().numpy().astype(np.complex128), Go)
     say(f"  cfg2 sampled grid rel L2 {err:.3e}")
     assert err < 1e-5
+
+
+def _rel_l2_dev(a, b):
+    a = a.to(torch.complex128)
+    b = b.to(torch.complex128)
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def test_full_config3_compression_and_precision():
+    """Config 3 at full size (946 baselines x 64 channels x 512 timesteps = 30,998,528
+    records, 4096^2, 64 planes, supports 9..63): every run boundary and key bit-exact;
+    compressed and uncompressed GPU grids agree; BF16 and FP16 tables against the FP32-table
+    grid over the full grid, and all three against the FP64 oracle on every 31st baseline."""
+    w = workloads.make(3, device=DEV)
+    say("cfg3 records", w.n_records, w.geom)
+    vis_h = w.vis.cpu().numpy()
+    data = dict(uvw=w.uvw, il=w.inv_lambda, vis=vis_h, wt=None, flag=None)
+    t32, gr, G32 = run_gpu(w.geom, data)
+    orc = oracle.compress(w.geom, otable(w.geom, "f32"), w.uvw, w.inv_lambda, vis_h)
+    _, st = compare_runs(gr, orc)
+    say(f"  cfg3 compression: records/runs {st.n_griddable / st.n_runs:.3f}, "
+        f"updates total/real {(st.upd_real + st.upd_saved) / st.upd_real:.3f}")
+    del orc, gr
+    _, gu, Gu = run_gpu(w.geom, data, compress=False, table=t32)
+    err_u = _rel_l2_dev(Gu, G32)
+    say(f"  cfg3 uncompressed vs compressed rel L2 {err_u:.3e}")
+    assert err_u < 1e-5
+    del gu, Gu
+    full = {}
+    for dt, tol in (("bf16", 3e-3), ("f16", 1e-3)):
+        _, g2, Gd = run_gpu(w.geom, data, dtype=dt)
+        full[dt] = _rel_l2_dev(Gd, G32)
+        say(f"  cfg3 full-grid rel L2 {dt} vs f32 tables {full[dt]:.3e}")
+        assert full[dt] < tol
+        del g2, Gd
+    sub = slice(0, None, 31)
+    d2 = dict(uvw=w.uvw[sub], il=w.inv_lambda, vis=vis_h[sub], wt=None, flag=None)
+    t64 = otable(w.geom, "f64")
+    Go = oracle.grid(w.geom, t64, oracle.compress(w.geom, t64, d2["uvw"], d2["il"], d2["vis"]))
+    for dt, tol in (("f32", 1e-5), ("bf16", 3e-3), ("f16", 1e-3)):
+        _, _, Gs = run_gpu(w.geom, d2, dtype=dt)
+        err = rel_l2(Gs.cpu().numpy().astype(np.complex128), Go)
+        say(f"  cfg3 sampled grid rel L2 {dt} vs FP64 oracle {err:.3e}")
+        assert err < tol
+
+
+@pytest.fixture(scope="module")
+def cfg4_full():
+    w = workloads.make(4, device=DEV)
+    vis_h = w.vis.cpu().numpy()
+    data = dict(uvw=w.uvw, il=w.inv_lambda, vis=vis_h, wt=None, flag=None)
+    t64 = otable(w.geom, "f64")
+    orc = oracle.compress(w.geom, t64, w.uvw, w.inv_lambda, vis_h)
+    return w.geom, data, orc, oracle.grid(w.geom, t64, orc)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 3e-3), ("f16", 1e-3)])
+def test_full_config4_precision(cfg4_full, dtype, tol):
+    """Config 4 (the 512^2 precision sub-problem: 946 x 8 x 64 records, 64 planes, supports
+    9..63) at full size: runs bit-exact, grid and degrid of each table type against the FP64
+    oracle on its FP64 table."""
+    geom, data, orc, Go = cfg4_full
+    _, gr, G = run_gpu(geom, data, dtype=dtype)
+    # the normaliser sums the stored (rounded) table values: compare against the same table
+    compare_runs(gr, oracle.compress(geom, otable(geom, dtype), data["uvw"], data["il"], data["vis"]))
+    err = rel_l2(G.cpu().numpy().astype(np.complex128), Go)
+    rng = np.random.default_rng(44)
+    n = geom["n"]
+    g = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64)
+    out = gr.degrid(torch.as_tensor(g).to(DEV))
+    torch.cuda.synchronize()
+    ref = oracle.degrid(geom, otable(geom, "f64"), orc, g.astype(np.complex128), data["uvw"], None,
+                        data["vis"].shape)
+    err_d = rel_l2(out.cpu().numpy().astype(np.complex128), ref)
+    say(f"  cfg4 {dtype}: grid rel L2 {err:.3e}, degrid rel L2 {err_d:.3e}")
+    assert err < tol and err_d < tol
+
+
+def test_full_config5_adjoint_and_finite_difference():
+    """Config 5 at full size (32,640 baselines x 8 channels x 256 timesteps = 66,846,720
+    records, 4096^2, supports 7..31) through GridFn: runs bit-exact; the dot-product test
+    <G v, g> = <v, G^H g> with a random grid g; and central differences of
+    L = ||IFFT(grid)/normaliser - target||^2 (target: 100 seeded point sources) along the
+    data direction and along the returned gradient (L is quadratic, so the central
+    difference has no truncation error; only FP32 rounding of the grid enters)."""
+    w = workloads.make(5, device=DEV)
+    say("cfg5 records", w.n_records, w.geom)
+    geom = wg.geom_from_dict(w.geom)
+    table = wg.KernelTable(geom, "f32", device=DEV)
+    uvw = torch.as_tensor(w.uvw).to(DEV)
+    il = torch.as_tensor(w.inv_lambda).to(DEV)
+    gridder = wg.Gridder(geom, table, uvw, il)
+    v = w.vis
+    with torch.no_grad():
+        G = wg.GridFn.apply(v, gridder)
+    torch.cuda.synchronize()
+    orc = oracle.compress(w.geom, otable(w.geom, "f32"), w.uvw, w.inv_lambda, v.cpu().numpy())
+    _, st = compare_runs(gridder, orc)
+    del orc
+    n = w.geom["n"]
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(55)
+    g = torch.complex(torch.randn((n, n), generator=gen, device=DEV), torch.randn((n, n), generator=gen, device=DEV))
+    lhs = torch.vdot(G.flatten().to(torch.complex128), g.flatten().to(torch.complex128)).real
+    ghg = gridder.degrid(g)
+    rhs = torch.vdot(v.flatten().to(torch.complex128), ghg.flatten().to(torch.complex128)).real
+    scale = float(torch.linalg.norm(G.to(torch.complex128)) * torch.linalg.norm(g.to(torch.complex128)))
+    say(f"  cfg5 dot-product test: |lhs - rhs| / (|Gv| |g|) = {abs(float(lhs - rhs)) / scale:.3e}")
+    assert abs(float(lhs - rhs)) < 1e-5 * scale
+    del g, ghg
+
+    norm = n * n / st.normaliser
+    target = torch.as_tensor(workloads.target_image(w)).to(DEV)
+
+    def loss(vv):
+        grid = wg.GridFn.apply(vv, gridder).to(torch.complex128)
+        img = torch.fft.fftshift(torch.fft.ifft2(torch.fft.ifftshift(grid))) * norm
+        return ((img.real - target) ** 2 + img.imag ** 2).sum()
+
+    vr = v.clone().requires_grad_(True)
+    L = loss(vr)
+    L.backward()
+    grad = vr.grad.detach()
+    for name, d in (("data", v), ("gradient", grad / torch.linalg.norm(grad) * torch.linalg.norm(v))):
+        h = 0.25
+        with torch.no_grad():
+            fd = (loss(v + h * d) - loss(v - h * d)) / (2 * h)
+        an = torch.sum(grad.to(torch.complex128).conj() * d.to(torch.complex128)).real
+        say(f"  cfg5 FD along {name}: {float(fd):.9e} analytic {float(an):.9e} (L {float(L):.6e})")
+        assert abs(float(fd - an)) < 1e-4 * abs(float(an))

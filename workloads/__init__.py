@@ -175,3 +175,17 @@ def make(cfg: int, device=None, **overrides) -> Workload:
     geom = dict(n=p["n"], beta=p["beta"], n_w=p["n_w"], s_lo=p["s_lo"], s_hi=p["s_hi"],
                 m_img=p["m_img"], du=float(du), w_max=w_max)
     return Workload(cfg, uvw, inv_lambda, vis, weight, flag, geom, sources, p)
+
+
+def target_image(w: Workload, n_src: int = 100, seed: int = 4000) -> np.ndarray:
+    """A seeded model sky for the differentiation workload: n_src point sources of flux
+    U[0.5, 5] placed on image pixels inside the central 80 % of an N x N image whose pixel
+    size is FOV/N = 1/(N du); float64 [N, N], row = m, column = l, centre at N/2."""
+    n = w.geom["n"]
+    rng = np.random.default_rng(seed + w.cfg)
+    img = np.zeros((n, n))
+    lim = int(0.4 * n)
+    pix = rng.integers(-lim, lim + 1, size=(n_src, 2))
+    flux = 0.5 + 4.5 * rng.random(n_src)
+    np.add.at(img, (n // 2 + pix[:, 1], n // 2 + pix[:, 0]), flux)
+    return img
