@@ -2,10 +2,16 @@
 //
 // Per w-plane: evaluate the image-plane function (separable prolate spheroidal taper times
 // the inverse w-screen) on m_img x m_img samples, zero-pad to L = beta*m_img, apply a
-// forward 2-D FFT (row pass, then column pass, each an L-point radix-2 FFT held in LDS),
-// normalise by the w=0 plane's centre value, find the natural support from the 1e-3
-// magnitude threshold, then trim/reorder into one S x S matrix per oversample offset pair,
-// round to the table's storage type and sum real parts (eq. sum).
+// forward 2-D DFT (row pass, then column pass), normalise by the w=0 plane's centre value,
+// find the natural support from the 1e-3 magnitude threshold, then trim/reorder into one
+// S x S matrix per oversample offset pair, round to the table's storage type and sum real
+// parts (eq. sum).
+//
+// Each L-point transform of a zero-padded line of M samples x[n], n in [-M/2, M/2), is
+// computed as beta transforms of M points: X[beta*k1 + b] = sum_n (x[n] w_L^(n b)) w_M^(n k1)
+// with w_N = exp(-2 pi i / N). The M-point transforms are Stockham auto-sort FFTs whose
+// passes (radix 16, and one radix-2/4/8 pass when log2 M is not a multiple of 4) run in
+// registers and exchange through LDS between passes.
 //
 // The prolate spheroidal function psi_0(c, x), c = 3*pi, is computed here from its
 // expansion in normalised Legendre polynomials: the coefficients are the eigenvector of
@@ -136,7 +142,7 @@ __device__ double taper(double x, const TaperCoef &tc) {
 }
 
 struct BuildArgs {
-    int M, L, lgL, beta, n_w, Wf, W, dtype;
+    int M, L, lgM, beta, n_w, Wf, W, dtype;
     double du, w_max;
     const double2 *tw;
     double2 *A;    // [n_w][L][M]  row-pass output, column-major per plane
@@ -156,27 +162,137 @@ __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place radix-2 decimation-in-time FFT (forward, e^{-2 pi i}) of L points in LDS; the
-// input must already be in bit-reversed order. tw[j] = exp(-2 pi i j / L), j < L/2, also in LDS.
-__device__ void fft_lds(double2 *s, int L, const double2 *tw) {
-    for (int len = 2; len <= L; len <<= 1) {
-        const int half = len >> 1, step = L / len;
-        for (int b = threadIdx.x; b < (L >> 1); b += blockDim.x) {
-            const int grp = b / half, pos = b - grp * half;
-            const int i = grp * len + pos, j = i + half;
-            double2 u = s[i], v = cmul(s[j], tw[pos * step]);
-            s[i] = make_double2(u.x + v.x, u.y + v.y);
-            s[j] = make_double2(u.x - v.x, u.y - v.y);
-        }
-        __syncthreads();
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// exp(-2 pi i j / 16), j < 8: cos and sin of multiples of pi/8
+constexpr double kCos1 = 0.92387953251128675613;  // cos(pi/8)
+constexpr double kSin1 = 0.38268343236508977173;  // sin(pi/8)
+constexpr double kHalfRt2 = 0.70710678118654752440;
+
+// d * exp(-2 pi i j / 16) for a compile-time j after unrolling
+__device__ inline double2 rot16(double2 d, int j) {
+    switch (j) {
+    case 0: return d;
+    case 1: return cmul(d, make_double2(kCos1, -kSin1));
+    case 2: return cmul(d, make_double2(kHalfRt2, -kHalfRt2));
+    case 3: return cmul(d, make_double2(kSin1, -kCos1));
+    case 4: return make_double2(d.y, -d.x);
+    case 5: return cmul(d, make_double2(-kSin1, -kCos1));
+    case 6: return cmul(d, make_double2(-kHalfRt2, -kHalfRt2));
+    default: return cmul(d, make_double2(-kCos1, -kSin1));
     }
 }
 
-__device__ inline int bitrev(int x, int lg) { return (int)(__brev((unsigned)x) >> (32 - lg)); }
+constexpr int bitrev_c(int k, int bits) {
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((k >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+
+// Forward DFT of R <= 16 points in registers, natural order in and out (radix-2
+// decimation in frequency, then the bit-reversal permutation).
+template <int R>
+__device__ inline void dft_reg(double2 (&v)[R]) {
+    constexpr int bits = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+#pragma unroll
+    for (int h = R / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int s0 = 0; s0 < R; s0 += 2 * h) {
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+                const double2 x = v[s0 + i], y = v[s0 + i + h];
+                v[s0 + i] = cadd(x, y);
+                v[s0 + i + h] = rot16(csub(x, y), i * (16 / (2 * h)));
+            }
+        }
+    }
+    double2 t[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) t[k] = v[bitrev_c(k, bits)];
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = t[k];
+}
+
+// One radix-R Stockham pass over nsub independent M-point transforms. ns is the product of
+// the radices of the earlier passes. Butterfly j of a transform reads elements j + r*M/R,
+// multiplies element r by exp(-2 pi i (j mod ns) r / (ns R)), transforms, and writes
+// element r to (j - j mod ns) R + (j mod ns) + r ns. ld(b, e) and st(b, e, v) access
+// element e of transform b.
+template <int R, class Ld, class St>
+__device__ inline void stockham_pass(int M, int nsub, int ns, int L, const double2 *__restrict__ tw, Ld ld, St st) {
+    const int nb = M / R;
+    const int step = L / (ns * R);
+    for (int t = threadIdx.x; t < nsub * nb; t += blockDim.x) {
+        const int b = t / nb, j = t - b * nb;
+        const int jm = j & (ns - 1);
+        double2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            v[r] = ld(b, j + r * nb);
+            if (r > 0 && ns > 1) v[r] = cmul(v[r], tw[jm * r * step]);
+        }
+        dft_reg<R>(v);
+        const int d0 = (j - jm) * R + jm;
+#pragma unroll
+        for (int r = 0; r < R; ++r) st(b, d0 + r * ns, v[r]);
+    }
+}
+
+template <class Ld, class St>
+__device__ inline void stockham_any(int R, int M, int nsub, int ns, int L, const double2 *tw, Ld ld, St st) {
+    switch (R) {
+    case 2: stockham_pass<2>(M, nsub, ns, L, tw, ld, st); break;
+    case 4: stockham_pass<4>(M, nsub, ns, L, tw, ld, st); break;
+    case 8: stockham_pass<8>(M, nsub, ns, L, tw, ld, st); break;
+    default: stockham_pass<16>(M, nsub, ns, L, tw, ld, st); break;
+    }
+}
+
+// Passes of an M-point transform (M = 2^lgM): radix 2^(lgM mod 4) first when lgM is not a
+// multiple of 4, radix 16 after that.
+__host__ __device__ inline int n_passes(int lgM) { return (lgM + 3) / 4; }
+
+// The L = beta*M outputs of the zero-padded transform of the centred line x (M values in
+// LDS, x[n + M/2] = sample n): first(b, e) = x[n] w_L^(n b) feeds the first pass, out(b, k1, v)
+// receives X[beta*k1 + b]. buf0 and buf1 hold beta*M values each (buf1 only with three or
+// more passes; it may alias x, which is read by the first pass only).
+template <class Out>
+__device__ void oversampled_dft(const BuildArgs &a, const double2 *x, double2 *buf0, double2 *buf1, Out out) {
+    const int M = a.M, L = a.L, nsub = a.beta;
+    const double2 *tw = a.tw;
+    auto first = [&](int b, int e) {
+        const int n = e - ((e >= M / 2) ? M : 0);
+        return cmul(x[(e + M / 2) & (M - 1)], tw[(n * b) & (L - 1)]);
+    };
+    const int P = n_passes(a.lgM);
+    int ns = 1, rem = a.lgM;
+    double2 *src = nullptr, *dst = buf0;
+    for (int p = 0; p < P; ++p) {
+        const int bits = (p == 0 && (a.lgM & 3)) ? (a.lgM & 3) : 4;
+        const int R = 1 << bits;
+        rem -= bits;
+        const bool last = rem == 0;
+        auto lds_ld = [&](int b, int e) { return src[b * M + e]; };
+        auto lds_st = [&](int b, int e, double2 v) { dst[b * M + e] = v; };
+        if (p == 0 && last)
+            stockham_any(R, M, nsub, ns, L, tw, first, out);
+        else if (p == 0)
+            stockham_any(R, M, nsub, ns, L, tw, first, lds_st);
+        else if (last)
+            stockham_any(R, M, nsub, ns, L, tw, lds_ld, out);
+        else
+            stockham_any(R, M, nsub, ns, L, tw, lds_ld, lds_st);
+        __syncthreads();
+        ns <<= bits;
+        src = dst;
+        dst = (dst == buf0) ? buf1 : buf0;
+    }
+}
 
 __global__ void k_twiddle(double2 *tw, int L) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < L / 2) {
+    if (j < L) {
         double s, c;
         sincospi(-2.0 * (double)j / (double)L, &s, &c);
         tw[j] = make_double2(c, s);
@@ -189,21 +305,18 @@ __global__ void k_taper(BuildArgs a, TaperCoef tc) {
     if (p < a.M) a.tap[p] = taper(2.0 * (double)(p - a.M / 2) / (double)a.M, tc);
 }
 
-// Twiddles of an L-point transform into LDS (after the data block).
-__device__ inline double2 *load_twiddles(double2 *s, const BuildArgs &a) {
-    double2 *tw = s + a.L;
-    for (int j = threadIdx.x; j < a.L / 2; j += blockDim.x) tw[j] = a.tw[j];
-    return tw;
+// LDS of the row and column kernels: beta*M values of buf0, then max(M, beta*M when a
+// second exchange buffer is needed) values of the input line / buf1.
+inline size_t dft_lds_bytes(int M, int L, int lgM) {
+    return sizeof(double2) * (size_t)(L + (n_passes(lgM) >= 3 ? L : M));
 }
 
-// Row pass: image row q of plane k -> L-point FFT along u; stores the centred spectrum
-// column-major so the column pass reads contiguous values.
-__global__ void k_rows(BuildArgs a) {
-    extern __shared__ double2 s[];
+// Row pass: image row q of plane k -> L-point transform along u; stores the centred
+// spectrum column-major so the column pass reads contiguous values.
+__global__ __launch_bounds__(128) void k_rows(BuildArgs a) {
+    extern __shared__ double2 lds[];
+    double2 *buf0 = lds, *xin = lds + a.L;
     const int q = blockIdx.x, k = blockIdx.y;
-    double2 *tw = load_twiddles(s, a);
-    for (int i = threadIdx.x; i < a.L; i += blockDim.x) s[i] = make_double2(0.0, 0.0);
-    __syncthreads();
     const double xq = 2.0 * (double)(q - a.M / 2) / (double)a.M;
     const double m = xq / (2.0 * a.du);
     const double tq = a.tap[q];
@@ -222,16 +335,15 @@ __global__ void k_rows(BuildArgs a) {
             const double t2 = tq * tp;
             v = make_double2(t2 * cs, t2 * sn);
         }
-        const int pos = (p - a.M / 2 + a.L) & (a.L - 1);
-        s[bitrev(pos, a.lgL)] = v;
+        xin[p] = v;
     }
     __syncthreads();
-    fft_lds(s, a.L, tw);
-    double2 *out = a.A + (size_t)k * a.L * a.M;
-    for (int kk = threadIdx.x; kk < a.L; kk += blockDim.x) {
-        const int cu = (kk + a.L / 2) & (a.L - 1);
-        out[(size_t)cu * a.M + q] = s[kk];
-    }
+    double2 *col = a.A + (size_t)k * a.L * a.M + q;
+    const int L = a.L, M = a.M, beta = a.beta;
+    oversampled_dft(a, xin, buf0, xin, [&](int b, int k1, double2 v) {
+        const int cu = (k1 * beta + b + L / 2) & (L - 1);
+        col[(size_t)cu * M] = v;
+    });
 }
 
 __global__ void k_c00_and_reset(BuildArgs a, double *wbound) {
@@ -258,36 +370,28 @@ __global__ void k_c00_and_reset(BuildArgs a, double *wbound) {
     if (threadIdx.x == 0) *a.c00 = red[0];
 }
 
-// Column pass for column cu of plane k: FFT along v, normalise, support search over the
-// whole plane, and keep the central window the matrices are cut from.
-__global__ void k_cols(BuildArgs a) {
-    extern __shared__ double2 s[];
-    __shared__ int red[256];
+// Column pass for column cu of plane k: transform along v, normalise, support search over
+// the whole plane, and keep the central window the matrices are cut from.
+__global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
+    extern __shared__ double2 lds[];
+    __shared__ int red[128];
+    double2 *buf0 = lds, *xin = lds + a.L;
     const int cu = blockIdx.x, k = blockIdx.y;
-    double2 *tw = load_twiddles(s, a);
-    for (int i = threadIdx.x; i < a.L; i += blockDim.x) s[i] = make_double2(0.0, 0.0);
-    __syncthreads();
     const double2 *in = a.A + ((size_t)k * a.L + cu) * a.M;
-    for (int q = threadIdx.x; q < a.M; q += blockDim.x) {
-        const int pos = (q - a.M / 2 + a.L) & (a.L - 1);
-        s[bitrev(pos, a.lgL)] = in[q];
-    }
+    for (int q = threadIdx.x; q < a.M; q += blockDim.x) xin[q] = in[q];
     __syncthreads();
-    fft_lds(s, a.L, tw);
     const double c00 = *a.c00;
     const int fu = cu - a.L / 2;
     const bool keep_u = fu >= -a.Wf && fu <= a.Wf;
+    const int L = a.L, beta = a.beta, Wf = a.Wf, W = a.W;
+    double2 *win = a.win + (size_t)k * W * W + (fu + Wf);
     int dmax = 0;
-    for (int kk = threadIdx.x; kk < a.L; kk += blockDim.x) {
-        const int fv = ((kk + a.L / 2) & (a.L - 1)) - a.L / 2;
-        const double2 v = make_double2(s[kk].x / c00, s[kk].y / c00);
-        if (hypot(v.x, v.y) > kThreshold) {
-            const int d = max(abs(fu), abs(fv));
-            dmax = max(dmax, d);
-        }
-        if (keep_u && fv >= -a.Wf && fv <= a.Wf)
-            a.win[((size_t)k * a.W + (fv + a.Wf)) * a.W + (fu + a.Wf)] = v;
-    }
+    oversampled_dft(a, xin, buf0, xin, [&](int b, int k1, double2 s) {
+        const int fv = ((k1 * beta + b + L / 2) & (L - 1)) - L / 2;
+        const double2 v = make_double2(s.x / c00, s.y / c00);
+        if (hypot(v.x, v.y) > kThreshold) dmax = max(dmax, max(abs(fu), abs(fv)));
+        if (keep_u && fv >= -Wf && fv <= Wf) win[(size_t)(fv + Wf) * W] = v;
+    });
     red[threadIdx.x] = dmax;
     __syncthreads();
     for (int d = blockDim.x / 2; d > 0; d >>= 1) {
@@ -394,7 +498,7 @@ WsLayout ws_layout(const wg_geom *g) {
     w.W = 2 * w.Wf + 1;
     size_t o = 0;
     w.tw = o;
-    o = align256(o + sizeof(double2) * (w.L / 2));
+    o = align256(o + sizeof(double2) * w.L);
     w.A = o;
     o = align256(o + sizeof(double2) * (size_t)g->n_w * w.L * g->m_img);
     w.win = o;
@@ -441,8 +545,8 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
     BuildArgs a;
     a.M = g->m_img;
     a.L = lay.L;
-    a.lgL = 0;
-    while ((1 << a.lgL) < a.L) ++a.lgL;
+    a.lgM = 0;
+    while ((1 << a.lgM) < a.M) ++a.lgM;
     a.beta = g->beta;
     a.n_w = g->n_w;
     a.Wf = lay.Wf;
@@ -457,12 +561,12 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
     a.kmax = (int *)(base + lay.kmax);
     a.tap = (double *)(base + lay.tap);
 
-    const size_t lds = sizeof(double2) * (a.L + a.L / 2);  // data + twiddles
-    hipLaunchKernelGGL(k_twiddle, dim3((a.L / 2 + 255) / 256), dim3(256), 0, s, (double2 *)a.tw, a.L);
+    const size_t lds = dft_lds_bytes(a.M, a.L, a.lgM);
+    hipLaunchKernelGGL(k_twiddle, dim3((a.L + 255) / 256), dim3(256), 0, s, (double2 *)a.tw, a.L);
     hipLaunchKernelGGL(k_taper, dim3((a.M + 255) / 256), dim3(256), 0, s, a, tc);
-    hipLaunchKernelGGL(k_rows, dim3(a.M, a.n_w), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_rows, dim3(a.M, a.n_w), dim3(128), lds, s, a);
     hipLaunchKernelGGL(k_c00_and_reset, dim3(1), dim3(256), 0, s, a, kt->wbound);
-    hipLaunchKernelGGL(k_cols, dim3(a.L, a.n_w), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_cols, dim3(a.L, a.n_w), dim3(128), lds, s, a);
     hipLaunchKernelGGL(k_supports, dim3(1), dim3(64), 0, s, a, g->s_lo, g->s_hi, kt->support, kt->offset);
     if (hipGetLastError() != hipSuccess) return WG_EHIP;
 
