@@ -199,7 +199,8 @@ struct Stage {
 };
 
 // Persistent walk over the support-sorted work list (largest supports first): wave w takes
-// units w, w + W, ... where W is the number of waves in the launch.
+// units w, w + W, ... where W is the number of waves in the launch, so the units in flight
+// are spread over the whole list (many baselines at once, few shared grid cells).
 template <typename F>
 __device__ inline void for_each_unit(int nunits, F &&body) {
     const int wpb = blockDim.x / kWave;
@@ -226,11 +227,15 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
     int cur[kSlots];  // owned cell (y*n + x); set from the chunk's first run
 #pragma unroll
     for (int m = 0; m < NS; ++m) acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
+    // Commit the cell's compensated sum (acc - cmp); the next cell starts from acc = cmp,
+    // i.e. from the value zero, with the compensation term left as it is (Kahan's recurrence
+    // holds from any starting pair).
     auto commit = [&](int m) {
-        float *cell = a.grid + 2 * (int64_t)cur[m];
+        float *cell = a.grid + 2 * (int64_t)(unsigned)cur[m];
         unsafeAtomicAdd(cell, acc_r[m] - cmp_r[m]);
         unsafeAtomicAdd(cell + 1, acc_i[m] - cmp_i[m]);
-        acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
+        acc_r[m] = cmp_r[m];
+        acc_i[m] = cmp_i[m];
     };
     bool first = true;
 
@@ -365,10 +370,17 @@ __device__ inline float wave_total(float v) {
 template <int DT>
 struct DStage {
     typename KRaw<DT>::type k[kSlots];
-    int yc[kSlots];
     float2 g[kSlots];
-    unsigned ld;  // bit m: g[m] holds a newly loaded cell value
+    bool ld[kSlots];  // g[m] holds a newly loaded cell value (a lane mask per slot)
 };
+
+// A wave-uniform value held in a VGPR, so that an instruction taking it together with a
+// per-run scalar needs only one scalar operand.
+__device__ inline unsigned in_vgpr(unsigned x) {
+    unsigned r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
 
 template <int DT, int NS>
 __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
@@ -381,8 +393,8 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
     lane_classes<NS>(S, c0, c1, lane, cls);
     const bool last_ok = c0 + (nslots - 1) * kWave + lane < c1;
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
-    const u16x2 mul_k = {(unsigned short)esz, (unsigned short)(S * esz)};
-    const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};
+    const u16x2 mul_k = as_u16x2(in_vgpr((unsigned)(S * esz) << 16 | (unsigned)esz));
+    const u16x2 mul_c = as_u16x2(in_vgpr((unsigned)a.n << 16 | 1u));
     int pyc[kSlots];      // cells of the most recently fetched run
     float2 gv[kSlots];    // grid values of the owned cells
 #pragma unroll
@@ -399,17 +411,13 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
             const u16x2 ph = as_u16x2((unsigned)rl(b.ph, t));
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
-            st.ld = 0;
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 const u16x2 w = footprint_pos(cls[m], ph, ss);
                 const int yc = (int)dot2(w, mul_c, cell0);
-                st.yc[m] = yc;
                 st.k[m] = buf_load<DT>(rs, (int)dot2(w, mul_k, kbB));
-                if (yc != pyc[m]) {
-                    st.ld |= 1u << m;
-                    st.g[m] = grid[yc];
-                }
+                st.ld[m] = yc != pyc[m];
+                if (st.ld[m]) st.g[m] = grid[(unsigned)yc];
                 pyc[m] = yc;
             }
         };
@@ -418,7 +426,7 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 if (m < nslots) {
-                    if ((st.ld >> m) & 1u) gv[m] = st.g[m];
+                    if (st.ld[m]) gv[m] = st.g[m];
                     if (m < nslots - 1 || last_ok) {
                         const float2 kv = to_float2<DT>(st.k[m]);
                         pr = fmaf(kv.x, gv[m].x, fmaf(kv.y, gv[m].y, pr));

@@ -254,9 +254,9 @@ __device__ inline void stockham_any(int R, int M, int nsub, int ns, int L, const
 __host__ __device__ inline int n_passes(int lgM) { return (lgM + 3) / 4; }
 
 // The L = beta*M outputs of the zero-padded transform of the centred line x (M values in
-// LDS, x[n + M/2] = sample n): first(b, e) = x[n] w_L^(n b) feeds the first pass, out(b, k1, v)
-// receives X[beta*k1 + b]. buf0 and buf1 hold beta*M values each (buf1 only with three or
-// more passes; it may alias x, which is read by the first pass only).
+// LDS or global memory, x[n + M/2] = sample n): first(b, e) = x[n] w_L^(n b) feeds the first
+// pass, out(b, k1, v) receives X[beta*k1 + b]. buf0 and buf1 hold beta*M values each in LDS
+// (buf1 only with three or more passes; it may alias x, which the first pass alone reads).
 template <class Out>
 __device__ void oversampled_dft(const BuildArgs &a, const double2 *x, double2 *buf0, double2 *buf1, Out out) {
     const int M = a.M, L = a.L, nsub = a.beta;
@@ -372,6 +372,10 @@ __global__ void k_c00_and_reset(BuildArgs a, double *wbound) {
 
 // Column pass for column cu of plane k: transform along v, normalise, support search over
 // the whole plane, and keep the central window the matrices are cut from.
+//
+// The support test |C/c00| > 1e-3 is decided on |C|^2 against (1e-3 c00)^2 wherever the two
+// differ by more than a relative 1e-9 (far beyond the rounding of either side); only values
+// closer than that take the exact quotient and hypot, so every decision equals the exact one.
 __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     extern __shared__ double2 lds[];
     __shared__ int red[128];
@@ -381,6 +385,8 @@ __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     for (int q = threadIdx.x; q < a.M; q += blockDim.x) xin[q] = in[q];
     __syncthreads();
     const double c00 = *a.c00;
+    const double t2 = (kThreshold * c00) * (kThreshold * c00);
+    const double t2_hi = t2 * (1.0 + 1e-9), t2_lo = t2 * (1.0 - 1e-9);
     const int fu = cu - a.L / 2;
     const bool keep_u = fu >= -a.Wf && fu <= a.Wf;
     const int L = a.L, beta = a.beta, Wf = a.Wf, W = a.W;
@@ -388,9 +394,11 @@ __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     int dmax = 0;
     oversampled_dft(a, xin, buf0, xin, [&](int b, int k1, double2 s) {
         const int fv = ((k1 * beta + b + L / 2) & (L - 1)) - L / 2;
-        const double2 v = make_double2(s.x / c00, s.y / c00);
-        if (hypot(v.x, v.y) > kThreshold) dmax = max(dmax, max(abs(fu), abs(fv)));
-        if (keep_u && fv >= -Wf && fv <= Wf) win[(size_t)(fv + Wf) * W] = v;
+        const double r2 = s.x * s.x + s.y * s.y;
+        bool above = r2 > t2_hi;
+        if (!above && r2 >= t2_lo) above = hypot(s.x / c00, s.y / c00) > kThreshold;
+        if (above) dmax = max(dmax, max(abs(fu), abs(fv)));
+        if (keep_u && fv >= -Wf && fv <= Wf) win[(size_t)(fv + Wf) * W] = make_double2(s.x / c00, s.y / c00);
     });
     red[threadIdx.x] = dmax;
     __syncthreads();
