@@ -7,6 +7,8 @@ shares no code with it.
 * `ktable.build`            -- Convolution Function Generator (numpy FFT, scipy PSWF).
 * `compress`, `index`       -- WImager preparation phase, plain C (wgrid_oracle.c).
 * `grid`, `degrid`          -- eq. gridding and its adjoint, plain C.
+* `image.finalise`          -- Algorithm finalizer (inverse FFT, normaliser, taper and
+                               oversampling corrections), numpy.
 
 Parity unpinned: none of the functions here; every one is pinned by the tests listed in
 the design notes (closed forms, invariants, brute force on tiny inputs).
