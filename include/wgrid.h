@@ -242,6 +242,27 @@ int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const 
               const float *grid, const double *uvw, const float *weight, int64_t nb, int32_t nc,
               int32_t nt, float *vis_out, wg_stream_t stream);
 
+/*
+ * Image finaliser (Algorithm finalizer), one polarisation: inverse 2-D FFT of the grid, real
+ * part over the normaliser N_p (eq. normalizer; read on the device from stats->normaliser),
+ * divided by the prolate taper psi_0(3 pi, 2 l du) normalised to 1 at the centre (sec.
+ * convgriddingmath) and by sinc(pi l du / beta) sinc(pi m du / beta) (eq. coversampled).
+ * Image pixel [q][p] holds (l, m) = ((p - n/2), (q - n/2)) / (n du); the real part is taken
+ * because each record is gridded once, at its w >= 0 representative (eq. conj). Pixels where
+ * the taper is zero (first row and column) are 0; the whole image is 0 when the normaliser
+ * is 0. FFTs in FP32.
+ *   grid   complex64 [n][n] (device, read only)
+ *   stats  device wg_stats (from wg_compress)
+ *   image  float32 [n][n] (device, OVERWRITTEN)
+ *   ws     device workspace of wg_finalise_ws_bytes bytes (two n x n complex64 buffers,
+ *          twiddles, corrections)
+ * n must be a power of two, 16..8192 (one FP32 complex row in 64 KB of LDS).
+ * Errors: WG_EINVAL, WG_ECAPACITY (ws too small), WG_EUNSUPPORTED (n), WG_EHIP.
+ */
+int wg_finalise_ws_bytes(const wg_geom *g, size_t *ws_bytes);
+int wg_finalise(const wg_geom *g, const float *grid, const wg_stats *stats, float *image, void *ws,
+                size_t ws_bytes, wg_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,9 @@ Algorithm finalizer, one polarisation:
 4. division by sinc(pi l du / beta) sinc(pi m du / beta), the attenuation by the nearest
    oversampled kernel sample (eq. coversampled).
 
-Pixels where the taper is zero (l or m = -FOV/2, the first row and column) are set to 0.
+Pixels where the taper is zero (l or m = -FOV/2, the first row and column) are set to 0, and
+so is the whole image when the normaliser is 0 (nothing was gridded; the thesis leaves this
+case open).
 """
 from __future__ import annotations
 
@@ -34,6 +36,8 @@ def axis_correction(geom: dict) -> np.ndarray:
 def finalise(geom: dict, grid: np.ndarray, normaliser: float) -> np.ndarray:
     """Dirty image, float64 [N][N] (row m, column l), from a complex [N][N] grid."""
     n = geom["n"]
+    if normaliser == 0.0:
+        return np.zeros((n, n))
     g = np.asarray(grid, dtype=np.complex128)
     img = np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(g))) * float(n * n)
     c = axis_correction(geom)

@@ -1,0 +1,262 @@
+// Image finaliser (Algorithm finalizer), one polarisation, on gfx950.
+//
+//   1. inverse 2-D FFT of the UV-grid: img[q][p] = sum_cells G[y][x] e^{+2 pi i ((x - N/2)(p - N/2)
+//      + (y - N/2)(q - N/2)) / N}, so pixel [q][p] holds (l, m) = ((p - N/2), (q - N/2)) / (N du);
+//   2. real part (each record is gridded once, at its w >= 0 representative of eq. conj) over
+//      the normaliser N_p of eq. normalizer, giving Jy/beam;
+//   3. division by the taper c(l) c(m) of sec. convgriddingmath (psi_0(3 pi, 2 l du)),
+//      normalised to 1 at the centre;
+//   4. division by sinc(pi l du / beta) sinc(pi m du / beta) (eq. coversampled).
+// Pixels where the taper is zero (the first row and column, l or m = -FOV/2) are 0, and the
+// whole image is 0 when the normaliser is 0 (nothing was gridded).
+//
+// Layout of the work: row transforms (one workgroup per row, an N-point FP32 Stockham FFT in
+// LDS with radix-16 passes in registers), a tiled transpose, row transforms again, and a
+// tiled transposing pass that applies steps 2-4 while writing the image row-major. The
+// ifftshift of the input and the fftshift of the output are index XORs with N/2.
+#include <math.h>
+
+#include "prolate.hpp"
+#include "wg_common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace wg {
+namespace {
+
+constexpr int kMaxImageN = 8192;  // one row of FP32 complex values in 64 KB of LDS
+
+__device__ inline float2 fmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 faddc(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 fsubc(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// exp(+2 pi i j / 16), j < 8
+constexpr float kC1 = 0.92387953251128675613f;  // cos(pi/8)
+constexpr float kS1 = 0.38268343236508977173f;  // sin(pi/8)
+constexpr float kH = 0.70710678118654752440f;
+
+__device__ inline float2 rot16_inv(float2 d, int j) {
+    switch (j) {
+    case 0: return d;
+    case 1: return fmulc(d, make_float2(kC1, kS1));
+    case 2: return fmulc(d, make_float2(kH, kH));
+    case 3: return fmulc(d, make_float2(kS1, kC1));
+    case 4: return make_float2(-d.y, d.x);
+    case 5: return fmulc(d, make_float2(-kS1, kC1));
+    case 6: return fmulc(d, make_float2(-kH, kH));
+    default: return fmulc(d, make_float2(-kC1, kS1));
+    }
+}
+
+constexpr int bitrev_i(int k, int bits) {
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((k >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+
+// Inverse DFT (e^{+2 pi i}) of R <= 16 points starting at v[o], natural order in and out.
+template <int R>
+__device__ inline void idft_reg(float2 *v) {
+    constexpr int bits = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+#pragma unroll
+    for (int h = R / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int s0 = 0; s0 < R; s0 += 2 * h) {
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+                const float2 x = v[s0 + i], y = v[s0 + i + h];
+                v[s0 + i] = faddc(x, y);
+                v[s0 + i + h] = rot16_inv(fsubc(x, y), i * (16 / (2 * h)));
+            }
+        }
+    }
+    float2 t[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) t[k] = v[bitrev_i(k, bits)];
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = t[k];
+}
+
+// One radix-R pass of an N-point inverse Stockham FFT for the lane's 16 values: 16/R
+// butterflies j = t + b*T (T = N/16 active threads). Butterfly j reads elements j + r*N/R
+// (times exp(+2 pi i (j mod ns) r / (ns R))) and writes element r to (j - j mod ns) R +
+// (j mod ns) + r ns. The pass reads from `in` (global, shifted) when first, else from LDS,
+// and writes to `out` (global, shifted) when last, else back to LDS.
+template <int R>
+__device__ inline void ifft_pass(float2 *buf, const float2 *in, float2 *out, int n, int ns, bool first,
+                                 bool last, bool active, const float2 *tw) {
+    const int T = n >> 4, t = threadIdx.x, nb = n / R, half = n >> 1;
+    float2 v[16];
+    if (active) {
+#pragma unroll
+        for (int b = 0; b < 16 / R; ++b) {
+            const int j = t + b * T, jm = j & (ns - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = j + r * nb;
+                float2 x = first ? in[e ^ half] : buf[e];
+                if (r > 0 && ns > 1) x = fmulc(x, tw[jm * r * (n / (ns * R))]);
+                v[b * R + r] = x;
+            }
+            idft_reg<R>(v + b * R);
+        }
+    }
+    if (!first) __syncthreads();  // every read of buf precedes the writes below
+    if (active) {
+#pragma unroll
+        for (int b = 0; b < 16 / R; ++b) {
+            const int j = t + b * T, jm = j & (ns - 1);
+            const int d0 = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = d0 + r * ns;
+                if (last)
+                    out[e ^ half] = v[b * R + r];
+                else
+                    buf[e] = v[b * R + r];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Rows of src (N x N, complex) -> inverse transforms in dst; ifftshift on input and
+// fftshift on output. blockDim >= N/16.
+__global__ __launch_bounds__(512) void k_ifft_rows(const float2 *__restrict__ src, float2 *__restrict__ dst,
+                                                   int n, int lg, const float2 *__restrict__ tw) {
+    extern __shared__ float2 buf[];
+    const float2 *in = src + (size_t)blockIdx.x * n;
+    float2 *out = dst + (size_t)blockIdx.x * n;
+    const bool active = (int)threadIdx.x < (n >> 4);
+    const int P = (lg + 3) >> 2;
+    int ns = 1, rem = lg;
+    for (int p = 0; p < P; ++p) {
+        const int bits = (p == 0 && (lg & 3)) ? (lg & 3) : 4;
+        rem -= bits;
+        const bool first = p == 0, last = rem == 0;
+        switch (bits) {
+        case 1: ifft_pass<2>(buf, in, out, n, ns, first, last, active, tw); break;
+        case 2: ifft_pass<4>(buf, in, out, n, ns, first, last, active, tw); break;
+        case 3: ifft_pass<8>(buf, in, out, n, ns, first, last, active, tw); break;
+        default: ifft_pass<16>(buf, in, out, n, ns, first, last, active, tw); break;
+        }
+        ns <<= bits;
+    }
+}
+
+// dst[c][r] = src[r][c] for an N x N complex matrix, 32 x 32 tiles through LDS.
+__global__ void k_transpose(const float2 *__restrict__ src, float2 *__restrict__ dst, int n) {
+    __shared__ float2 tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    for (int i = threadIdx.y; i < 32; i += blockDim.y) {
+        const int r = by + i, c = bx + threadIdx.x;
+        if (r < n && c < n) tile[i][threadIdx.x] = src[(size_t)r * n + c];
+    }
+    __syncthreads();
+    for (int i = threadIdx.y; i < 32; i += blockDim.y) {
+        const int r = bx + i, c = by + threadIdx.x;
+        if (r < n && c < n) dst[(size_t)r * n + c] = tile[threadIdx.x][i];
+    }
+}
+
+// Twiddles exp(+2 pi i j / N), j < N, and the per-axis correction
+// corr[p] = taper(2 (p - N/2) / N) / taper(0) * sinc(pi (p - N/2) / (N beta)).
+__global__ void k_fin_setup(float2 *tw, double *corr, int n, int beta, TaperCoef tc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s, c;
+    sincospi(2.0 * (double)j / (double)n, &s, &c);
+    tw[j] = make_float2((float)c, (float)s);
+    const double x = 2.0 * (double)(j - n / 2) / (double)n;
+    const double y = (double)(j - n / 2) / ((double)n * (double)beta);
+    const double sinc = (j == n / 2) ? 1.0 : sinpi(y) / (M_PI * y);
+    corr[j] = taper(x, tc) / taper(0.0, tc) * sinc;
+}
+
+// image[q][p] = Re(T[p][q]) / (normaliser * corr[q] * corr[p]) (0 where the product is 0 or
+// the normaliser is 0), T the twice-transformed, transposed grid; 32 x 32 tiles.
+__global__ void k_fin_out(const float2 *__restrict__ T, const double *__restrict__ corr,
+                          const wg_stats *__restrict__ stats, float *__restrict__ image, int n) {
+    __shared__ float tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    for (int i = threadIdx.y; i < 32; i += blockDim.y) {
+        const int r = by + i, c = bx + threadIdx.x;  // T row r = l index p, column c = m index q
+        if (r < n && c < n) tile[i][threadIdx.x] = T[(size_t)r * n + c].x;
+    }
+    __syncthreads();
+    const double norm = stats->normaliser;
+    for (int i = threadIdx.y; i < 32; i += blockDim.y) {
+        const int q = bx + i, p = by + threadIdx.x;
+        if (q < n && p < n) {
+            const double d = norm * corr[q] * corr[p];
+            image[(size_t)q * n + p] = d != 0.0 ? (float)((double)tile[threadIdx.x][i] / d) : 0.0f;
+        }
+    }
+}
+
+struct FinLayout {
+    size_t a, b, tw, corr, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+FinLayout fin_layout(int n) {
+    FinLayout l;
+    const size_t nn = (size_t)n * n;
+    l.a = 0;
+    l.b = align256(l.a + sizeof(float2) * nn);
+    l.tw = align256(l.b + sizeof(float2) * nn);
+    l.corr = align256(l.tw + sizeof(float2) * n);
+    l.total = align256(l.corr + sizeof(double) * n);
+    return l;
+}
+
+int image_lg(int n) {
+    if (n < 16 || n > kMaxImageN || (n & (n - 1))) return -1;
+    int lg = 0;
+    while ((1 << lg) < n) ++lg;
+    return lg;
+}
+
+}  // namespace
+}  // namespace wg
+
+extern "C" int wg_finalise_ws_bytes(const wg_geom *g, size_t *ws_bytes) {
+    using namespace wg;
+    const int st = check_geom(g);
+    if (st != WG_OK) return st;
+    if (!ws_bytes) return WG_EINVAL;
+    if (image_lg(g->n) < 0) return WG_EUNSUPPORTED;
+    *ws_bytes = fin_layout(g->n).total;
+    return WG_OK;
+}
+
+extern "C" int wg_finalise(const wg_geom *g, const float *grid, const wg_stats *stats, float *image, void *ws,
+                           size_t ws_bytes, wg_stream_t stream) {
+    using namespace wg;
+    const int st = check_geom(g);
+    if (st != WG_OK) return st;
+    if (!grid || !stats || !image || !ws) return WG_EINVAL;
+    const int n = g->n, lg = image_lg(n);
+    if (lg < 0) return WG_EUNSUPPORTED;
+    const FinLayout lay = fin_layout(n);
+    if (ws_bytes < lay.total) return WG_ECAPACITY;
+    char *base = (char *)ws;
+    float2 *A = (float2 *)(base + lay.a), *B = (float2 *)(base + lay.b), *tw = (float2 *)(base + lay.tw);
+    double *corr = (double *)(base + lay.corr);
+    hipStream_t s = (hipStream_t)stream;
+
+    TaperCoef tc;
+    prolate_coefficients(kTaperC, &tc);
+    const int threads = n / 16 > 64 ? n / 16 : 64;
+    const size_t lds = sizeof(float2) * (size_t)n;
+    const dim3 tiles((n + 31) / 32, (n + 31) / 32), tb(32, 8);
+    hipLaunchKernelGGL(k_fin_setup, dim3((n + 255) / 256), dim3(256), 0, s, tw, corr, n, g->beta, tc);
+    hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, (const float2 *)grid, A, n, lg, tw);
+    hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
+    hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw);
+    hipLaunchKernelGGL(k_fin_out, tiles, tb, 0, s, A, corr, stats, image, n);
+    return launch_status();
+}

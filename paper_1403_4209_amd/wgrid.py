@@ -80,6 +80,10 @@ def lib():
         L.wg_grid.argtypes = [P, P, P, P, P, P]
         L.wg_degrid.restype = ctypes.c_int
         L.wg_degrid.argtypes = [P, P, P, P, P, P, P, I64, I32, I32, P, P]
+        L.wg_finalise_ws_bytes.restype = ctypes.c_int
+        L.wg_finalise_ws_bytes.argtypes = [P, P]
+        L.wg_finalise.restype = ctypes.c_int
+        L.wg_finalise.argtypes = [P, P, P, P, P, ctypes.c_size_t, P]
         _lib = L
     return _lib
 
@@ -149,6 +153,29 @@ def wg_grid(geom, kt, runs: WgRuns, stats: torch.Tensor, grid: torch.Tensor, str
 def wg_degrid(geom, kt, runs: WgRuns, stats, grid, uvw, weight, nb, nc, nt, vis_out, stream=None):
     _check(lib().wg_degrid(ctypes.byref(geom), ctypes.byref(kt), ctypes.byref(runs), _p(stats), _p(grid), _p(uvw),
                            _p(weight), int(nb), int(nc), int(nt), _p(vis_out), _stream(stream)), "wg_degrid")
+
+
+def wg_finalise_ws_bytes(geom: WgGeom) -> int:
+    ws = ctypes.c_size_t(0)
+    _check(lib().wg_finalise_ws_bytes(ctypes.byref(geom), ctypes.byref(ws)), "wg_finalise_ws_bytes")
+    return int(ws.value)
+
+
+def wg_finalise(geom: WgGeom, grid: torch.Tensor, stats: torch.Tensor, image: torch.Tensor, ws: torch.Tensor,
+                stream=None):
+    _check(lib().wg_finalise(ctypes.byref(geom), _p(grid), _p(stats), _p(image), _p(ws), ws.numel() * ws.element_size(),
+                             _stream(stream)), "wg_finalise")
+
+
+def finalise(geom: WgGeom, grid: torch.Tensor, stats: torch.Tensor, out=None, ws=None, stream=None) -> torch.Tensor:
+    """Dirty image float32 [n][n] from a complex64 [n][n] grid and device statistics."""
+    n = geom.n
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float32, device=grid.device)
+    if ws is None:
+        ws = torch.empty(wg_finalise_ws_bytes(geom), dtype=torch.uint8, device=grid.device)
+    wg_finalise(geom, torch.view_as_real(grid.contiguous()), stats, out, ws, stream)
+    return out
 
 
 # -------------------------------------------------------------------------- owning helpers
@@ -271,6 +298,11 @@ class Gridder:
         wg_degrid(self.geom, self.table.kt, self.runs.c, self.runs.stats_d, torch.view_as_real(grid.contiguous()),
                   self.uvw, self.weight, self.nb, self.nc, self.nt, torch.view_as_real(out), stream)
         return out
+
+
+    def finalise(self, grid, out=None, stream=None):
+        """Dirty image of `grid` with this batch's normaliser (wg_finalise)."""
+        return finalise(self.geom, grid, self.runs.stats_d, out=out, stream=stream)
 
 
 class GridFn(torch.autograd.Function):

@@ -26,7 +26,7 @@ def wg():
 def test_header_declares_entry_points():
     names = declared_functions()
     for n in ["wg_status_str", "wg_version", "wg_ktable_sizes", "wg_ktable_build", "wg_plan_elems",
-              "wg_compress", "wg_grid", "wg_degrid"]:
+              "wg_compress", "wg_grid", "wg_degrid", "wg_finalise_ws_bytes", "wg_finalise"]:
         assert n in names
 
 
@@ -92,3 +92,23 @@ def test_entry_points_reject_null_arguments(wg):
     kt_small = wg.WgKtable(0, 8, 8, 0, 1, 1, 1, 1, 1, 10)
     assert L.wg_ktable_build(by(g), by(kt_small), 1, 10, None, None, None) == wg.WG_ECAPACITY
     assert L.wg_plan_elems(-1, 1) == -1
+
+
+def test_finaliser_sizes_and_rejections(wg):
+    """wg_finalise needs n a power of two in 16..8192 and two n x n complex64 buffers of
+    workspace; every invalid call returns before any launch."""
+    L = wg.lib()
+    by = ctypes.byref
+    g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)
+    ws = wg.wg_finalise_ws_bytes(g)
+    assert ws >= 2 * 256 * 256 * 8
+    g_odd = wg.make_geom(96, 8, 8, 7, 7, 64, 15.0, 100.0)      # valid geometry, not a power of two
+    with pytest.raises(wg.WgError):
+        wg.wg_finalise_ws_bytes(g_odd)
+    size = ctypes.c_size_t(0)
+    assert L.wg_finalise_ws_bytes(by(g_odd), by(size)) == wg.WG_EUNSUPPORTED
+    assert L.wg_finalise_ws_bytes(by(g), None) == wg.WG_EINVAL
+    assert L.wg_finalise(by(g), None, 1, 1, 1, ws, None) == wg.WG_EINVAL
+    assert L.wg_finalise(by(g), 1, None, 1, 1, ws, None) == wg.WG_EINVAL
+    assert L.wg_finalise(by(g), 1, 1, 1, 1, ws - 1, None) == wg.WG_ECAPACITY
+    assert L.wg_finalise(by(g_odd), 1, 1, 1, 1, ws, None) == wg.WG_EUNSUPPORTED
