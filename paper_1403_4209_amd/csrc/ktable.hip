@@ -202,10 +202,16 @@ inline size_t dft_lds_bytes(int M, int L, int lgM) {
 
 // Row pass: image row q of plane k -> L-point transform along u; stores the centred
 // spectrum column-major so the column pass reads contiguous values.
+//
+// The image-plane function is even in l and in m on the sample grid, bit for bit: the taper
+// is a series of even Legendre polynomials, the w-screen depends on l^2 and m^2, and the one
+// unpaired sample (x = -1) has taper 0. So row M - q equals row q, row 0 is zero, and each row
+// transform is even in u. Only rows q >= M/2 are transformed (each stored also as row M - q)
+// and only the columns the column pass reads (u >= 0 and the Nyquist column -L/2) are stored.
 __global__ __launch_bounds__(128) void k_rows(BuildArgs a) {
     extern __shared__ double2 lds[];
     double2 *buf0 = lds, *xin = lds + a.L;
-    const int q = blockIdx.x, k = blockIdx.y;
+    const int q = a.M / 2 + (int)blockIdx.x, k = blockIdx.y;
     const double xq = 2.0 * (double)(q - a.M / 2) / (double)a.M;
     const double m = xq / (2.0 * a.du);
     const double tq = a.tap[q];
@@ -227,11 +233,17 @@ __global__ __launch_bounds__(128) void k_rows(BuildArgs a) {
         xin[p] = v;
     }
     __syncthreads();
-    double2 *col = a.A + (size_t)k * a.L * a.M + q;
+    double2 *plane = a.A + (size_t)k * a.L * a.M;
     const int L = a.L, M = a.M, beta = a.beta;
     oversampled_dft(a, xin, buf0, xin, [&](int b, int k1, double2 v) {
         const int cu = (k1 * beta + b + L / 2) & (L - 1);
-        col[(size_t)cu * M] = v;
+        if (cu != 0 && cu < L / 2) return;  // u < 0: the column pass uses the mirror column
+        double2 *col = plane + (size_t)cu * M;
+        col[q] = v;
+        if (q > M / 2)
+            col[M - q] = v;
+        else
+            col[0] = make_double2(0.0, 0.0);  // row 0 (taper zero), written once per column
     });
 }
 
@@ -260,7 +272,9 @@ __global__ void k_c00_and_reset(BuildArgs a, double *wbound) {
 }
 
 // Column pass for column cu of plane k: transform along v, normalise, support search over
-// the whole plane, and keep the central window the matrices are cut from.
+// the whole plane, and keep the central window the matrices are cut from. The plane is even
+// in u (see the row pass): columns u >= 0 and the Nyquist column -L/2 are transformed, and
+// each window column u > 0 is stored also as column -u.
 //
 // The support test |C/c00| > 1e-3 is decided on |C|^2 against (1e-3 c00)^2 wherever the two
 // differ by more than a relative 1e-9 (far beyond the rounding of either side); only values
@@ -269,7 +283,8 @@ __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     extern __shared__ double2 lds[];
     __shared__ int red[128];
     double2 *buf0 = lds, *xin = lds + a.L;
-    const int cu = blockIdx.x, k = blockIdx.y;
+    const int fu_b = (int)blockIdx.x == a.L / 2 ? -a.L / 2 : (int)blockIdx.x;
+    const int cu = fu_b + a.L / 2, k = blockIdx.y;
     const double2 *in = a.A + ((size_t)k * a.L + cu) * a.M;
     for (int q = threadIdx.x; q < a.M; q += blockDim.x) xin[q] = in[q];
     __syncthreads();
@@ -280,6 +295,7 @@ __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     const bool keep_u = fu >= -a.Wf && fu <= a.Wf;
     const int L = a.L, beta = a.beta, Wf = a.Wf, W = a.W;
     double2 *win = a.win + (size_t)k * W * W + (fu + Wf);
+    const int mirror = -2 * fu;  // column -fu relative to column fu
     int dmax = 0;
     oversampled_dft(a, xin, buf0, xin, [&](int b, int k1, double2 s) {
         const int fv = ((k1 * beta + b + L / 2) & (L - 1)) - L / 2;
@@ -287,7 +303,11 @@ __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
         bool above = r2 > t2_hi;
         if (!above && r2 >= t2_lo) above = hypot(s.x / c00, s.y / c00) > kThreshold;
         if (above) dmax = max(dmax, max(abs(fu), abs(fv)));
-        if (keep_u && fv >= -Wf && fv <= Wf) win[(size_t)(fv + Wf) * W] = make_double2(s.x / c00, s.y / c00);
+        if (keep_u && fv >= -Wf && fv <= Wf) {
+            const double2 v = make_double2(s.x / c00, s.y / c00);
+            win[(size_t)(fv + Wf) * W] = v;
+            if (fu > 0) win[(size_t)(fv + Wf) * W + mirror] = v;
+        }
     });
     red[threadIdx.x] = dmax;
     __syncthreads();
@@ -461,9 +481,9 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
     const size_t lds = dft_lds_bytes(a.M, a.L, a.lgM);
     hipLaunchKernelGGL(k_twiddle, dim3((a.L + 255) / 256), dim3(256), 0, s, (double2 *)a.tw, a.L);
     hipLaunchKernelGGL(k_taper, dim3((a.M + 255) / 256), dim3(256), 0, s, a, tc);
-    hipLaunchKernelGGL(k_rows, dim3(a.M, a.n_w), dim3(128), lds, s, a);
+    hipLaunchKernelGGL(k_rows, dim3(a.M / 2, a.n_w), dim3(128), lds, s, a);
     hipLaunchKernelGGL(k_c00_and_reset, dim3(1), dim3(256), 0, s, a, kt->wbound);
-    hipLaunchKernelGGL(k_cols, dim3(a.L, a.n_w), dim3(128), lds, s, a);
+    hipLaunchKernelGGL(k_cols, dim3(a.L / 2 + 1, a.n_w), dim3(128), lds, s, a);
     hipLaunchKernelGGL(k_supports, dim3(1), dim3(64), 0, s, a, g->s_lo, g->s_hi, kt->support, kt->offset);
     if (hipGetLastError() != hipSuccess) return WG_EHIP;
 
