@@ -73,17 +73,23 @@ def grid_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_counters():
-    """HBM bytes per gridder launch from the committed rocprofv3 counter summary, or None
-    when the gridder source has changed since the counters were taken."""
+def read_counters(kernel):
+    """HBM bytes per launch of `kernel` (k_grid or k_degrid) from the committed rocprofv3
+    counter summary, or None when their source has changed since the counters were taken."""
     try:
         with open(PROFILE_COUNTERS) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line)
         if kv["grid_hip_sha256_16"].strip() != grid_source_hash():
             return None
-        return float(kv["traffic_bytes_per_launch"].strip())
+        return float(kv[f"traffic_{kernel}"].strip())
     except Exception:
         return None
+
+
+def roofline(kernel, alg_bytes, ms, traffic):
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
 
 
 def cpu_baseline(w, vis_h, u_full):
@@ -167,11 +173,14 @@ def main():
     t_ktable, t_comp, t_zero, t_grid, t_degrid = phase
     value = 2.0 * U / (ms_step * 1e-3) / 1e9
 
-    # gridder roofline: algorithmic bytes per launch = table samples streamed (8 B each for
-    # FP32) + run records read (20 B) + the grid read and written once (16 B per cell)
-    alg_bytes = U * 8 + st.n_runs * 20 + 16 * geom.n * geom.n
-    achieved = alg_bytes / (t_grid * 1e-3) / 1e9
-    traffic = read_counters()
+    # rooflines: algorithmic bytes per launch = table samples streamed (8 B each for FP32) +
+    # run fields read or partial sums written (20 B per run) + the grid read and written once
+    # (gridder, 16 B per cell) or read once (degridder, 8 B per cell). The dominant (slower)
+    # kernel of the step is reported as `roofline`, the other as `roofline_other`.
+    nn = geom.n * geom.n
+    rl_grid = roofline("k_grid (wg_grid)", U * 8 + st.n_runs * 20 + 16 * nn, t_grid, read_counters("k_grid"))
+    rl_degrid = roofline("k_degrid (wg_degrid)", U * 8 + st.n_runs * 20 + 8 * nn, t_degrid, read_counters("k_degrid"))
+    rl_main, rl_other = (rl_degrid, rl_grid) if t_degrid > t_grid else (rl_grid, rl_degrid)
 
     out = {
         "metric": "grid-point updates/sec (Gupd/s) + HBM GB/s; BF16-kernel vs FP32 at stated rel err",
@@ -198,9 +207,8 @@ def main():
         "degrid_gupds": round(U / (t_degrid * 1e-3) / 1e9, 2),
         "compression_ratio_records": round(st.n_griddable / max(st.n_runs, 1), 3),
         "compression_ratio_updates": round((U + st.upd_saved) / max(U, 1), 3),
-        "roofline": {"kernel": "k_grid (wg_grid)", "bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+        "roofline": rl_main,
+        "roofline_other": rl_other,
     }
 
     # image finaliser (inverse FFT + corrections) of the step's grid, timed on its own: it is

@@ -94,14 +94,14 @@ struct UnitTable {
     int first[34];
 };
 
-__device__ void build_units(const int32_t *plan, bool per_row_chunk, UnitTable *t) {
+__device__ void build_units(const int32_t *plan, int slots, UnitTable *t) {
     int u = 0, m = 0;
     for (int S = kMaxS; S >= 1; S -= 2) {
         const int c = plan[kPlanCount + S];
         if (c > 0) {
             t->S[m] = S;
             t->first[m] = u;
-            u += c * (per_row_chunk ? nchunk_of(S) : 1);
+            u += c * nchunk_of(S, slots);
             ++m;
         }
     }
@@ -302,35 +302,42 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
 
 // Classes [c0, c1) of a support-S chunk, split evenly over the chunk's waves; the slot
 // count per lane is a template parameter so the unrolled slot loops carry no guards.
-__device__ inline void chunk_classes(int S, int chunk, int &c0, int &c1, int &ns) {
-    const int S2 = S * S, nch = nchunk_of(S);
+__device__ inline void chunk_classes(int S, int chunk, int slots, int &c0, int &c1, int &ns) {
+    const int S2 = S * S, nch = nchunk_of(S, slots);
     const int cpc = (S2 + nch - 1) / nch;
     c0 = chunk * cpc;
     c1 = min(S2, c0 + cpc);
     ns = uni((c1 - c0 + kWave - 1) / kWave);
 }
 
+// Slot count as a template parameter, instantiated for 1..MAX only (the kernel's register
+// allocation is the largest over its instantiations).
+template <int DT, int NS, int MAX>
+__device__ inline void grid_dispatch(int ns, const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
+                                     const int64_t *koff) {
+    if constexpr (NS < MAX) {
+        if (ns == NS) {
+            grid_chunk_ns<DT, NS>(a, S, c0, c1, rb, re, lane, koff);
+            return;
+        }
+        grid_dispatch<DT, NS + 1, MAX>(ns, a, S, c0, c1, rb, re, lane, koff);
+    } else {
+        grid_chunk_ns<DT, MAX>(a, S, c0, c1, rb, re, lane, koff);
+    }
+}
+
 template <int DT>
 __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
     int c0, c1, ns;
-    chunk_classes(S, chunk, c0, c1, ns);
-    switch (ns) {
-    case 1: grid_chunk_ns<DT, 1>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 2: grid_chunk_ns<DT, 2>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 3: grid_chunk_ns<DT, 3>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 4: grid_chunk_ns<DT, 4>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 5: grid_chunk_ns<DT, 5>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 6: grid_chunk_ns<DT, 6>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 7: grid_chunk_ns<DT, 7>(a, S, c0, c1, rb, re, lane, koff); break;
-    default: grid_chunk_ns<DT, 8>(a, S, c0, c1, rb, re, lane, koff); break;
-    }
+    chunk_classes(S, chunk, kSlots, c0, c1, ns);
+    grid_dispatch<DT, 1, kSlots>(ns, a, S, c0, c1, rb, re, lane, koff);
 }
 
 template <int DT>
 __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, true, &ut);
+    if (threadIdx.x == 0) build_units(a.plan, kSlots, &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     for_each_unit(nunits, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_of(S);
+        const int S = uni(ut.S[m]), nch = nchunk_of(S, kSlots);
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;
@@ -457,27 +464,32 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
     }
 }
 
+template <int DT, int NS, int MAX>
+__device__ inline void degrid_dispatch(int ns, const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
+                                       const int64_t *koff) {
+    if constexpr (NS < MAX) {
+        if (ns == NS) {
+            degrid_chunk_ns<DT, NS>(a, S, c0, c1, rb, re, lane, koff);
+            return;
+        }
+        degrid_dispatch<DT, NS + 1, MAX>(ns, a, S, c0, c1, rb, re, lane, koff);
+    } else {
+        degrid_chunk_ns<DT, MAX>(a, S, c0, c1, rb, re, lane, koff);
+    }
+}
+
 template <int DT>
 __device__ void degrid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
     int c0, c1, ns;
-    chunk_classes(S, chunk, c0, c1, ns);
-    switch (ns) {
-    case 1: degrid_chunk_ns<DT, 1>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 2: degrid_chunk_ns<DT, 2>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 3: degrid_chunk_ns<DT, 3>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 4: degrid_chunk_ns<DT, 4>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 5: degrid_chunk_ns<DT, 5>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 6: degrid_chunk_ns<DT, 6>(a, S, c0, c1, rb, re, lane, koff); break;
-    case 7: degrid_chunk_ns<DT, 7>(a, S, c0, c1, rb, re, lane, koff); break;
-    default: degrid_chunk_ns<DT, 8>(a, S, c0, c1, rb, re, lane, koff); break;
-    }
+    chunk_classes(S, chunk, kDegridSlots, c0, c1, ns);
+    degrid_dispatch<DT, 1, kDegridSlots>(ns, a, S, c0, c1, rb, re, lane, koff);
 }
 
 template <int DT>
 __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, true, &ut);
+    if (threadIdx.x == 0) build_units(a.plan, kDegridSlots, &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -485,7 +497,7 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     for_each_unit(nunits, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_of(S);
+        const int S = uni(ut.S[m]), nch = nchunk_of(S, kDegridSlots);
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;

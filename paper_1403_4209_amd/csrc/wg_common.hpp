@@ -10,7 +10,8 @@ namespace wg {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxS = WG_MAX_SUPPORT;
-constexpr int kSlots = 8;          // owned cells per lane in the gridder (register budget)
+constexpr int kSlots = 8;          // most cell classes per lane in the gridder (register budget)
+constexpr int kDegridSlots = 6;    // the same for the degridder
 
 // ---------------------------------------------------------------------------------------
 // Plan layout (int32 words). Items are local chunks (first run, one past last run) of
@@ -34,10 +35,10 @@ inline int64_t plan_segcnt_at(int64_t capacity) { return kPlanHdr + 2 * capacity
 inline int64_t plan_tiles_at(int64_t capacity, int64_t n_seg) { return plan_segcnt_at(capacity) + n_seg + 1; }
 inline int64_t n_scan_tiles(int64_t n_seg) { return (n_seg + kScanTile - 1) / kScanTile; }
 
-// Gridder decomposition of a support-S local chunk into waves: the S*S cell classes
-// (y mod S, x mod S) are numbered c = p*S + q and spread evenly over nchunk_of(S) waves,
-// at most kSlots classes per lane.
-__host__ __device__ inline int nchunk_of(int S) { return (S * S + kWave * kSlots - 1) / (kWave * kSlots); }
+// Decomposition of a support-S local chunk into waves: the S*S cell classes (y mod S,
+// x mod S) are numbered c = p*S + q and spread evenly over nchunk_of(S, slots) waves, at most
+// `slots` classes per lane.
+__host__ __device__ inline int nchunk_of(int S, int slots) { return (S * S + kWave * slots - 1) / (kWave * slots); }
 
 // Status helpers
 #define WG_HIP_CHECK(expr)                                   \
