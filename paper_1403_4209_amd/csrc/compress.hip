@@ -160,8 +160,15 @@ __global__ __launch_bounds__(256) void k_segments(CArgs a) {
         agg.norm = 0.0;
     }
     __syncthreads();
-    const int64_t seg = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (seg < a.n_seg) walk_segment<EMIT>(a, seg, s_wb, s_sup, agg);
+    // Waves take segments in (channel, baseline) order, so that the local chunks each
+    // workgroup appends to the plan come from different baselines: neighbouring work units
+    // of the gridder then sweep different regions of the grid. (Run numbering follows the
+    // record order and does not depend on this.)
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (g < a.n_seg) {
+        const int64_t nb = a.n_seg / a.nc, ch = g / nb, b = g - ch * nb;
+        walk_segment<EMIT>(a, b * a.nc + ch, s_wb, s_sup, agg);
+    }
     __syncthreads();
     if (!EMIT) {
         if (threadIdx.x < 64 && agg.cnt[threadIdx.x]) atomicAdd(&a.plan[kPlanCount + threadIdx.x], agg.cnt[threadIdx.x]);

@@ -22,6 +22,7 @@ struct GArgs {
     const int8_t *ou, *ov;
     const float2 *gamma;
     const int32_t *plan, *items;
+    int32_t *queue;  // work-list counter and exit count of this kernel (two plan words)
     const int64_t *offset;
     const void *data;
     float *grid;        // grid (wg_grid, accumulate) or input grid (wg_degrid)
@@ -198,14 +199,43 @@ struct Stage {
     int yc[kSlots];
 };
 
-// Persistent walk over the support-sorted work list (largest supports first): wave w takes
-// units w, w + W, ... where W is the number of waves in the launch, so the units in flight
-// are spread over the whole list (many baselines at once, few shared grid cells).
+// Static walk over the support-sorted work list (largest supports first): wave w takes
+// units w, w + W, ... (W waves in the launch). Waves drift apart, so the units in flight
+// spread over much of the list: many baselines and w-planes at once.
 template <typename F>
-__device__ inline void for_each_unit(int nunits, F &&body) {
+__device__ inline void for_each_unit_static(int nunits, F &&body) {
     const int wpb = blockDim.x / kWave;
     const int stride = gridDim.x * wpb;
     for (int u = uni(blockIdx.x * wpb + (int)(threadIdx.x / kWave)); u < nunits; u += stride) body(u);
+}
+
+// Persistent walk over the support-sorted work list (largest supports first) through a
+// shared counter: each wave takes the next unit, so the units in flight form a narrow window
+// of the list (one or two w-planes at a time: a table working set that stays in L2). Within
+// a support the plan lists chunks channel-major, so the window spans many baselines and
+// their commits rarely meet on a cell. Every wave leaves once the list is exhausted; the
+// last one out resets the counter and the exit count for the next launch.
+constexpr int kUnitsPerTicket = 4;  // units handed out per counter increment
+
+template <typename F>
+__device__ inline void for_each_unit(int nunits, int32_t *q, F &&body) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nwaves = (int)(gridDim.x * (blockDim.x / kWave));
+    for (;;) {
+        int u0 = 0;
+        if (lane == 0) u0 = atomicAdd(&q[0], kUnitsPerTicket);
+        u0 = __builtin_amdgcn_readlane(u0, 0);
+        if (u0 >= nunits) break;
+        const int u1 = min(u0 + kUnitsPerTicket, nunits);
+        for (int u = u0; u < u1; ++u) body(u);
+    }
+    if (lane == 0) {
+        __threadfence();
+        if (atomicAdd(&q[1], 1) == nwaves - 1) {
+            atomicExch(&q[0], 0);
+            atomicExch(&q[1], 0);
+        }
+    }
 }
 
 template <int DT, int NS>
@@ -342,7 +372,7 @@ __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
     const int lane = threadIdx.x & (kWave - 1);
-    for_each_unit(nunits, [&](int u) {
+    for_each_unit_static(nunits, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
         const int S = uni(ut.S[m]), nch = nchunk_of(S, kSlots);
@@ -494,7 +524,7 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
     const int lane = threadIdx.x & (kWave - 1);
-    for_each_unit(nunits, [&](int u) {
+    for_each_unit(nunits, a.queue, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
         const int S = uni(ut.S[m]), nch = nchunk_of(S, kDegridSlots);
@@ -553,6 +583,7 @@ GArgs make_args(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs) {
     a.ov = runs->ov;
     a.gamma = (const float2 *)runs->gamma;
     a.plan = runs->plan;
+    a.queue = nullptr;
     a.items = runs->plan + plan_items_at();
     a.offset = kt->offset;
     a.data = kt->data;
@@ -612,6 +643,7 @@ extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *r
     GArgs a = make_args(g, kt, runs);
     a.grid = (float *)grid;
     a.vis_out = (float2 *)vis_out;
+    a.queue = runs->plan + kPlanQueueDegrid;
     a.uvw = uvw;
     a.wt = weight;
     a.nc = nc;

@@ -20,6 +20,7 @@ constexpr int kDegridSlots = 6;    // the same for the degridder
 //   [kPlanCount + S]   items with support S              (S = 1..63, odd)
 //   [kPlanOff + S]     first item slot of support S       (kPlanOff + 64 = total)
 //   [kPlanCur + S]     append cursor of support S
+//   [kPlanQueueDegrid] degridder work-list counter and exit count (2 words), zero between launches
 //   [kPlanHdr ...]     items: 2 * capacity words
 //   then               runs per segment, scanned in place: n_seg + 1 words
 //   then               scan tile totals: n_tiles + 1 words
@@ -27,6 +28,7 @@ constexpr int kDegridSlots = 6;    // the same for the degridder
 constexpr int kPlanCount = 0;
 constexpr int kPlanOff = 64;
 constexpr int kPlanCur = 129;
+constexpr int kPlanQueueDegrid = 200;
 constexpr int kPlanHdr = 256;
 constexpr int kScanTile = 4096;
 
