@@ -131,7 +131,8 @@ typedef struct wg_ktable {
  * w-plane `plane` and oversample offsets (ou, ov); gamma is the sum over its records of
  * weight * (vis, conjugated when w < 0), as float32 (re, im). Runs are in record order.
  * `plan` is a device work list the gridder reads (local chunks of equal support, grouped by
- * support); size it with wg_plan_elems. `work` is scratch that wg_degrid overwrites (one
+ * support); size it with wg_plan_elems. It also holds wg_degrid's work counter, so two
+ * wg_degrid calls on the same runs must not overlap in time. `work` is scratch that wg_degrid overwrites (one
  * complex float per run). Every array has `capacity` entries (gamma and work 2x); capacity
  * must be >= nb*nc*nt, so the run list can never overflow.
  */
