@@ -229,6 +229,28 @@ def main():
     del fin_ws, image
 
     if not args.no_variants:
+        # table-generation study: the FP32 table of this geometry with more w-planes, up to the
+        # thesis's 200 (build timed alone, host copies off as in the step)
+        study = {}
+        for n_w in (32, 64, 128, 200):
+            gd = dict(w.geom, n_w=n_w)
+            gs = wg.geom_from_dict(gd)
+            ts = wg.KernelTable(gs, "f32", device=dev)
+            _, wsb = wg.wg_ktable_sizes(gs)
+            wss = torch.empty(wsb, dtype=torch.uint8, device=dev)
+            wg.wg_ktable_build(gs, ts.kt, wss, host_copies=False)
+            torch.cuda.synchronize()
+            tt = 0.0
+            for _ in range(3):
+                ev[0].record()
+                wg.wg_ktable_build(gs, ts.kt, wss, host_copies=False)
+                ev[1].record()
+                torch.cuda.synchronize()
+                tt += ev[0].elapsed_time(ev[1])
+            study[str(n_w)] = round(tt / 3, 4)
+            del ts, wss
+        out["ktable_ms_by_planes"] = study
+
         # BF16 table, same records (grid and degrid only; table build timed once)
         tb16 = wg.KernelTable(geom, "bf16", device=dev)
         g16 = wg.Gridder(geom, tb16, uvw, il, weight)

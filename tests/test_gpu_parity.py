@@ -128,6 +128,23 @@ def test_table_parity(case, dtype):
     assert np.array_equal(wb[1:], ref["wbound"][1:])
 
 
+def test_table_with_200_planes():
+    """The thesis's 200-plane table (its table-generation cost study) at a small image size:
+    supports and offsets bit-exact, samples within one unit of the oracle's rounded FP32
+    values, for every plane."""
+    geom = dict(n=512, beta=8, n_w=200, s_lo=9, s_hi=31, m_img=64, du=40.0, w_max=3000.0)
+    say("table 200 planes", geom)
+    g = wg.geom_from_dict(geom)
+    tb = wg.KernelTable(g, "f32", device=DEV)
+    ref = otable(geom, "f32")
+    assert list(tb.support) == [int(s) for s in ref["support"]]
+    assert list(tb.offset) == [int(o) for o in ref["offset"]]
+    got = tb.data_complex().cpu().numpy().astype(np.complex128)
+    for part in (np.real, np.imag):
+        d = np.abs(part(got) - part(ref["data"]))
+        assert np.all(d <= 2.0 ** -23 * np.abs(part(ref["data"])) + 1e-13)
+
+
 def test_table_async_build_matches_oracle():
     """The build without host copies (supports computed on the device, nothing waits) gives
     the oracle's supports and samples too."""
