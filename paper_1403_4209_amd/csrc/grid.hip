@@ -356,18 +356,22 @@ __device__ inline void grid_dispatch(int ns, const GArgs &a, int S, int c0, int 
     }
 }
 
+// Most classes per lane of the gridder: 8 with FP32 tables, 6 with 16-bit tables.
+template <int DT>
+constexpr int grid_slots() { return DT == WG_KF32 ? kSlots : kSlotsNarrow; }
+
 template <int DT>
 __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
     int c0, c1, ns;
-    chunk_classes(S, chunk, kSlots, c0, c1, ns);
-    grid_dispatch<DT, 1, kSlots>(ns, a, S, c0, c1, rb, re, lane, koff);
+    chunk_classes(S, chunk, grid_slots<DT>(), c0, c1, ns);
+    grid_dispatch<DT, 1, grid_slots<DT>()>(ns, a, S, c0, c1, rb, re, lane, koff);
 }
 
 template <int DT>
 __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, kSlots, &ut);
+    if (threadIdx.x == 0) build_units(a.plan, grid_slots<DT>(), &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     for_each_unit_static(nunits, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_of(S, kSlots);
+        const int S = uni(ut.S[m]), nch = nchunk_of(S, grid_slots<DT>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;
