@@ -196,8 +196,12 @@ __device__ inline void lane_classes(int S, int c0, int c1, int lane, u16x2 *cls)
 template <int DT>
 struct Stage {
     typename KRaw<DT>::type k[kSlots];
-    int yc[kSlots];
+    int yc[kSlots];  // cells, set only when the footprint moved
+    bool moved;      // wave-uniform: the run's footprint origin differs from the previous run's
 };
+
+// Cell base of "no previous run": no footprint starts there (cell bases are below n*n).
+constexpr unsigned kNoCell = 0xFFFFFFFFu;
 
 // Static walk over the support-sorted work list (largest supports first): wave w takes
 // units w, w + W, ... (W waves in the launch). Waves drift apart, so the units in flight
@@ -255,6 +259,10 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
     const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};           // cell offset in the grid
     float acc_r[kSlots], acc_i[kSlots], cmp_r[kSlots], cmp_i[kSlots];
     int cur[kSlots];  // owned cell (y*n + x); set from the chunk's first run
+    // Footprint positions of the lane's classes, recomputed only when the footprint moves
+    // (consecutive runs of a chunk mostly differ in oversampling offsets or plane alone).
+    u16x2 wpos[kSlots];
+    unsigned last_cell0 = kNoCell;
 #pragma unroll
     for (int m = 0; m < NS; ++m) acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
     // Commit the cell's compensated sum (acc - cmp); the next cell starts from acc = cmp,
@@ -273,17 +281,23 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
         const int n = min(kWave, re - base);
         const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
 
-        // cells and samples of the lane's classes for run t
+        // cells (when the footprint moved) and samples of the lane's classes for run t
         auto fetch = [&](int t, Stage<DT> &st) {
-            const u16x2 ph = as_u16x2((unsigned)rl(b.ph, t));
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
+            const bool ok = rl(b.ok, t) != 0;
+            st.moved = !ok || cell0 != last_cell0;
+            last_cell0 = (unsigned)uni((int)(ok ? cell0 : kNoCell));
+            if (st.moved) {
+                const u16x2 ph = as_u16x2((unsigned)rl(b.ph, t));
 #pragma unroll
-            for (int m = 0; m < NS; ++m) {
-                const u16x2 w = footprint_pos(cls[m], ph, ss);
-                st.yc[m] = (int)dot2(w, mul_c, cell0);
-                st.k[m] = buf_load<DT>(rs, (int)dot2(w, mul_k, kbB));
+                for (int m = 0; m < NS; ++m) {
+                    wpos[m] = footprint_pos(cls[m], ph, ss);
+                    st.yc[m] = (int)dot2(wpos[m], mul_c, cell0);
+                }
             }
+#pragma unroll
+            for (int m = 0; m < NS; ++m) st.k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
         };
         auto accumulate = [&](int t, const Stage<DT> &st) {
             if (!rl(b.ok, t)) return;
@@ -291,7 +305,7 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 if (m < nslots - 1 || last_ok) {
-                    if (st.yc[m] != cur[m]) {
+                    if (st.moved && st.yc[m] != cur[m]) {
                         commit(m);
                         cur[m] = st.yc[m];
                     }
@@ -404,15 +418,16 @@ __device__ inline float wave_total(float v) {
 }
 
 // Adjoint, with the gridder's decomposition: a wave owns the same cell classes of a local
-// chunk, keeps the grid value of each owned cell in a register and reloads it only when the
-// footprint moves the cell, and forms per run the partial dot product of conj(K) with those
-// values (a short FMA chain per lane, then a DPP tree over the wave). The waves sharing a
+// chunk, keeps the grid value of each owned cell in a register and reloads the values only
+// when the footprint moves (about one run in seven), and forms per run the partial dot
+// product of conj(K) with those values (a short FMA chain per lane, then a DPP tree over the
+// wave). The waves sharing a
 // chunk add their partial sums into work[run]; k_degrid_finish hands d to the run's records.
 template <int DT>
 struct DStage {
     typename KRaw<DT>::type k[kSlots];
-    float2 g[kSlots];
-    bool ld[kSlots];  // g[m] holds a newly loaded cell value (a lane mask per slot)
+    float2 g[kSlots];  // grid values of the run's cells (loaded when the footprint moved)
+    bool moved;        // wave-uniform: the run's footprint origin differs from the previous run's
 };
 
 // A wave-uniform value held in a VGPR, so that an instruction taking it together with a
@@ -436,38 +451,39 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
     const u16x2 mul_k = as_u16x2(in_vgpr((unsigned)(S * esz) << 16 | (unsigned)esz));
     const u16x2 mul_c = as_u16x2(in_vgpr((unsigned)a.n << 16 | 1u));
-    int pyc[kSlots];      // cells of the most recently fetched run
     float2 gv[kSlots];    // grid values of the owned cells
+    u16x2 wpos[kSlots];   // footprint positions, recomputed only when the footprint moves
+    unsigned last_cell0 = kNoCell;
 #pragma unroll
-    for (int m = 0; m < NS; ++m) {
-        pyc[m] = -1;
-        gv[m] = make_float2(0.f, 0.f);
-    }
+    for (int m = 0; m < NS; ++m) gv[m] = make_float2(0.f, 0.f);
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
         const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
 
         auto fetch = [&](int t, DStage<DT> &st) {
-            const u16x2 ph = as_u16x2((unsigned)rl(b.ph, t));
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
+            const bool ok = rl(b.ok, t) != 0;
+            st.moved = !ok || cell0 != last_cell0;
+            last_cell0 = (unsigned)uni((int)(ok ? cell0 : kNoCell));
+            if (st.moved) {
+                const u16x2 ph = as_u16x2((unsigned)rl(b.ph, t));
 #pragma unroll
-            for (int m = 0; m < NS; ++m) {
-                const u16x2 w = footprint_pos(cls[m], ph, ss);
-                const int yc = (int)dot2(w, mul_c, cell0);
-                st.k[m] = buf_load<DT>(rs, (int)dot2(w, mul_k, kbB));
-                st.ld[m] = yc != pyc[m];
-                if (st.ld[m]) st.g[m] = grid[(unsigned)yc];
-                pyc[m] = yc;
+                for (int m = 0; m < NS; ++m) {
+                    wpos[m] = footprint_pos(cls[m], ph, ss);
+                    st.g[m] = grid[dot2(wpos[m], mul_c, cell0)];
+                }
             }
+#pragma unroll
+            for (int m = 0; m < NS; ++m) st.k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
         };
         auto consume = [&](int t, const DStage<DT> &st) {
             float pr = 0.f, pim = 0.f;
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 if (m < nslots) {
-                    if (st.ld[m]) gv[m] = st.g[m];
+                    if (st.moved) gv[m] = st.g[m];
                     if (m < nslots - 1 || last_ok) {
                         const float2 kv = to_float2<DT>(st.k[m]);
                         pr = fmaf(kv.x, gv[m].x, fmaf(kv.y, gv[m].y, pr));

@@ -12,7 +12,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxS = WG_MAX_SUPPORT;
 constexpr int kSlots = 8;          // most cell classes per lane in the gridder (register budget)
 constexpr int kSlotsNarrow = 6;    // the same with BF16/FP16 tables (measured faster there)
-constexpr int kDegridSlots = 6;    // the same for the degridder
+constexpr int kDegridSlots = 5;    // the same for the degridder
 
 // ---------------------------------------------------------------------------------------
 // Plan layout (int32 words). Items are local chunks (first run, one past last run) of
