@@ -478,6 +478,7 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
 #pragma unroll
             for (int m = 0; m < NS; ++m) st.k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
         };
+        float sum_r = 0.f, sum_i = 0.f;  // lane t: this wave's sum for run base + t
         auto consume = [&](int t, const DStage<DT> &st) {
             float pr = 0.f, pim = 0.f;
 #pragma unroll
@@ -491,14 +492,10 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
                     }
                 }
             }
-            if (rl(b.ok, t)) {
-                const float dr = wave_total(pr), di = wave_total(pim);
-                if (lane == 0) {
-                    float *w = (float *)(a.work + base + t);
-                    unsafeAtomicAdd(w, dr);
-                    unsafeAtomicAdd(w + 1, di);
-                }
-            }
+            // the wave's sum for run t waits in lane t; one atomic per batch adds them all
+            const float dr = wave_total(pr), di = wave_total(pim);
+            sum_r = lane == t ? dr : sum_r;
+            sum_i = lane == t ? di : sum_i;
         };
 
         DStage<DT> sa, sb;
@@ -510,6 +507,11 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
                 if (t + 2 < n) fetch(t + 2, sa);
                 consume(t + 1, sb);
             }
+        }
+        if (lane < n && b.ok) {
+            float *w = (float *)(a.work + base + lane);
+            unsafeAtomicAdd(w, sum_r);
+            unsafeAtomicAdd(w + 1, sum_i);
         }
     }
 }
