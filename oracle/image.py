@@ -27,10 +27,12 @@ from .ktable import taper
 
 def axis_correction(geom: dict) -> np.ndarray:
     """c(l)/c(0) * sinc(pi l du / beta) for the N pixels of one axis (steps 3 and 4)."""
-    n, du, beta = geom["n"], geom["du"], geom["beta"]
-    l = (np.arange(n) - n // 2) / (n * du)
-    t = taper(2.0 * l * du) / taper(np.zeros(1))[0]
-    return t * np.sinc(l * du / beta)          # numpy sinc(x) = sin(pi x) / (pi x)
+    n, beta = geom["n"], geom["beta"]
+    # x = 2 l / FOV = 2 (p - N/2) / N, taken exactly (the first pixel sits at x = -1 whatever
+    # du is; going through l = (p - N/2) / (N du) would round it to inside the interval)
+    x = 2.0 * (np.arange(n) - n // 2) / n
+    t = taper(x) / taper(np.zeros(1))[0]
+    return t * np.sinc(x / (2.0 * beta))        # l du / beta; numpy sinc(x) = sin(pi x) / (pi x)
 
 
 def finalise(geom: dict, grid: np.ndarray, normaliser: float) -> np.ndarray:

@@ -527,6 +527,24 @@ def test_finaliser_unit_source_at_phase_centre(oracle_mod):
     assert abs(D[48, 48] - 1.0) < 1e-12
 
 
+@pytest.mark.parametrize("du", [15.006348791326975, 0.1, 3.3, 10.0])
+def test_finaliser_correction_edge_and_symmetry(du):
+    """The correction of one axis depends on the pixel's place in the field only (x = 2 l /
+    FOV, sec. convgriddingmath; l du / beta = x / (2 beta), eq. coversampled), not on du: the
+    first pixel sits at l = -FOV/2 exactly, where the taper is zero, whatever rounding du
+    brings; the taper and the sinc are even, so pixels N/2 - k and N/2 + k match; 1 at the
+    centre."""
+    from oracle import image as oimg
+    for n in (96, 256):
+        geom = dict(n=n, beta=8, n_w=2, s_lo=7, s_hi=7, m_img=n, du=du, w_max=10.0)
+        c = oimg.axis_correction(geom)
+        assert c[0] == 0.0 and c[n // 2] == 1.0
+        assert np.all(c[1:] > 0.0)
+        k = np.arange(1, n // 2)
+        assert np.array_equal(c[n // 2 - k], c[n // 2 + k])
+        assert np.array_equal(c, oimg.axis_correction(dict(geom, du=1.0)))
+
+
 @pytest.mark.parametrize("frac", [0.25, 0.35])
 def test_finaliser_recovers_point_source_flux(oracle_mod, frac):
     """A 2.5 Jy point source off the phase centre, observed by 40000 records at random
