@@ -221,7 +221,7 @@ def main():
     t_fin = 0.0
     for _ in range(args.steps):
         ev[0].record()
-        wg.finalise(geom, g32, gridder.runs.stats_d, out=image, ws=fin_ws)
+        wg.finalise(geom, g32, gridder.runs.normaliser(), out=image, ws=fin_ws)
         ev[1].record()
         torch.cuda.synchronize()
         t_fin += ev[0].elapsed_time(ev[1])

@@ -59,6 +59,9 @@ typedef enum wg_kdtype {
 
 /* wg_geom.flags */
 #define WG_COMPRESS 1u   /* merge consecutive records with the same key (eq. compression) */
+#define WG_GRID_PER_CHANNEL 2u /* one grid per channel, as the thesis's imaging tool sets up one
+                                  WImager instance per channel; without it every channel goes to
+                                  one grid (the channel interleaving of its Data Set 0 runs)  */
 
 /* Limits of this build. */
 #define WG_MAX_SUPPORT 63    /* largest kernel support (odd)                            */
@@ -79,7 +82,7 @@ typedef enum wg_kdtype {
  *           beta*m_img <= WG_MAX_FFT, and (s_hi-1)/2*beta + beta/2 < beta*m_img/2).
  *   du      uv cell size in wavelengths (> 0); the image field of view is 1/du.
  *   w_max   largest |w| tabulated, wavelengths (>= 0).
- *   flags   WG_COMPRESS or 0.
+ *   flags   WG_COMPRESS and/or WG_GRID_PER_CHANNEL, or 0.
  */
 typedef struct wg_geom {
     int32_t n;
@@ -132,7 +135,10 @@ typedef struct wg_ktable {
  * weight * (vis, conjugated when w < 0), as float32 (re, im). Runs are in record order.
  * `plan` is a device work list the gridder reads (local chunks of equal support, grouped by
  * support); size it with wg_plan_elems. It also holds wg_degrid's work counter, so two
- * wg_degrid calls on the same runs must not overlap in time. `work` is scratch that wg_degrid overwrites (one
+ * wg_degrid calls on the same runs must not overlap in time.
+ * With WG_GRID_PER_CHANNEL, `grid` (one int16 per run: the channel of its records, i.e. the
+ * grid it goes to) and `norm` (one double per channel: that channel's normaliser N of eq.
+ * normalizer) are required and written by wg_compress; otherwise they may be NULL. `work` is scratch that wg_degrid overwrites (one
  * complex float per run). Every array has `capacity` entries (gamma and work 2x); capacity
  * must be >= nb*nc*nt, so the run list can never overflow.
  */
@@ -149,6 +155,8 @@ typedef struct wg_runs {
     int32_t *plan;
     int64_t plan_elems;
     float *work;
+    int16_t *grid;
+    double *norm;
 } wg_runs;
 
 /*
@@ -222,7 +230,8 @@ int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const 
 /*
  * Gridding phase (eq. gridding): for every run, grid[row0+i][a+j] += gamma * K[i][j] with
  * a = x + n/2 - H, row0 = y + n/2 - H, K the run's matrix. ACCUMULATES into `grid`
- * (complex64 [n][n]); the caller zeroes it first. Accumulation is FP32 with Kahan
+ * (complex64 [n][n], or [nc][n][n] with WG_GRID_PER_CHANNEL, run q going to grid
+ * runs->grid[q]); the caller zeroes it first. Accumulation is FP32 with Kahan
  * compensation per owned cell between commits; commits use FP32 atomic adds, so the last
  * bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
  * Errors: WG_EINVAL, WG_EHIP.
@@ -232,7 +241,8 @@ int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg
 
 /*
  * Adjoint of wg_compress + wg_grid with respect to the visibilities: per run
- * d = sum_ij conj(K[i][j]) * grid[row0+i][a+j] (FP32, pairwise/tree summation; partial sums
+ * d = sum_ij conj(K[i][j]) * grid[row0+i][a+j] (grid complex64 [n][n], or [nc][n][n] read
+ * at grid runs->grid[q] with WG_GRID_PER_CHANNEL; FP32, pairwise/tree summation; partial sums
  * of the waves sharing a run are combined with FP32 atomic adds into runs->work, so the last
  * bits depend on scheduling); record r of the run gets weight_r * (d, or conj(d) when
  * w_r(metres) < 0); records in no run get 0. OVERWRITES vis_out (complex64 [nb][nc][nt]) and
@@ -245,7 +255,8 @@ int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const 
 
 /*
  * Image finaliser (Algorithm finalizer), one polarisation: inverse 2-D FFT of the grid, real
- * part over the normaliser N_p (eq. normalizer; read on the device from stats->normaliser),
+ * part over the normaliser N_p (eq. normalizer; read on the device from *normaliser, e.g.
+ * &stats->normaliser, or &runs->norm[c] for channel c of per-channel grids),
  * divided by the prolate taper psi_0(3 pi, 2 l du) normalised to 1 at the centre (sec.
  * convgriddingmath) and by sinc(pi l du / beta) sinc(pi m du / beta) (eq. coversampled).
  * Image pixel [q][p] holds (l, m) = ((p - n/2), (q - n/2)) / (n du); the real part is taken
@@ -253,7 +264,7 @@ int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const 
  * the taper is zero (first row and column) are 0; the whole image is 0 when the normaliser
  * is 0. FFTs in FP32.
  *   grid   complex64 [n][n] (device, read only)
- *   stats  device wg_stats (from wg_compress)
+ *   normaliser  device double
  *   image  float32 [n][n] (device, OVERWRITTEN)
  *   ws     device workspace of wg_finalise_ws_bytes bytes (two n x n complex64 buffers,
  *          twiddles, corrections)
@@ -261,7 +272,7 @@ int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const 
  * Errors: WG_EINVAL, WG_ECAPACITY (ws too small), WG_EUNSUPPORTED (n), WG_EHIP.
  */
 int wg_finalise_ws_bytes(const wg_geom *g, size_t *ws_bytes);
-int wg_finalise(const wg_geom *g, const float *grid, const wg_stats *stats, float *image, void *ws,
+int wg_finalise(const wg_geom *g, const float *grid, const double *normaliser, float *image, void *ws,
                 size_t ws_bytes, wg_stream_t stream);
 
 #ifdef __cplusplus

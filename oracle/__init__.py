@@ -9,6 +9,8 @@ shares no code with it.
 * `grid`, `degrid`          -- eq. gridding and its adjoint, plain C.
 * `image.finalise`          -- Algorithm finalizer (inverse FFT, normaliser, taper and
                                oversampling corrections), numpy.
+* `per_channel`             -- one grid per channel: each channel's records compressed,
+                               gridded and normalised on their own.
 
 Parity unpinned: none of the functions here; every one is pinned by the tests listed in
 the design notes (closed forms, invariants, brute force on tiny inputs).
@@ -140,3 +142,21 @@ def degrid(geom, table, runs, grid_arr, uvw, weight, shape):
                     _p(_c(runs["ou"], np.int32)), _p(_c(runs["ov"], np.int32)), _p(g), _p(uvw), _p(weight),
                     nb, nc, nt, _p(out))
     return out.reshape(nb, nc, nt)
+
+
+def per_channel(geom, table, uvw, inv_lambda, vis, weight=None, flag=None, compress_runs=True):
+    """Per-channel imaging as the thesis's imaging tool sets it up (one WImager instance per
+    channel): the records of channel c are compressed and gridded on a grid of their own, with
+    their own normaliser (eq. normalizer over that channel's records). Returns the per-channel
+    run lists, the grids complex128 [C][n][n] and the normalisers [C]."""
+    nc = len(inv_lambda)
+    runs, grids, norms = [], [], []
+    for c in range(nc):
+        sl = slice(c, c + 1)
+        r = compress(geom, table, uvw, inv_lambda[sl], vis[:, sl, :],
+                     None if weight is None else weight[:, sl, :], None if flag is None else flag[:, sl, :],
+                     compress_runs)
+        runs.append(r)
+        grids.append(grid(geom, table, r))
+        norms.append(r["normaliser"])
+    return runs, np.stack(grids), np.array(norms)

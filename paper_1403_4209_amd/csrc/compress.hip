@@ -36,6 +36,8 @@ struct CArgs {
     float2 *gamma;
     int32_t *plan, *items, *segcnt, *tiles;
     wg_stats *stats;
+    int16_t *grid_id;  // per-channel grids: the grid (channel) of each run, else NULL
+    double *norm;      // per-channel grids: the normaliser of each channel, else NULL
 };
 
 struct Key {
@@ -89,6 +91,8 @@ __device__ inline Key index_record(double um, double vm, double wm, double il, b
 __global__ void k_init(CArgs a, int64_t n_records) {
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < kPlanHdr; i += blockDim.x) a.plan[i] = 0;
+        if (a.norm)
+            for (int c = threadIdx.x; c < a.nc; c += blockDim.x) a.norm[c] = 0.0;
         if (threadIdx.x == 0) {
             a.stats->n_records = n_records;
             a.stats->n_griddable = 0;
@@ -300,6 +304,7 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
                 a.plane[j] = (int16_t)key.k;
                 a.ou[j] = (int8_t)key.ou;
                 a.ov[j] = (int8_t)key.ov;
+                if (a.grid_id) a.grid_id[j] = (int16_t)ch;
             }
             const int cnext = __shfl_down((int)c, 1, kWave);
             const bool last_in_seg = (t == a.nt - 1);
@@ -354,7 +359,10 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
         }
     } else {
         const double nsum = wave_sum(my_norm);
-        if (lane == 0) atomicAdd(&agg.norm, nsum);
+        if (lane == 0) {
+            atomicAdd(&agg.norm, nsum);
+            if (a.norm) atomicAdd(&a.norm[ch], nsum);
+        }
     }
 }
 
@@ -448,6 +456,11 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
         !runs->gamma || !runs->plan)
         return WG_EINVAL;
     const int64_t n_seg = nb * nc;
+    const bool per_channel = (g->flags & WG_GRID_PER_CHANNEL) != 0;
+    if (per_channel) {
+        if (!runs->grid || !runs->norm) return WG_EINVAL;
+        if (nc > 32767 || (int64_t)nc * g->n * g->n >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
+    }
     if (runs->capacity < n_rec) return WG_ECAPACITY;
     if (runs->plan_elems < wg_plan_elems(runs->capacity, n_seg)) return WG_ECAPACITY;
 
@@ -483,6 +496,8 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
     a.segcnt = runs->plan + plan_segcnt_at(runs->capacity);
     a.tiles = runs->plan + plan_tiles_at(runs->capacity, n_seg);
     a.stats = stats;
+    a.grid_id = per_channel ? runs->grid : nullptr;
+    a.norm = per_channel ? runs->norm : nullptr;
 
     hipStream_t s = (hipStream_t)stream;
     const int64_t n_tiles = n_scan_tiles(n_seg);

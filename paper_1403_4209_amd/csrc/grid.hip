@@ -22,6 +22,8 @@ struct GArgs {
     const int8_t *ou, *ov;
     const float2 *gamma;
     const int32_t *plan, *items;
+    const int16_t *grid_id;  // per-channel grids: the grid of each run (else NULL)
+    int64_t cells;           // cells of one grid (n*n)
     int32_t *queue;  // work-list counter and exit count of this kernel (two plan words)
     const int64_t *offset;
     const void *data;
@@ -138,7 +140,7 @@ __device__ inline RunBatch load_batch(const GArgs &a, int S, int j, bool valid, 
         if (ax >= 0 && ax + S <= a.n && row0 >= 0 && row0 + S <= a.n && kbase >= 0 &&
             kbase + (int64_t)S * S <= a.data_cap) {
             b.ok = 1;
-            b.cell0 = row0 * a.n + ax;
+            b.cell0 = row0 * a.n + ax + (a.grid_id ? (int)(a.grid_id[j] * a.cells) : 0);
             b.ph = (row0 % S) << 16 | (ax % S);
             b.kb = (int)kbase;
             b.gr = g.x;
@@ -605,6 +607,8 @@ GArgs make_args(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs) {
     a.ov = runs->ov;
     a.gamma = (const float2 *)runs->gamma;
     a.plan = runs->plan;
+    a.grid_id = (g->flags & WG_GRID_PER_CHANNEL) ? runs->grid : nullptr;
+    a.cells = (int64_t)g->n * g->n;
     a.queue = nullptr;
     a.items = runs->plan + plan_items_at();
     a.offset = kt->offset;
@@ -618,10 +622,11 @@ GArgs make_args(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs) {
     return a;
 }
 
-int check_runs(const wg_runs *runs) {
+int check_runs(const wg_geom *g, const wg_runs *runs) {
     if (!runs || !runs->start || !runs->len || !runs->x || !runs->y || !runs->plane || !runs->ou ||
         !runs->ov || !runs->gamma || !runs->plan || runs->capacity < 1)
         return WG_EINVAL;
+    if ((g->flags & WG_GRID_PER_CHANNEL) && !runs->grid) return WG_EINVAL;
     return WG_OK;
 }
 
@@ -636,7 +641,7 @@ extern "C" int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *run
     int st = check_geom(g);
     if (st != WG_OK) return st;
     if ((st = check_table(g, kt)) != WG_OK) return st;
-    if ((st = check_runs(runs)) != WG_OK) return st;
+    if ((st = check_runs(g, runs)) != WG_OK) return st;
     if (!grid || !stats) return WG_EINVAL;
     if (kt->data_cap >= ((int64_t)1 << 28)) return WG_EUNSUPPORTED;  // byte offsets stay 32-bit
     GArgs a = make_args(g, kt, runs);
@@ -657,7 +662,7 @@ extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *r
     int st = check_geom(g);
     if (st != WG_OK) return st;
     if ((st = check_table(g, kt)) != WG_OK) return st;
-    if ((st = check_runs(runs)) != WG_OK) return st;
+    if ((st = check_runs(g, runs)) != WG_OK) return st;
     if (!grid || !stats || !uvw || !vis_out || !runs->work || nb < 1 || nc < 1 || nt < 1) return WG_EINVAL;
     if (kt->data_cap >= ((int64_t)1 << 28)) return WG_EUNSUPPORTED;  // byte offsets stay 32-bit
     const int64_t n_rec = nb * (int64_t)nc * nt;

@@ -178,7 +178,7 @@ __global__ void k_fin_setup(float2 *tw, double *corr, int n, int beta, TaperCoef
 // image[q][p] = Re(T[p][q]) / (normaliser * corr[q] * corr[p]) (0 where the product is 0 or
 // the normaliser is 0), T the twice-transformed, transposed grid; 32 x 32 tiles.
 __global__ void k_fin_out(const float2 *__restrict__ T, const double *__restrict__ corr,
-                          const wg_stats *__restrict__ stats, float *__restrict__ image, int n) {
+                          const double *__restrict__ normaliser, float *__restrict__ image, int n) {
     __shared__ float tile[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     for (int i = threadIdx.y; i < 32; i += blockDim.y) {
@@ -186,7 +186,7 @@ __global__ void k_fin_out(const float2 *__restrict__ T, const double *__restrict
         if (r < n && c < n) tile[i][threadIdx.x] = T[(size_t)r * n + c].x;
     }
     __syncthreads();
-    const double norm = stats->normaliser;
+    const double norm = *normaliser;
     for (int i = threadIdx.y; i < 32; i += blockDim.y) {
         const int q = bx + i, p = by + threadIdx.x;
         if (q < n && p < n) {
@@ -233,12 +233,12 @@ extern "C" int wg_finalise_ws_bytes(const wg_geom *g, size_t *ws_bytes) {
     return WG_OK;
 }
 
-extern "C" int wg_finalise(const wg_geom *g, const float *grid, const wg_stats *stats, float *image, void *ws,
+extern "C" int wg_finalise(const wg_geom *g, const float *grid, const double *normaliser, float *image, void *ws,
                            size_t ws_bytes, wg_stream_t stream) {
     using namespace wg;
     const int st = check_geom(g);
     if (st != WG_OK) return st;
-    if (!grid || !stats || !image || !ws) return WG_EINVAL;
+    if (!grid || !normaliser || !image || !ws) return WG_EINVAL;
     const int n = g->n, lg = image_lg(n);
     if (lg < 0) return WG_EUNSUPPORTED;
     const FinLayout lay = fin_layout(n);
@@ -257,6 +257,6 @@ extern "C" int wg_finalise(const wg_geom *g, const float *grid, const wg_stats *
     hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, (const float2 *)grid, A, n, lg, tw);
     hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
     hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw);
-    hipLaunchKernelGGL(k_fin_out, tiles, tb, 0, s, A, corr, stats, image, n);
+    hipLaunchKernelGGL(k_fin_out, tiles, tb, 0, s, A, corr, normaliser, image, n);
     return launch_status();
 }

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libwgrid.so")
 WG_OK, WG_EINVAL, WG_ECAPACITY, WG_EHIP, WG_EUNSUPPORTED = 0, -1, -3, -4, -5
 WG_KF32, WG_KBF16, WG_KF16 = 0, 1, 2
 WG_COMPRESS = 1
+WG_GRID_PER_CHANNEL = 2
 DTYPES = {"f32": WG_KF32, "bf16": WG_KBF16, "f16": WG_KF16}
 _ELEM_BYTES = {WG_KF32: 8, WG_KBF16: 4, WG_KF16: 4}
 
@@ -51,7 +52,8 @@ class WgRuns(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("start", ctypes.c_void_p), ("len", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("plane", ctypes.c_void_p),
                 ("ou", ctypes.c_void_p), ("ov", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
-                ("plan", ctypes.c_void_p), ("plan_elems", ctypes.c_int64), ("work", ctypes.c_void_p)]
+                ("plan", ctypes.c_void_p), ("plan_elems", ctypes.c_int64), ("work", ctypes.c_void_p),
+                ("grid", ctypes.c_void_p), ("norm", ctypes.c_void_p)]
 
 
 _lib = None
@@ -161,31 +163,33 @@ def wg_finalise_ws_bytes(geom: WgGeom) -> int:
     return int(ws.value)
 
 
-def wg_finalise(geom: WgGeom, grid: torch.Tensor, stats: torch.Tensor, image: torch.Tensor, ws: torch.Tensor,
+def wg_finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, image: torch.Tensor, ws: torch.Tensor,
                 stream=None):
-    _check(lib().wg_finalise(ctypes.byref(geom), _p(grid), _p(stats), _p(image), _p(ws), ws.numel() * ws.element_size(),
-                             _stream(stream)), "wg_finalise")
+    _check(lib().wg_finalise(ctypes.byref(geom), _p(grid), _p(normaliser), _p(image), _p(ws),
+                             ws.numel() * ws.element_size(), _stream(stream)), "wg_finalise")
 
 
-def finalise(geom: WgGeom, grid: torch.Tensor, stats: torch.Tensor, out=None, ws=None, stream=None) -> torch.Tensor:
-    """Dirty image float32 [n][n] from a complex64 [n][n] grid and device statistics."""
+def finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, out=None, ws=None, stream=None) -> torch.Tensor:
+    """Dirty image float32 [n][n] from a complex64 [n][n] grid; `normaliser` is a one-element
+    float64 device tensor (a view of the statistics or of the per-channel normalisers)."""
     n = geom.n
     if out is None:
         out = torch.empty((n, n), dtype=torch.float32, device=grid.device)
     if ws is None:
         ws = torch.empty(wg_finalise_ws_bytes(geom), dtype=torch.uint8, device=grid.device)
-    wg_finalise(geom, torch.view_as_real(grid.contiguous()), stats, out, ws, stream)
+    wg_finalise(geom, torch.view_as_real(grid.contiguous()), normaliser, out, ws, stream)
     return out
 
 
 # -------------------------------------------------------------------------- owning helpers
-def make_geom(n, beta, n_w, s_lo, s_hi, m_img, du, w_max, compress=True) -> WgGeom:
-    return WgGeom(int(n), int(beta), int(n_w), int(s_lo), int(s_hi), int(m_img), float(du), float(w_max),
-                  WG_COMPRESS if compress else 0, 0)
+def make_geom(n, beta, n_w, s_lo, s_hi, m_img, du, w_max, compress=True, per_channel=False) -> WgGeom:
+    flags = (WG_COMPRESS if compress else 0) | (WG_GRID_PER_CHANNEL if per_channel else 0)
+    return WgGeom(int(n), int(beta), int(n_w), int(s_lo), int(s_hi), int(m_img), float(du), float(w_max), flags, 0)
 
 
-def geom_from_dict(d: dict, compress=True) -> WgGeom:
-    return make_geom(d["n"], d["beta"], d["n_w"], d["s_lo"], d["s_hi"], d["m_img"], d["du"], d["w_max"], compress)
+def geom_from_dict(d: dict, compress=True, per_channel=False) -> WgGeom:
+    return make_geom(d["n"], d["beta"], d["n_w"], d["s_lo"], d["s_hi"], d["m_img"], d["du"], d["w_max"], compress,
+                     per_channel)
 
 
 class KernelTable:
@@ -231,7 +235,7 @@ class Stats:
 class Runs:
     """Run list + plan + device statistics for one record batch."""
 
-    def __init__(self, capacity: int, n_segments: int, device="cuda"):
+    def __init__(self, capacity: int, n_segments: int, device="cuda", n_grids: int = 1):
         dev = torch.device(device)
         cap = max(1, int(capacity))
         self.capacity = cap
@@ -247,8 +251,18 @@ class Runs:
         self.plan = torch.empty(pe, dtype=torch.int32, device=dev)
         self.work = torch.empty(2 * cap, dtype=torch.float32, device=dev)
         self.stats_d = torch.zeros(8, dtype=torch.int64, device=dev)
+        # per-channel grids: the grid of each run and the normaliser of each grid
+        self.n_grids = int(n_grids)
+        self.grid = torch.empty(cap, dtype=torch.int16, device=dev) if n_grids > 1 else None
+        self.norm = torch.zeros(n_grids, dtype=torch.float64, device=dev) if n_grids > 1 else None
         self.c = WgRuns(cap, _p(self.start), _p(self.len), _p(self.x), _p(self.y), _p(self.plane), _p(self.ou),
-                        _p(self.ov), _p(self.gamma), _p(self.plan), pe, _p(self.work))
+                        _p(self.ov), _p(self.gamma), _p(self.plan), pe, _p(self.work), _p(self.grid), _p(self.norm))
+
+    def normaliser(self, g: int | None = None) -> torch.Tensor:
+        """One-element float64 device view of the normaliser (of grid g with per-channel grids)."""
+        if g is None:
+            return self.stats_d.view(torch.float64)[6:7]
+        return self.norm[g:g + 1]
 
     def stats(self) -> Stats:
         h = self.stats_d.cpu()
@@ -261,7 +275,9 @@ class Runs:
                     x=self.x[:n].cpu().numpy(), y=self.y[:n].cpu().numpy(),
                     plane=self.plane[:n].cpu().numpy(), ou=self.ou[:n].cpu().numpy(),
                     ov=self.ov[:n].cpu().numpy(),
-                    gamma=torch.view_as_complex(self.gamma[: 2 * n].view(n, 2)).cpu().numpy(), n_runs=n)
+                    gamma=torch.view_as_complex(self.gamma[: 2 * n].view(n, 2)).cpu().numpy(), n_runs=n,
+                    grid=None if self.grid is None else self.grid[:n].cpu().numpy(),
+                    norm=None if self.norm is None else self.norm.cpu().numpy())
 
 
 def _f32_view(vis: torch.Tensor) -> torch.Tensor:
@@ -279,30 +295,46 @@ class Gridder:
         self.nb, self.nt = int(uvw.shape[0]), int(uvw.shape[1])
         self.nc = int(inv_lambda.shape[0])
         self.n_rec = self.nb * self.nc * self.nt
-        self.runs = Runs(self.n_rec, self.nb * self.nc, device=uvw.device)
+        self.per_channel = bool(geom.flags & WG_GRID_PER_CHANNEL)
+        self.n_grids = self.nc if self.per_channel else 1
+        self.runs = Runs(self.n_rec, self.nb * self.nc, device=uvw.device, n_grids=self.n_grids)
+
+    def grid_shape(self):
+        n = self.geom.n
+        return (self.nc, n, n) if self.per_channel else (n, n)
 
     def compress(self, vis, stream=None):
         wg_compress(self.geom, self.table.kt, self.uvw, self.inv_lambda, _f32_view(vis.contiguous()), self.weight,
                     self.flag, self.nb, self.nc, self.nt, self.runs.c, self.runs.stats_d, stream)
 
     def grid(self, out=None, stream=None):
-        n = self.geom.n
+        """Accumulate the batch into a complex64 grid ([n][n], or [nc][n][n] per channel)."""
         if out is None:
-            out = torch.zeros((n, n), dtype=torch.complex64, device=self.uvw.device)
+            out = torch.zeros(self.grid_shape(), dtype=torch.complex64, device=self.uvw.device)
         wg_grid(self.geom, self.table.kt, self.runs.c, self.runs.stats_d, torch.view_as_real(out), stream)
         return out
 
     def degrid(self, grid, out=None, stream=None):
+        if tuple(grid.shape) != self.grid_shape():
+            raise ValueError(f"grid shape {tuple(grid.shape)} != {self.grid_shape()}")
         if out is None:
             out = torch.empty((self.nb, self.nc, self.nt), dtype=torch.complex64, device=self.uvw.device)
         wg_degrid(self.geom, self.table.kt, self.runs.c, self.runs.stats_d, torch.view_as_real(grid.contiguous()),
                   self.uvw, self.weight, self.nb, self.nc, self.nt, torch.view_as_real(out), stream)
         return out
 
-
     def finalise(self, grid, out=None, stream=None):
-        """Dirty image of `grid` with this batch's normaliser (wg_finalise)."""
-        return finalise(self.geom, grid, self.runs.stats_d, out=out, stream=stream)
+        """Dirty image(s) of `grid` with this batch's normaliser(s) (wg_finalise): float32
+        [n][n], or [nc][n][n] for per-channel grids (each with its channel's normaliser)."""
+        if not self.per_channel:
+            return finalise(self.geom, grid, self.runs.normaliser(), out=out, stream=stream)
+        n = self.geom.n
+        if out is None:
+            out = torch.empty((self.nc, n, n), dtype=torch.float32, device=grid.device)
+        ws = torch.empty(wg_finalise_ws_bytes(self.geom), dtype=torch.uint8, device=grid.device)
+        for c in range(self.nc):
+            finalise(self.geom, grid[c], self.runs.normaliser(c), out=out[c], ws=ws, stream=stream)
+        return out
 
 
 class GridFn(torch.autograd.Function):

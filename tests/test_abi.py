@@ -73,7 +73,7 @@ def test_entry_points_reject_null_arguments(wg):
     L = wg.lib()
     g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)
     kt = wg.WgKtable(0, 8, 8, 7, 1, 1, 1, 1, 1, 10)
-    runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, 1)
+    runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, 1, None, None)
     by = ctypes.byref
     assert L.wg_compress(by(g), by(kt), None, None, None, None, None, 1, 1, 1, by(runs), None, None) == wg.WG_EINVAL
     assert L.wg_compress(None, by(kt), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
@@ -86,7 +86,7 @@ def test_entry_points_reject_null_arguments(wg):
     assert L.wg_grid(by(g), None, by(runs), 1, 1, None) == wg.WG_EINVAL
     assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, None, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
     assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, 5, 1, 3, 1, None) == wg.WG_ECAPACITY
-    runs_nowork = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, None)
+    runs_nowork = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, None, None, None)
     assert L.wg_degrid(by(g), by(kt), by(runs_nowork), 1, 1, 1, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
     assert L.wg_ktable_build(by(g), None, 1, 10, None, None, None) == wg.WG_EINVAL
     kt_small = wg.WgKtable(0, 8, 8, 0, 1, 1, 1, 1, 1, 10)
@@ -112,3 +112,24 @@ def test_finaliser_sizes_and_rejections(wg):
     assert L.wg_finalise(by(g), 1, None, 1, 1, ws, None) == wg.WG_EINVAL
     assert L.wg_finalise(by(g), 1, 1, 1, 1, ws - 1, None) == wg.WG_ECAPACITY
     assert L.wg_finalise(by(g_odd), 1, 1, 1, 1, ws, None) == wg.WG_EUNSUPPORTED
+
+
+def test_per_channel_grids_need_their_arrays(wg):
+    """WG_GRID_PER_CHANNEL requires the per-run grid indices and the per-channel normalisers
+    in wg_runs; unknown flag bits are rejected."""
+    L = wg.lib()
+    by = ctypes.byref
+    g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, per_channel=True)
+    kt = wg.WgKtable(0, 8, 8, 7, 1, 1, 1, 1, 1, 10)
+    runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, 1, None, None)
+    assert L.wg_compress(by(g), by(kt), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
+    assert L.wg_grid(by(g), by(kt), by(runs), 1, 1, None) == wg.WG_EINVAL
+    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
+    big = wg.WgRuns(1 << 20, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 24, 1, 1, 1)
+    # 32 channels of 8192^2 cells (2^31) exceed the 31-bit cell index of per-channel grids
+    g2 = wg.make_geom(8192, 8, 8, 7, 7, 256, 15.0, 100.0, per_channel=True)
+    assert L.wg_compress(by(g2), by(kt), 1, 1, 1, None, None, 1, 32, 1, by(big), 1, None) == wg.WG_EUNSUPPORTED
+    g_bad = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)
+    g_bad.flags = 8
+    size = ctypes.c_int64(0), ctypes.c_size_t(0)
+    assert L.wg_ktable_sizes(by(g_bad), by(size[0]), by(size[1])) == wg.WG_EINVAL
