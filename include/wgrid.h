@@ -62,6 +62,11 @@ typedef enum wg_kdtype {
 #define WG_GRID_PER_CHANNEL 2u /* one grid per channel, as the thesis's imaging tool sets up one
                                   WImager instance per channel; without it every channel goes to
                                   one grid (the channel interleaving of its Data Set 0 runs)  */
+#define WG_W_STACKING 4u       /* w-stacking (eq. stacking): one grid per w-plane, every record
+                                  gridded with the w = 0 kernel (plane 0's support, slices and
+                                  zeta) on the grid of its w-plane; the w-term is applied in the
+                                  image plane by wg_finalise_stacked. Excludes
+                                  WG_GRID_PER_CHANNEL.                                         */
 
 /* Limits of this build. */
 #define WG_MAX_SUPPORT 63    /* largest kernel support (odd)                            */
@@ -82,7 +87,8 @@ typedef enum wg_kdtype {
  *           beta*m_img <= WG_MAX_FFT, and (s_hi-1)/2*beta + beta/2 < beta*m_img/2).
  *   du      uv cell size in wavelengths (> 0); the image field of view is 1/du.
  *   w_max   largest |w| tabulated, wavelengths (>= 0).
- *   flags   WG_COMPRESS and/or WG_GRID_PER_CHANNEL, or 0.
+ *   flags   WG_COMPRESS, and at most one of WG_GRID_PER_CHANNEL and WG_W_STACKING; or 0
+ *           (unknown bits or both grid modes: WG_EINVAL).
  */
 typedef struct wg_geom {
     int32_t n;
@@ -138,7 +144,9 @@ typedef struct wg_ktable {
  * wg_degrid calls on the same runs must not overlap in time.
  * With WG_GRID_PER_CHANNEL, `grid` (one int16 per run: the channel of its records, i.e. the
  * grid it goes to) and `norm` (one double per channel: that channel's normaliser N of eq.
- * normalizer) are required and written by wg_compress; otherwise they may be NULL. `work` is scratch that wg_degrid overwrites (one
+ * normalizer) are required and written by wg_compress. With WG_W_STACKING, `grid` is
+ * required and holds the run's w-plane (its grid), `plane` is 0 (the kernel used) and `norm`
+ * may be NULL (the one normaliser is in the statistics). Otherwise both may be NULL. `work` is scratch that wg_degrid overwrites (one
  * complex float per run). Every array has `capacity` entries (gamma and work 2x); capacity
  * must be >= nb*nc*nt, so the run list can never overflow.
  */
@@ -230,8 +238,8 @@ int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const 
 /*
  * Gridding phase (eq. gridding): for every run, grid[row0+i][a+j] += gamma * K[i][j] with
  * a = x + n/2 - H, row0 = y + n/2 - H, K the run's matrix. ACCUMULATES into `grid`
- * (complex64 [n][n], or [nc][n][n] with WG_GRID_PER_CHANNEL, run q going to grid
- * runs->grid[q]); the caller zeroes it first. Accumulation is FP32 with Kahan
+ * (complex64 [n][n], or [nc][n][n] with WG_GRID_PER_CHANNEL or [n_w][n][n] with
+ * WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first. Accumulation is FP32 with Kahan
  * compensation per owned cell between commits; commits use FP32 atomic adds, so the last
  * bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
  * Errors: WG_EINVAL, WG_EHIP.
@@ -241,8 +249,8 @@ int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg
 
 /*
  * Adjoint of wg_compress + wg_grid with respect to the visibilities: per run
- * d = sum_ij conj(K[i][j]) * grid[row0+i][a+j] (grid complex64 [n][n], or [nc][n][n] read
- * at grid runs->grid[q] with WG_GRID_PER_CHANNEL; FP32, pairwise/tree summation; partial sums
+ * d = sum_ij conj(K[i][j]) * grid[row0+i][a+j] (grid complex64 [n][n], or [nc][n][n] / [n_w][n][n]
+ * read at grid runs->grid[q] with WG_GRID_PER_CHANNEL / WG_W_STACKING; FP32, pairwise/tree summation; partial sums
  * of the waves sharing a run are combined with FP32 atomic adds into runs->work, so the last
  * bits depend on scheduling); record r of the run gets weight_r * (d, or conj(d) when
  * w_r(metres) < 0); records in no run get 0. OVERWRITES vis_out (complex64 [nb][nc][nt]) and
@@ -266,14 +274,31 @@ int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const 
  *   grid   complex64 [n][n] (device, read only)
  *   normaliser  device double
  *   image  float32 [n][n] (device, OVERWRITTEN)
- *   ws     device workspace of wg_finalise_ws_bytes bytes (two n x n complex64 buffers,
- *          twiddles, corrections)
+ *   ws     device workspace of wg_finalise_ws_bytes bytes (two n x n complex64 buffers, one
+ *          n x n float32 accumulator, twiddles, corrections; the same size serves
+ *          wg_finalise_stacked)
  * n must be a power of two, 16..8192 (one FP32 complex row in 64 KB of LDS).
  * Errors: WG_EINVAL, WG_ECAPACITY (ws too small), WG_EUNSUPPORTED (n), WG_EHIP.
  */
 int wg_finalise_ws_bytes(const wg_geom *g, size_t *ws_bytes);
 int wg_finalise(const wg_geom *g, const float *grid, const double *normaliser, float *image, void *ws,
                 size_t ws_bytes, wg_stream_t stream);
+
+/*
+ * W-stacking image (eq. stacking): the w-plane grids of WG_W_STACKING are each inverse
+ * transformed, multiplied in the image plane by the plane's w-term correction
+ * exp(+2 pi i w_k (sqrt(1 - l^2 - m^2) - 1)) (0 where l^2 + m^2 > 1), w_k = w_max (k/(n_w-1))^2
+ * the plane's w, and added; then, as in wg_finalise, the real part over the normaliser,
+ * divided by the taper and sinc corrections. The correction is the image-plane factor that
+ * the w-projection kernel of plane k carries (eq. C_W), so the stacked image equals the
+ * w-projection image up to the truncation of the kernels to their supports.
+ *   grids  complex64 [n_w][n][n] (device, read only), grid k holding w-plane k's records
+ *   normaliser, image, ws as for wg_finalise (ws of wg_finalise_ws_bytes bytes). The
+ *   accumulation over planes is FP32, plane by plane in order.
+ * Errors: as wg_finalise; WG_EINVAL also when g->flags lacks WG_W_STACKING.
+ */
+int wg_finalise_stacked(const wg_geom *g, const float *grids, const double *normaliser, float *image, void *ws,
+                        size_t ws_bytes, wg_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,10 @@ shares no code with it.
                                oversampling corrections), numpy.
 * `per_channel`             -- one grid per channel: each channel's records compressed,
                                gridded and normalised on their own.
+* `w_stacking`              -- eq. stacking: records partitioned by w-plane, each part
+                               gridded with the w = 0 kernel on a grid of its own.
+* `image.finalise_stacked`  -- the w-plane grids transformed, corrected for their w-term in
+                               the image plane and added, then finalised.
 
 Parity unpinned: none of the functions here; every one is pinned by the tests listed in
 the design notes (closed forms, invariants, brute force on tiny inputs).
@@ -160,3 +164,41 @@ def per_channel(geom, table, uvw, inv_lambda, vis, weight=None, flag=None, compr
         grids.append(grid(geom, table, r))
         norms.append(r["normaliser"])
     return runs, np.stack(grids), np.array(norms)
+
+
+def plane0_table(geom, table):
+    """The w = 0 plane of `table` as a one-plane table (with geometry dict(geom, n_w=1))."""
+    off = np.asarray(table["offset"], dtype=np.int64)
+    zeta = np.asarray(table["zeta"], dtype=np.float64).reshape(geom["n_w"], -1)
+    return dict(support=np.asarray(table["support"])[:1], offset=off[:2], wbound=np.asarray(table["wbound"])[:1],
+                zeta=zeta[:1].copy(), data=np.asarray(table["data"])[: off[1]])
+
+
+def w_stacking(geom, table, uvw, inv_lambda, vis, weight=None, flag=None, compress_runs=True):
+    """W-stacking (eq. stacking): each record belongs to the w-plane that w-projection would
+    give it (nearest plane in sqrt(w), after the flip of eq. conj); the records of plane j are
+    compressed and gridded with the w = 0 kernel (plane 0 of `table`: its support, slices and
+    zeta) on grid j. Returns the per-plane run lists (on the one-plane table), the grids
+    complex128 [n_w][n][n] and the normaliser (eq. normalizer with the w = 0 zeta)."""
+    vis = np.asarray(vis)
+    k = index(geom, table, uvw, inv_lambda, flag)[:, 2].reshape(vis.shape)
+    g0, t0 = dict(geom, n_w=1), plane0_table(geom, table)
+    base = np.zeros(vis.shape, dtype=bool) if flag is None else (np.asarray(flag).reshape(vis.shape) != 0)
+    runs, grids, norm = [], [], 0.0
+    for j in range(geom["n_w"]):
+        fj = (base | (k != j)).astype(np.uint8)
+        r = compress(g0, t0, uvw, inv_lambda, vis, weight, fj, compress_runs)
+        runs.append(r)
+        grids.append(grid(g0, t0, r))
+        norm += r["normaliser"]
+    return runs, np.stack(grids), norm
+
+
+def w_stacking_degrid(geom, table, runs, grids, uvw, weight, shape):
+    """Adjoint of `w_stacking`'s gridding: every record is read back from the grid of its
+    plane with the w = 0 kernel (each record is in one plane's runs at most)."""
+    g0, t0 = dict(geom, n_w=1), plane0_table(geom, table)
+    out = np.zeros(shape, dtype=np.complex128)
+    for j, r in enumerate(runs):
+        out += degrid(g0, t0, r, grids[j], uvw, weight, shape)
+    return out

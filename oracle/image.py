@@ -14,6 +14,11 @@ Algorithm finalizer, one polarisation:
 4. division by sinc(pi l du / beta) sinc(pi m du / beta), the attenuation by the nearest
    oversampled kernel sample (eq. coversampled).
 
+W-stacking (eq. stacking) transforms each w-plane grid, multiplies it by the plane's w-term
+correction exp(+2 pi i w_k (sqrt(1 - l^2 - m^2) - 1)) in the image plane (0 where l^2 + m^2
+> 1), the factor that the w-projection kernel of plane k carries (eq. C_W), and adds the
+planes before step 2.
+
 Pixels where the taper is zero (l or m = -FOV/2, the first row and column) are set to 0, and
 so is the whole image when the normaliser is 0 (nothing was gridded; the thesis leaves this
 case open).
@@ -22,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .ktable import taper
+from .ktable import plane_w, taper
 
 
 def axis_correction(geom: dict) -> np.ndarray:
@@ -35,13 +40,50 @@ def axis_correction(geom: dict) -> np.ndarray:
     return t * np.sinc(x / (2.0 * beta))        # l du / beta; numpy sinc(x) = sin(pi x) / (pi x)
 
 
+def transform(geom: dict, grid: np.ndarray) -> np.ndarray:
+    """Step 1: sum_cells G e^{+2 pi i (u l + v m)} at every pixel, complex [N][N]."""
+    n = geom["n"]
+    g = np.asarray(grid, dtype=np.complex128)
+    return np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(g))) * float(n * n)
+
+
+def w_correction(geom: dict, k: int) -> np.ndarray:
+    """exp(+2 pi i w_k (n - 1)), n = sqrt(1 - l^2 - m^2), at every pixel [q (m)][p (l)] for
+    w-plane k (0 where l^2 + m^2 > 1)."""
+    n, du = geom["n"], geom["du"]
+    lm = (np.arange(n) - n // 2) / (n * du)
+    rr = 1.0 - lm[None, :] ** 2 - lm[:, None] ** 2
+    w = plane_w(k, geom["n_w"], geom["w_max"])
+    f = np.exp(2j * np.pi * w * (np.sqrt(np.maximum(rr, 0.0)) - 1.0))
+    f[rr < 0.0] = 0.0
+    return f
+
+
+def stacked_transform(geom: dict, grids: np.ndarray) -> np.ndarray:
+    """Eq. stacking before step 2: sum over planes k of transform(G_k) * w_correction(k)."""
+    out = np.zeros((geom["n"], geom["n"]), dtype=np.complex128)
+    for k in range(geom["n_w"]):
+        out += transform(geom, grids[k]) * w_correction(geom, k)
+    return out
+
+
+def finalise_stacked(geom: dict, grids: np.ndarray, normaliser: float) -> np.ndarray:
+    """Dirty image from the [n_w][N][N] w-plane grids of w-stacking."""
+    if normaliser == 0.0:
+        return np.zeros((geom["n"], geom["n"]))
+    return _steps_2_to_4(geom, stacked_transform(geom, grids), normaliser)
+
+
 def finalise(geom: dict, grid: np.ndarray, normaliser: float) -> np.ndarray:
     """Dirty image, float64 [N][N] (row m, column l), from a complex [N][N] grid."""
     n = geom["n"]
     if normaliser == 0.0:
         return np.zeros((n, n))
-    g = np.asarray(grid, dtype=np.complex128)
-    img = np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(g))) * float(n * n)
+    return _steps_2_to_4(geom, transform(geom, grid), normaliser)
+
+
+def _steps_2_to_4(geom: dict, img: np.ndarray, normaliser: float) -> np.ndarray:
+    n = geom["n"]
     c = axis_correction(geom)
     corr = np.outer(c, c)
     out = np.zeros((n, n))

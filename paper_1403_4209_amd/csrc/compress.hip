@@ -20,6 +20,7 @@ namespace {
 
 struct CArgs {
     int n, beta, lb, n_w, nc, nt, compress;
+    int stack;  // w-stacking: every record takes plane 0's kernel; its w-plane picks its grid
     int64_t n_seg;
     double uv_scale;
     const double *uvw;
@@ -36,7 +37,7 @@ struct CArgs {
     float2 *gamma;
     int32_t *plan, *items, *segcnt, *tiles;
     wg_stats *stats;
-    int16_t *grid_id;  // per-channel grids: the grid (channel) of each run, else NULL
+    int16_t *grid_id;  // the grid of each run (its channel, or its w-plane when stacking), else NULL
     double *norm;      // per-channel grids: the normaliser of each channel, else NULL
 };
 
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(256) void k_segments(CArgs a) {
     __shared__ BlockAgg agg;
     for (int i = threadIdx.x; i < a.n_w; i += blockDim.x) {
         s_wb[i] = a.wbound[i];
-        s_sup[i] = a.support[i];
+        s_sup[i] = a.support[a.stack ? 0 : i];  // stacking: plane 0's support for every plane
     }
     if (threadIdx.x < 64) {
         agg.cnt[threadIdx.x] = 0;
@@ -280,7 +281,7 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
                 vr = e * v.x;
                 vi = e * ((float)key.psi * v.y);
                 const int sigma = (key.ov + (a.beta >> 1) - 1) * a.beta + (key.ou + (a.beta >> 1) - 1);
-                my_norm += (double)e * a.zeta[(int64_t)key.k * nbeta2 + sigma];
+                my_norm += (double)e * a.zeta[(int64_t)(a.stack ? 0 : key.k) * nbeta2 + sigma];
             }
             const uint64_t gle = gm & (lt | (1ull << lane));
             const int seg_start = gle ? 63 - __clzll(gle) : -1;
@@ -301,10 +302,10 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
                 a.start[j] = (int32_t)r;
                 a.x[j] = key.X;
                 a.y[j] = key.Y;
-                a.plane[j] = (int16_t)key.k;
+                a.plane[j] = (int16_t)(a.stack ? 0 : key.k);
                 a.ou[j] = (int8_t)key.ou;
                 a.ov[j] = (int8_t)key.ov;
-                if (a.grid_id) a.grid_id[j] = (int16_t)ch;
+                if (a.grid_id) a.grid_id[j] = (int16_t)(a.stack ? key.k : ch);
             }
             const int cnext = __shfl_down((int)c, 1, kWave);
             const bool last_in_seg = (t == a.nt - 1);
@@ -457,9 +458,14 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
         return WG_EINVAL;
     const int64_t n_seg = nb * nc;
     const bool per_channel = (g->flags & WG_GRID_PER_CHANNEL) != 0;
+    const bool stack = (g->flags & WG_W_STACKING) != 0;
     if (per_channel) {
         if (!runs->grid || !runs->norm) return WG_EINVAL;
         if (nc > 32767 || (int64_t)nc * g->n * g->n >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
+    }
+    if (stack) {
+        if (!runs->grid) return WG_EINVAL;
+        if ((int64_t)g->n_w * g->n * g->n >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
     }
     if (runs->capacity < n_rec) return WG_ECAPACITY;
     if (runs->plan_elems < wg_plan_elems(runs->capacity, n_seg)) return WG_ECAPACITY;
@@ -473,6 +479,7 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
     a.nc = nc;
     a.nt = nt;
     a.compress = (g->flags & WG_COMPRESS) ? 1 : 0;
+    a.stack = stack ? 1 : 0;
     a.n_seg = n_seg;
     a.uv_scale = (double)g->beta / g->du;
     a.uvw = uvw;
@@ -496,7 +503,7 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
     a.segcnt = runs->plan + plan_segcnt_at(runs->capacity);
     a.tiles = runs->plan + plan_tiles_at(runs->capacity, n_seg);
     a.stats = stats;
-    a.grid_id = per_channel ? runs->grid : nullptr;
+    a.grid_id = (per_channel || stack) ? runs->grid : nullptr;
     a.norm = per_channel ? runs->norm : nullptr;
 
     hipStream_t s = (hipStream_t)stream;

@@ -22,7 +22,7 @@ struct GArgs {
     const int8_t *ou, *ov;
     const float2 *gamma;
     const int32_t *plan, *items;
-    const int16_t *grid_id;  // per-channel grids: the grid of each run (else NULL)
+    const int16_t *grid_id;  // the grid of each run (its channel or its w-plane), else NULL
     int64_t cells;           // cells of one grid (n*n)
     int32_t *queue;  // work-list counter and exit count of this kernel (two plan words)
     const int64_t *offset;
@@ -607,7 +607,7 @@ GArgs make_args(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs) {
     a.ov = runs->ov;
     a.gamma = (const float2 *)runs->gamma;
     a.plan = runs->plan;
-    a.grid_id = (g->flags & WG_GRID_PER_CHANNEL) ? runs->grid : nullptr;
+    a.grid_id = (g->flags & (WG_GRID_PER_CHANNEL | WG_W_STACKING)) ? runs->grid : nullptr;
     a.cells = (int64_t)g->n * g->n;
     a.queue = nullptr;
     a.items = runs->plan + plan_items_at();
@@ -626,7 +626,7 @@ int check_runs(const wg_geom *g, const wg_runs *runs) {
     if (!runs || !runs->start || !runs->len || !runs->x || !runs->y || !runs->plane || !runs->ou ||
         !runs->ov || !runs->gamma || !runs->plan || runs->capacity < 1)
         return WG_EINVAL;
-    if ((g->flags & WG_GRID_PER_CHANNEL) && !runs->grid) return WG_EINVAL;
+    if ((g->flags & (WG_GRID_PER_CHANNEL | WG_W_STACKING)) && !runs->grid) return WG_EINVAL;
     return WG_OK;
 }
 

@@ -10,6 +10,11 @@
 // Pixels where the taper is zero (the first row and column, l or m = -FOV/2) are 0, and the
 // whole image is 0 when the normaliser is 0 (nothing was gridded).
 //
+// W-stacking (eq. stacking) adds, before step 2, the sum over the w-plane grids of their
+// transforms times the plane's image-plane w-term correction exp(+2 pi i w_k (n - 1)),
+// n = sqrt(1 - l^2 - m^2): the factor that the w-projection kernel of plane k carries
+// (eq. C_W), applied after the transform instead of by the kernel.
+//
 // Layout of the work: row transforms (one workgroup per row, an N-point FP32 Stockham FFT in
 // LDS with radix-16 passes in registers), a tiled transpose, row transforms again, and a
 // tiled transposing pass that applies steps 2-4 while writing the image row-major. The
@@ -175,15 +180,40 @@ __global__ void k_fin_setup(float2 *tw, double *corr, int n, int beta, TaperCoef
     corr[j] = taper(x, tc) / taper(0.0, tc) * sinc;
 }
 
+__device__ inline float re_of(float2 v) { return v.x; }
+__device__ inline float re_of(float v) { return v; }
+
+// W-stacking: acc[p][q] (+)= Re(T[p][q] * exp(+2 pi i w (n - 1))) for plane k's transformed,
+// transposed grid T (row p = l index, column q = m index); the first plane writes. The
+// correction is 0 where l^2 + m^2 > 1 (no direction there).
+__global__ void k_stack_acc(const float2 *__restrict__ T, float *__restrict__ acc, int n, double du, double w,
+                            int first) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    const int p = (int)(e / n), q = (int)(e - (int64_t)p * n);
+    const double l = (double)(p - n / 2) / ((double)n * du), m = (double)(q - n / 2) / ((double)n * du);
+    const double rr = 1.0 - l * l - m * m;
+    float v = 0.0f;
+    if (rr >= 0.0) {
+        double s, c;
+        sincospi(2.0 * w * (sqrt(rr) - 1.0), &s, &c);
+        const float2 t = T[e];
+        v = (float)((double)t.x * c - (double)t.y * s);
+    }
+    acc[e] = first ? v : acc[e] + v;
+}
+
 // image[q][p] = Re(T[p][q]) / (normaliser * corr[q] * corr[p]) (0 where the product is 0 or
-// the normaliser is 0), T the twice-transformed, transposed grid; 32 x 32 tiles.
-__global__ void k_fin_out(const float2 *__restrict__ T, const double *__restrict__ corr,
+// the normaliser is 0), T the twice-transformed, transposed grid (or the w-stacking sum of
+// real parts); 32 x 32 tiles.
+template <typename In>
+__global__ void k_fin_out(const In *__restrict__ T, const double *__restrict__ corr,
                           const double *__restrict__ normaliser, float *__restrict__ image, int n) {
     __shared__ float tile[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     for (int i = threadIdx.y; i < 32; i += blockDim.y) {
         const int r = by + i, c = bx + threadIdx.x;  // T row r = l index p, column c = m index q
-        if (r < n && c < n) tile[i][threadIdx.x] = T[(size_t)r * n + c].x;
+        if (r < n && c < n) tile[i][threadIdx.x] = re_of(T[(size_t)r * n + c]);
     }
     __syncthreads();
     const double norm = *normaliser;
@@ -197,7 +227,7 @@ __global__ void k_fin_out(const float2 *__restrict__ T, const double *__restrict
 }
 
 struct FinLayout {
-    size_t a, b, tw, corr, total;
+    size_t a, b, acc, tw, corr, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -207,7 +237,8 @@ FinLayout fin_layout(int n) {
     const size_t nn = (size_t)n * n;
     l.a = 0;
     l.b = align256(l.a + sizeof(float2) * nn);
-    l.tw = align256(l.b + sizeof(float2) * nn);
+    l.acc = align256(l.b + sizeof(float2) * nn);
+    l.tw = align256(l.acc + sizeof(float) * nn);
     l.corr = align256(l.tw + sizeof(float2) * n);
     l.total = align256(l.corr + sizeof(double) * n);
     return l;
@@ -233,12 +264,16 @@ extern "C" int wg_finalise_ws_bytes(const wg_geom *g, size_t *ws_bytes) {
     return WG_OK;
 }
 
-extern "C" int wg_finalise(const wg_geom *g, const float *grid, const double *normaliser, float *image, void *ws,
-                           size_t ws_bytes, wg_stream_t stream) {
-    using namespace wg;
+namespace wg {
+namespace {
+
+// Both finalisers: one grid (stacked = false) or the n_w w-plane grids of w-stacking.
+int finalise(const wg_geom *g, const float *grid, const double *normaliser, float *image, void *ws,
+             size_t ws_bytes, wg_stream_t stream, bool stacked) {
     const int st = check_geom(g);
     if (st != WG_OK) return st;
     if (!grid || !normaliser || !image || !ws) return WG_EINVAL;
+    if (stacked && !(g->flags & WG_W_STACKING)) return WG_EINVAL;
     const int n = g->n, lg = image_lg(n);
     if (lg < 0) return WG_EUNSUPPORTED;
     const FinLayout lay = fin_layout(n);
@@ -254,9 +289,38 @@ extern "C" int wg_finalise(const wg_geom *g, const float *grid, const double *no
     const size_t lds = sizeof(float2) * (size_t)n;
     const dim3 tiles((n + 31) / 32, (n + 31) / 32), tb(32, 8);
     hipLaunchKernelGGL(k_fin_setup, dim3((n + 255) / 256), dim3(256), 0, s, tw, corr, n, g->beta, tc);
-    hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, (const float2 *)grid, A, n, lg, tw);
-    hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
-    hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw);
-    hipLaunchKernelGGL(k_fin_out, tiles, tb, 0, s, A, corr, normaliser, image, n);
+    const int64_t nn = (int64_t)n * n;
+    const int planes = stacked ? g->n_w : 1;
+    for (int k = 0; k < planes; ++k) {
+        const float2 *G = (const float2 *)grid + (size_t)k * nn;
+        hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, G, A, n, lg, tw);
+        hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
+        hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw);
+        if (stacked) {
+            // the plane's w, computed as the table generator places its planes
+            const double q = g->n_w > 1 ? (double)k / (double)(g->n_w - 1) : 0.0;
+            const double w = g->w_max * (q * q);
+            hipLaunchKernelGGL(k_stack_acc, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A,
+                               (float *)(base + lay.acc), n, g->du, w, k == 0 ? 1 : 0);
+        }
+    }
+    if (stacked)
+        hipLaunchKernelGGL(k_fin_out<float>, tiles, tb, 0, s, (const float *)(base + lay.acc), corr, normaliser,
+                           image, n);
+    else
+        hipLaunchKernelGGL(k_fin_out<float2>, tiles, tb, 0, s, A, corr, normaliser, image, n);
     return launch_status();
+}
+
+}  // namespace
+}  // namespace wg
+
+extern "C" int wg_finalise(const wg_geom *g, const float *grid, const double *normaliser, float *image, void *ws,
+                           size_t ws_bytes, wg_stream_t stream) {
+    return wg::finalise(g, grid, normaliser, image, ws, ws_bytes, stream, false);
+}
+
+extern "C" int wg_finalise_stacked(const wg_geom *g, const float *grids, const double *normaliser, float *image,
+                                   void *ws, size_t ws_bytes, wg_stream_t stream) {
+    return wg::finalise(g, grids, normaliser, image, ws, ws_bytes, stream, true);
 }

@@ -24,6 +24,7 @@ WG_OK, WG_EINVAL, WG_ECAPACITY, WG_EHIP, WG_EUNSUPPORTED = 0, -1, -3, -4, -5
 WG_KF32, WG_KBF16, WG_KF16 = 0, 1, 2
 WG_COMPRESS = 1
 WG_GRID_PER_CHANNEL = 2
+WG_W_STACKING = 4
 DTYPES = {"f32": WG_KF32, "bf16": WG_KBF16, "f16": WG_KF16}
 _ELEM_BYTES = {WG_KF32: 8, WG_KBF16: 4, WG_KF16: 4}
 
@@ -86,6 +87,8 @@ def lib():
         L.wg_finalise_ws_bytes.argtypes = [P, P]
         L.wg_finalise.restype = ctypes.c_int
         L.wg_finalise.argtypes = [P, P, P, P, P, ctypes.c_size_t, P]
+        L.wg_finalise_stacked.restype = ctypes.c_int
+        L.wg_finalise_stacked.argtypes = [P, P, P, P, P, ctypes.c_size_t, P]
         _lib = L
     return _lib
 
@@ -169,6 +172,12 @@ def wg_finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, imag
                              ws.numel() * ws.element_size(), _stream(stream)), "wg_finalise")
 
 
+def wg_finalise_stacked(geom: WgGeom, grids: torch.Tensor, normaliser: torch.Tensor, image: torch.Tensor,
+                        ws: torch.Tensor, stream=None):
+    _check(lib().wg_finalise_stacked(ctypes.byref(geom), _p(grids), _p(normaliser), _p(image), _p(ws),
+                                     ws.numel() * ws.element_size(), _stream(stream)), "wg_finalise_stacked")
+
+
 def finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, out=None, ws=None, stream=None) -> torch.Tensor:
     """Dirty image float32 [n][n] from a complex64 [n][n] grid; `normaliser` is a one-element
     float64 device tensor (a view of the statistics or of the per-channel normalisers)."""
@@ -182,14 +191,16 @@ def finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, out=Non
 
 
 # -------------------------------------------------------------------------- owning helpers
-def make_geom(n, beta, n_w, s_lo, s_hi, m_img, du, w_max, compress=True, per_channel=False) -> WgGeom:
-    flags = (WG_COMPRESS if compress else 0) | (WG_GRID_PER_CHANNEL if per_channel else 0)
+def make_geom(n, beta, n_w, s_lo, s_hi, m_img, du, w_max, compress=True, per_channel=False,
+              w_stacking=False) -> WgGeom:
+    flags = ((WG_COMPRESS if compress else 0) | (WG_GRID_PER_CHANNEL if per_channel else 0)
+             | (WG_W_STACKING if w_stacking else 0))
     return WgGeom(int(n), int(beta), int(n_w), int(s_lo), int(s_hi), int(m_img), float(du), float(w_max), flags, 0)
 
 
-def geom_from_dict(d: dict, compress=True, per_channel=False) -> WgGeom:
+def geom_from_dict(d: dict, compress=True, per_channel=False, w_stacking=False) -> WgGeom:
     return make_geom(d["n"], d["beta"], d["n_w"], d["s_lo"], d["s_hi"], d["m_img"], d["du"], d["w_max"], compress,
-                     per_channel)
+                     per_channel, w_stacking)
 
 
 class KernelTable:
@@ -235,7 +246,7 @@ class Stats:
 class Runs:
     """Run list + plan + device statistics for one record batch."""
 
-    def __init__(self, capacity: int, n_segments: int, device="cuda", n_grids: int = 1):
+    def __init__(self, capacity: int, n_segments: int, device="cuda", grid_ids: bool = False, n_norms: int = 0):
         dev = torch.device(device)
         cap = max(1, int(capacity))
         self.capacity = cap
@@ -251,10 +262,10 @@ class Runs:
         self.plan = torch.empty(pe, dtype=torch.int32, device=dev)
         self.work = torch.empty(2 * cap, dtype=torch.float32, device=dev)
         self.stats_d = torch.zeros(8, dtype=torch.int64, device=dev)
-        # per-channel grids: the grid of each run and the normaliser of each grid
-        self.n_grids = int(n_grids)
-        self.grid = torch.empty(cap, dtype=torch.int16, device=dev) if n_grids > 1 else None
-        self.norm = torch.zeros(n_grids, dtype=torch.float64, device=dev) if n_grids > 1 else None
+        # per-channel grids and w-stacking: the grid of each run; per-channel grids: the
+        # normaliser of each grid
+        self.grid = torch.empty(cap, dtype=torch.int16, device=dev) if grid_ids else None
+        self.norm = torch.zeros(n_norms, dtype=torch.float64, device=dev) if n_norms > 0 else None
         self.c = WgRuns(cap, _p(self.start), _p(self.len), _p(self.x), _p(self.y), _p(self.plane), _p(self.ou),
                         _p(self.ov), _p(self.gamma), _p(self.plan), pe, _p(self.work), _p(self.grid), _p(self.norm))
 
@@ -296,12 +307,14 @@ class Gridder:
         self.nc = int(inv_lambda.shape[0])
         self.n_rec = self.nb * self.nc * self.nt
         self.per_channel = bool(geom.flags & WG_GRID_PER_CHANNEL)
-        self.n_grids = self.nc if self.per_channel else 1
-        self.runs = Runs(self.n_rec, self.nb * self.nc, device=uvw.device, n_grids=self.n_grids)
+        self.w_stacking = bool(geom.flags & WG_W_STACKING)
+        self.n_grids = self.nc if self.per_channel else geom.n_w if self.w_stacking else 1
+        self.runs = Runs(self.n_rec, self.nb * self.nc, device=uvw.device,
+                         grid_ids=self.per_channel or self.w_stacking, n_norms=self.nc if self.per_channel else 0)
 
     def grid_shape(self):
         n = self.geom.n
-        return (self.nc, n, n) if self.per_channel else (n, n)
+        return (self.n_grids, n, n) if (self.per_channel or self.w_stacking) else (n, n)
 
     def compress(self, vis, stream=None):
         wg_compress(self.geom, self.table.kt, self.uvw, self.inv_lambda, _f32_view(vis.contiguous()), self.weight,
@@ -325,7 +338,16 @@ class Gridder:
 
     def finalise(self, grid, out=None, stream=None):
         """Dirty image(s) of `grid` with this batch's normaliser(s) (wg_finalise): float32
-        [n][n], or [nc][n][n] for per-channel grids (each with its channel's normaliser)."""
+        [n][n], or [nc][n][n] for per-channel grids (each with its channel's normaliser); one
+        [n][n] image of the w-plane grids with w-stacking (wg_finalise_stacked)."""
+        if self.w_stacking:
+            n = self.geom.n
+            if out is None:
+                out = torch.empty((n, n), dtype=torch.float32, device=grid.device)
+            ws = torch.empty(wg_finalise_ws_bytes(self.geom), dtype=torch.uint8, device=grid.device)
+            wg_finalise_stacked(self.geom, torch.view_as_real(grid.contiguous()), self.runs.normaliser(), out, ws,
+                                stream)
+            return out
         if not self.per_channel:
             return finalise(self.geom, grid, self.runs.normaliser(), out=out, stream=stream)
         n = self.geom.n

@@ -26,7 +26,8 @@ def wg():
 def test_header_declares_entry_points():
     names = declared_functions()
     for n in ["wg_status_str", "wg_version", "wg_ktable_sizes", "wg_ktable_build", "wg_plan_elems",
-              "wg_compress", "wg_grid", "wg_degrid", "wg_finalise_ws_bytes", "wg_finalise"]:
+              "wg_compress", "wg_grid", "wg_degrid", "wg_finalise_ws_bytes", "wg_finalise",
+              "wg_finalise_stacked"]:
         assert n in names
 
 
@@ -133,3 +134,29 @@ def test_per_channel_grids_need_their_arrays(wg):
     g_bad.flags = 8
     size = ctypes.c_int64(0), ctypes.c_size_t(0)
     assert L.wg_ktable_sizes(by(g_bad), by(size[0]), by(size[1])) == wg.WG_EINVAL
+
+
+def test_w_stacking_needs_grid_ids_and_excludes_per_channel(wg):
+    """WG_W_STACKING requires the per-run grid indices (the w-plane of each run), excludes
+    WG_GRID_PER_CHANNEL, and wg_finalise_stacked refuses a geometry without it."""
+    L = wg.lib()
+    by = ctypes.byref
+    g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, w_stacking=True)
+    kt = wg.WgKtable(0, 8, 8, 7, 1, 1, 1, 1, 1, 10)
+    runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, 1, None, None)
+    assert L.wg_compress(by(g), by(kt), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
+    assert L.wg_grid(by(g), by(kt), by(runs), 1, 1, None) == wg.WG_EINVAL
+    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
+    # 128 w-planes of 4096^2 cells (2^31) exceed the 31-bit cell index
+    big = wg.WgRuns(1 << 20, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 24, 1, 1, None)
+    g2 = wg.make_geom(4096, 8, 128, 7, 7, 256, 15.0, 100.0, w_stacking=True)
+    kt2 = wg.WgKtable(0, 128, 8, 7, 1, 1, 1, 1, 1, 10)
+    assert L.wg_compress(by(g2), by(kt2), 1, 1, 1, None, None, 1, 1, 1, by(big), 1, None) == wg.WG_EUNSUPPORTED
+    both = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, per_channel=True, w_stacking=True)
+    size = ctypes.c_int64(0), ctypes.c_size_t(0)
+    assert L.wg_ktable_sizes(by(both), by(size[0]), by(size[1])) == wg.WG_EINVAL
+    plain = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)
+    assert L.wg_finalise_stacked(by(plain), 1, 1, 1, 1, 1 << 30, None) == wg.WG_EINVAL
+    ws = ctypes.c_size_t(0)
+    assert L.wg_finalise_ws_bytes(by(g), by(ws)) == wg.WG_OK
+    assert ws.value >= 256 * 256 * (8 + 8 + 4)
