@@ -51,14 +51,14 @@ def lib():
         P = ctypes.c_void_p
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.or_compress.restype = i64
-        L.or_compress.argtypes = [i32, i32, i32, f64, P, P, P, P, P, P, P, P, i64, i32, i32, i32,
+        L.or_compress.argtypes = [i32, i32, i32, f64, P, P, P, P, P, P, P, P, i64, i32, i32, i32, i32,
                                   P, P, P, P, P, P, P, P, P, P]
         L.or_index.restype = None
-        L.or_index.argtypes = [i32, i32, i32, f64, P, P, P, P, P, i64, i32, i32, P]
+        L.or_index.argtypes = [i32, i32, i32, f64, P, P, P, P, P, i64, i32, i32, i32, P]
         L.or_grid.restype = None
-        L.or_grid.argtypes = [i32, i32, P, P, P, i64, P, P, P, P, P, P, P]
+        L.or_grid.argtypes = [i32, i32, i32, P, P, P, i64, P, P, P, P, P, P, P]
         L.or_degrid.restype = None
-        L.or_degrid.argtypes = [i32, i32, P, P, P, i64, P, P, P, P, P, P, P, P, P, P, i64, i32, i32, P]
+        L.or_degrid.argtypes = [i32, i32, i32, P, P, P, i64, P, P, P, P, P, P, P, P, P, P, P, i64, i32, i32, P]
         _lib = L
     return _lib
 
@@ -75,77 +75,95 @@ def uv_scale(geom: dict) -> float:
     return float(geom["beta"]) / float(geom["du"])
 
 
+def _npol(a):
+    """Polarisations of a record array: [B][C][T] holds one, [B][C][T][P] holds P."""
+    return int(np.shape(a)[3]) if a is not None and np.ndim(a) == 4 else 1
+
+
 def index(geom, table, uvw, inv_lambda, flag=None):
-    """Per-record (X, Y, plane, o_u, o_v, psi, griddable) as int32 [N_rec, 7]."""
+    """Per-record (X, Y, plane, o_u, o_v, psi, griddable) as int32 [N_rec, 7]; `flag` is
+    [B][C][T] or per polarisation [B][C][T][P] (griddable needs one unflagged)."""
     uvw = _c(uvw, np.float64)
     inv_lambda = _c(inv_lambda, np.float64)
     nb, nt = uvw.shape[0], uvw.shape[1]
     nc = inv_lambda.shape[0]
-    flag = _c(flag, np.uint8)
+    npol = _npol(flag)
+    flag = _c(None if flag is None else np.asarray(flag).reshape(-1), np.uint8)
     out = np.zeros((nb * nc * nt, 7), dtype=np.int32)
     lib().or_index(geom["n"], geom["beta"], geom["n_w"], uv_scale(geom), _p(_c(table["wbound"], np.float64)),
-                   _p(_c(table["support"], np.int32)), _p(uvw), _p(inv_lambda), _p(flag), nb, nc, nt, _p(out))
+                   _p(_c(table["support"], np.int32)), _p(uvw), _p(inv_lambda), _p(flag), nb, nc, nt, npol,
+                   _p(out))
     return out
 
 
 def compress(geom, table, uvw, inv_lambda, vis, weight=None, flag=None, compress=True):
-    """Runs and statistics. Returns dict(start, len, x, y, plane, ou, ov, gamma (complex128),
-    stats (n_records, n_griddable, n_runs, n_compressed, upd_real, upd_saved), normaliser)."""
+    """Runs and statistics. `vis` (and `weight`, `flag`) are [B][C][T], or [B][C][T][P] for P
+    = 2 or 4 polarisations. Returns dict(start, len, x, y, plane, ou, ov, gamma (complex128,
+    [runs] or [runs][P]), stats (n_records, n_griddable, n_runs, n_compressed, upd_real,
+    upd_saved), normaliser (a float, or [P]), npol)."""
     uvw = _c(uvw, np.float64)
     inv_lambda = _c(inv_lambda, np.float64)
     nb, nt = uvw.shape[0], uvw.shape[1]
     nc = inv_lambda.shape[0]
     nrec = nb * nc * nt
+    npol = _npol(vis)
     vis = np.ascontiguousarray(np.asarray(vis, dtype=np.complex64).reshape(-1)).view(np.float32)
     weight = _c(None if weight is None else np.asarray(weight).reshape(-1), np.float32)
     flag = _c(None if flag is None else np.asarray(flag).reshape(-1), np.uint8)
     arr = {k: np.zeros(max(nrec, 1), dtype=np.int32) for k in ("start", "len", "x", "y", "plane", "ou", "ov")}
-    gamma = np.zeros(2 * max(nrec, 1), dtype=np.float64)
+    gamma = np.zeros(2 * max(nrec, 1) * npol, dtype=np.float64)
     stats = np.zeros(6, dtype=np.int64)
-    norm = ctypes.c_double(0.0)
+    norm = np.zeros(npol, dtype=np.float64)
     n = lib().or_compress(geom["n"], geom["beta"], geom["n_w"], uv_scale(geom),
                           _p(_c(table["wbound"], np.float64)), _p(_c(table["support"], np.int32)),
                           _p(_c(table["zeta"], np.float64)), _p(uvw), _p(inv_lambda), _p(vis),
-                          _p(weight), _p(flag), nb, nc, nt, int(bool(compress)),
+                          _p(weight), _p(flag), nb, nc, nt, npol, int(bool(compress)),
                           _p(arr["start"]), _p(arr["len"]), _p(arr["x"]), _p(arr["y"]), _p(arr["plane"]),
-                          _p(arr["ou"]), _p(arr["ov"]), _p(gamma), _p(stats), ctypes.byref(norm))
+                          _p(arr["ou"]), _p(arr["ov"]), _p(gamma), _p(stats), _p(norm))
     out = {k: v[:n].copy() for k, v in arr.items()}
-    out["gamma"] = gamma[:2 * n].view(np.complex128).copy()
+    gam = gamma[:2 * n * npol].view(np.complex128).copy()
+    out["gamma"] = gam if npol == 1 else gam.reshape(n, npol)
     out["stats"] = stats
-    out["normaliser"] = norm.value
+    out["normaliser"] = float(norm[0]) if npol == 1 else norm
     out["n_runs"] = int(n)
+    out["npol"] = npol
     return out
 
 
 def grid(geom, table, runs, grid_in=None):
-    """eq. gridding in FP64 over `runs`; returns a complex128 [n, n] grid (accumulates onto
-    grid_in when given)."""
+    """eq. gridding in FP64 over `runs`; returns a complex128 [n, n] grid, [n, n, P] with P
+    polarisations (accumulates onto grid_in when given)."""
     n = geom["n"]
-    g = np.zeros((n, n), dtype=np.complex128) if grid_in is None else np.array(grid_in, dtype=np.complex128)
+    npol = runs.get("npol", 1)
+    shape = (n, n) if npol == 1 else (n, n, npol)
+    g = np.zeros(shape, dtype=np.complex128) if grid_in is None else np.array(grid_in, dtype=np.complex128)
     data = np.ascontiguousarray(table["data"], dtype=np.complex128)
     gam = np.ascontiguousarray(runs["gamma"], dtype=np.complex128)
-    lib().or_grid(n, geom["beta"], _p(_c(table["support"], np.int32)), _p(_c(table["offset"], np.int64)),
+    lib().or_grid(n, geom["beta"], npol, _p(_c(table["support"], np.int32)), _p(_c(table["offset"], np.int64)),
                   _p(data), runs["n_runs"], _p(_c(runs["x"], np.int32)), _p(_c(runs["y"], np.int32)),
                   _p(_c(runs["plane"], np.int32)), _p(_c(runs["ou"], np.int32)), _p(_c(runs["ov"], np.int32)),
                   _p(gam), _p(g))
     return g
 
 
-def degrid(geom, table, runs, grid_arr, uvw, weight, shape):
-    """Adjoint of gridding (and of the weighting/flip); returns complex128 [B, C, T]."""
-    nb, nc, nt = shape
+def degrid(geom, table, runs, grid_arr, uvw, weight, shape, flag=None):
+    """Adjoint of gridding (and of the weighting/flip); returns complex128 of `shape`,
+    [B, C, T] or [B, C, T, P]."""
+    nb, nc, nt = shape[:3]
+    npol = 1 if len(shape) == 3 else int(shape[3])
     uvw = _c(uvw, np.float64)
     weight = _c(None if weight is None else np.asarray(weight).reshape(-1), np.float32)
-    out = np.zeros(nb * nc * nt, dtype=np.complex128)
+    flag = _c(None if flag is None else np.asarray(flag).reshape(-1), np.uint8)
+    out = np.zeros(nb * nc * nt * npol, dtype=np.complex128)
     g = np.ascontiguousarray(grid_arr, dtype=np.complex128)
     data = np.ascontiguousarray(table["data"], dtype=np.complex128)
-    lib().or_degrid(geom["n"], geom["beta"], _p(_c(table["support"], np.int32)),
+    lib().or_degrid(geom["n"], geom["beta"], npol, _p(_c(table["support"], np.int32)),
                     _p(_c(table["offset"], np.int64)), _p(data), runs["n_runs"],
                     _p(_c(runs["start"], np.int32)), _p(_c(runs["len"], np.int32)),
                     _p(_c(runs["x"], np.int32)), _p(_c(runs["y"], np.int32)), _p(_c(runs["plane"], np.int32)),
                     _p(_c(runs["ou"], np.int32)), _p(_c(runs["ov"], np.int32)), _p(g), _p(uvw), _p(weight),
-                    nb, nc, nt, _p(out))
-    return out.reshape(nb, nc, nt)
+                    _p(flag), nb, nc, nt, _p(out))
+    return out.reshape(shape)
 
 
 def per_channel(geom, table, uvw, inv_lambda, vis, weight=None, flag=None, compress_runs=True):

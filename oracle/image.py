@@ -19,6 +19,15 @@ correction exp(+2 pi i w_k (sqrt(1 - l^2 - m^2) - 1)) in the image plane (0 wher
 > 1), the factor that the w-projection kernel of plane k carries (eq. C_W), and adds the
 planes before step 2.
 
+Polarisations (step 2, "convert to multiple-Stokes image and normalise"): each polarised
+grid is transformed and divided by its own normaliser N_p, then the Stokes images are the
+real parts of the usual linear combinations (the thesis names the outputs, I, Q, U, V or the
+subset the polarisations allow, not the formulas; these are the standard feed relations):
+  linear   XX = I + Q, XY = U + iV, YX = U - iV, YY = I - Q;
+  circular RR = I + V, RL = Q + iU, LR = Q - iU, LL = I - V;
+so two parallel hands give (I, Q) or (I, V), four give (I, Q, U, V), and one polarisation
+is imaged as it is, as I. A polarisation whose normaliser is 0 (all flagged) adds 0.
+
 Pixels where the taper is zero (l or m = -FOV/2, the first row and column) are set to 0, and
 so is the whole image when the normaliser is 0 (nothing was gridded; the thesis leaves this
 case open).
@@ -89,4 +98,43 @@ def _steps_2_to_4(geom: dict, img: np.ndarray, normaliser: float) -> np.ndarray:
     out = np.zeros((n, n))
     nz = corr != 0.0
     out[nz] = img.real[nz] / (normaliser * corr[nz])
+    return out
+
+
+# Stokes images from the polarised images: name, coefficient of each polarisation
+STOKES = {
+    (1, False): [("I", (1.0,))],
+    (1, True): [("I", (1.0,))],
+    (2, False): [("I", (0.5, 0.5)), ("Q", (0.5, -0.5))],
+    (2, True): [("I", (0.5, 0.5)), ("V", (0.5, -0.5))],
+    (4, False): [("I", (0.5, 0, 0, 0.5)), ("Q", (0.5, 0, 0, -0.5)), ("U", (0, 0.5, 0.5, 0)),
+                 ("V", (0, -0.5j, 0.5j, 0))],
+    (4, True): [("I", (0.5, 0, 0, 0.5)), ("Q", (0, 0.5, 0.5, 0)), ("U", (0, -0.5j, 0.5j, 0)),
+                ("V", (0.5, 0, 0, -0.5))],
+}
+
+
+def finalise_stokes(geom: dict, grid: np.ndarray, normalisers, circular: bool = False) -> dict:
+    """Dirty Stokes images {name: float64 [N][N]} from a [N][N][P] polarised grid (P = 1, 2
+    or 4) and its per-polarisation normalisers."""
+    g = np.asarray(grid, dtype=np.complex128)
+    if g.ndim == 2:
+        g = g[:, :, None]
+    npol = g.shape[2]
+    norms = np.atleast_1d(np.asarray(normalisers, dtype=np.float64))
+    pol_img = []
+    for p in range(npol):
+        pol_img.append(transform(geom, g[:, :, p]) / norms[p] if norms[p] != 0.0 else None)
+    c = axis_correction(geom)
+    corr = np.outer(c, c)
+    nz = corr != 0.0
+    out = {}
+    for name, coef in STOKES[(npol, bool(circular))]:
+        acc = np.zeros((geom["n"], geom["n"]), dtype=np.complex128)
+        for p in range(npol):
+            if coef[p] != 0 and pol_img[p] is not None:
+                acc += coef[p] * pol_img[p]
+        img = np.zeros((geom["n"], geom["n"]))
+        img[nz] = acc.real[nz] / corr[nz]
+        out[name] = img
     return out
