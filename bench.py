@@ -9,8 +9,9 @@ rotation tracks and point-source visibilities) and resident in HBM before timing
 
 Prints ONE JSON line. `value` = grid-point updates per second over the step (the gridder's
 updates plus the degridder's, each sum over runs of S^2). Per-phase times, the BF16-table
-variant, the uncompressed variant, the gridder's roofline and the CPU oracle baseline are
-extra fields.
+variant, the uncompressed variant, the w-stacking variant (grid per w-plane + stacked image
+against w-projection's grid + image), the image finaliser, the table-generation study, the
+gridder's roofline and the CPU oracle baseline are extra fields.
 """
 from __future__ import annotations
 
@@ -33,7 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="skip the BF16 and uncompressed variants")
+    ap.add_argument("--no-variants", action="store_true", help="skip the table study and the BF16, uncompressed and w-stacking variants")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (to scale HBM counters)")
     return ap.parse_args()
@@ -302,6 +303,37 @@ def main():
         out["uncompressed"] = {"compress_ms": round(tcu, 4), "grid_ms": round(tgu, 4),
                                "speedup_of_compression": round((tcu + tgu) / (t_comp + t_grid), 3)}
         del gu
+
+        # w-stacking (eq. stacking) of the same records: every record gridded with the w = 0
+        # kernel (support 9) on the grid of its w-plane (32 grids of 2048^2), then the planes
+        # transformed, w-corrected and added; against w-projection's grid + finalise
+        geom_s = wg.geom_from_dict(w.geom, w_stacking=True)
+        gs_ = wg.Gridder(geom_s, table, uvw, il, weight)
+        grids = torch.zeros(gs_.grid_shape(), dtype=torch.complex64, device=dev)
+        img_s = torch.empty((geom.n, geom.n), dtype=torch.float32, device=dev)
+        tcs = tgs = tfs = 0.0
+        for i in range(args.steps + 1):
+            grids.zero_()
+            ev[0].record()
+            gs_.compress(vis)
+            ev[1].record()
+            gs_.grid(out=grids)
+            ev[2].record()
+            gs_.finalise(grids, out=img_s)
+            ev[3].record()
+            torch.cuda.synchronize()
+            if i:
+                tcs += ev[0].elapsed_time(ev[1])
+                tgs += ev[1].elapsed_time(ev[2])
+                tfs += ev[2].elapsed_time(ev[3])
+        tcs, tgs, tfs = tcs / args.steps, tgs / args.steps, tfs / args.steps
+        ss = gs_.runs.stats()
+        out["w_stacking"] = {"grids": int(geom.n_w), "compress_ms": round(tcs, 4), "grid_ms": round(tgs, 4),
+                             "finalise_stacked_ms": round(tfs, 4), "upd_real": int(ss.upd_real),
+                             "grid_gupds_real": round(ss.upd_real / (tgs * 1e-3) / 1e9, 2),
+                             "image_ms": round(tcs + tgs + tfs, 4),
+                             "w_projection_image_ms": round(t_comp + t_grid + out["finalise_ms"], 4)}
+        del gs_, grids, img_s
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, vis.cpu().numpy(), U)

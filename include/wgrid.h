@@ -23,13 +23,15 @@
  *   - No C++ exception crosses this interface.
  *   - Records: nb baselines x nc channels x nt timesteps, record r = (b*nc + ch)*nt + t.
  *     uvw is float64 [nb][nt][3] in metres (input I-1), inv_lambda float64 [nc] in 1/m
- *     (I-2), vis complex64 [nb][nc][nt] as interleaved (re, im) float32 (I-5), weight
- *     float32 [nb][nc][nt] (I-3; NULL means 1), flag uint8 [nb][nc][nt] (I-4; nonzero =
- *     flagged; NULL means none). Single polarisation.
- *   - Grid: complex64 [n][n] interleaved, row y follows v, column x follows u, cell
+ *     (I-2), vis complex64 [nb][nc][nt][P] as interleaved (re, im) float32 (I-5), weight
+ *     float32 [nb][nc][nt][P] (I-3; NULL means 1), flag uint8 [nb][nc][nt][P] (I-4;
+ *     nonzero = flagged; NULL means none), with P = g->n_pol polarisations per record
+ *     (WImager inputs: flags, weights and visibilities per polarisation).
+ *   - Grid: complex64 [n][n][P] interleaved, row y follows v, column x follows u, cell
  *     (n/2, n/2) is u = v = 0 (gridding phase, Convolution Position sequence).
  *   - Off-grid, flagged or non-finite records are not errors: they are not griddable
- *     (gridding indicator g = 0) and are counted in wg_stats.
+ *     (gridding indicator g = 0) and are counted in wg_stats. A record with at least one
+ *     unflagged polarisation is griddable; its flagged polarisations add 0.
  */
 #ifndef WGRID_H
 #define WGRID_H
@@ -62,6 +64,9 @@ typedef enum wg_kdtype {
 #define WG_GRID_PER_CHANNEL 2u /* one grid per channel, as the thesis's imaging tool sets up one
                                   WImager instance per channel; without it every channel goes to
                                   one grid (the channel interleaving of its Data Set 0 runs)  */
+#define WG_POL_CIRCULAR 8u     /* the records' products are RR, RL, LR, LL (or RR, LL) rather
+                                  than XX, XY, YX, YY (or XX, YY); used by wg_finalise's Stokes
+                                  conversion only                                              */
 #define WG_W_STACKING 4u       /* w-stacking (eq. stacking): one grid per w-plane, every record
                                   gridded with the w = 0 kernel (plane 0's support, slices and
                                   zeta) on the grid of its w-plane; the w-term is applied in the
@@ -87,8 +92,14 @@ typedef enum wg_kdtype {
  *           beta*m_img <= WG_MAX_FFT, and (s_hi-1)/2*beta + beta/2 < beta*m_img/2).
  *   du      uv cell size in wavelengths (> 0); the image field of view is 1/du.
  *   w_max   largest |w| tabulated, wavelengths (>= 0).
- *   flags   WG_COMPRESS, and at most one of WG_GRID_PER_CHANNEL and WG_W_STACKING; or 0
- *           (unknown bits or both grid modes: WG_EINVAL).
+ *   flags   WG_COMPRESS, WG_POL_CIRCULAR, and at most one of WG_GRID_PER_CHANNEL and
+ *           WG_W_STACKING; or 0 (unknown bits or both grid modes: WG_EINVAL).
+ *   n_pol   polarisations per record P: 1 (0 is read as 1), 2 (the parallel hands XX, YY or
+ *           RR, LL) or 4 (XX, XY, YX, YY or RR, RL, LR, LL), in that order; others are
+ *           WG_EINVAL. WG_W_STACKING needs P = 1 (else WG_EUNSUPPORTED).
+ *           The flip of a record with w < 0 (eq. conj) conjugates each value; with P = 4 it
+ *           also exchanges the cross hands with their weights and flags (the partner of a
+ *           polarised record: V_pq(-u) = conj V_qp(u)).
  */
 typedef struct wg_geom {
     int32_t n;
@@ -100,7 +111,7 @@ typedef struct wg_geom {
     double du;
     double w_max;
     uint32_t flags;
-    int32_t reserved;
+    int32_t n_pol;
 } wg_geom;
 
 /*
@@ -137,8 +148,9 @@ typedef struct wg_ktable {
  * Runs produced by wg_compress (filtered sequences FS-1..FS-5 with the compression of
  * Algorithm compressindex folded in). Run q covers records start[q] .. start[q]+len[q]-1 of
  * one (baseline, channel) segment, all with pixel (x, y) relative to the grid centre,
- * w-plane `plane` and oversample offsets (ou, ov); gamma is the sum over its records of
- * weight * (vis, conjugated when w < 0), as float32 (re, im). Runs are in record order.
+ * w-plane `plane` and oversample offsets (ou, ov); gamma [capacity][P] is per polarisation
+ * the sum over its records of weight * (1 - flag) * (vis, conjugated when w < 0), as float32
+ * (re, im) (eqs. compress1, conjugatetake). Runs are in record order.
  * `plan` is a device work list the gridder reads (local chunks of equal support, grouped by
  * support); size it with wg_plan_elems. It also holds wg_degrid's work counter, so two
  * wg_degrid calls on the same runs must not overlap in time.
@@ -146,9 +158,11 @@ typedef struct wg_ktable {
  * grid it goes to) and `norm` (one double per channel: that channel's normaliser N of eq.
  * normalizer) are required and written by wg_compress. With WG_W_STACKING, `grid` is
  * required and holds the run's w-plane (its grid), `plane` is 0 (the kernel used) and `norm`
- * may be NULL (the one normaliser is in the statistics). Otherwise both may be NULL. `work` is scratch that wg_degrid overwrites (one
- * complex float per run). Every array has `capacity` entries (gamma and work 2x); capacity
- * must be >= nb*nc*nt, so the run list can never overflow.
+ * may be NULL (the one normaliser is in the statistics). With P > 1, `norm` is required
+ * and holds the normaliser of each polarisation, [nc][P] with per-channel grids, else [P].
+ * Otherwise both may be NULL. `work` is scratch that wg_degrid overwrites (P complex
+ * floats per run). Every array has `capacity` entries (gamma and work 2P floats each);
+ * capacity must be >= nb*nc*nt, so the run list can never overflow.
  */
 typedef struct wg_runs {
     int64_t capacity;
@@ -172,7 +186,9 @@ typedef struct wg_runs {
  * device: n_records; n_griddable = sum (g+c); n_runs = sum g (records gridded by the
  * gridder); n_compressed = sum c; upd_real = sum g*S^2 (grid-point updates executed);
  * upd_saved = sum c*S^2 (updates saved by compression); normaliser = N of eq. normalizer
- * (FP64); n_items = number of local chunks in the plan.
+ * (FP64; of the first polarisation, over all grids); n_items = number of local chunks in
+ * the plan. Update counts are per polarisation (a run of support S updates S^2 cells of
+ * each of the P grids).
  */
 typedef struct wg_stats {
     int64_t n_records;
@@ -236,7 +252,8 @@ int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const 
                 int32_t nt, wg_runs *runs, wg_stats *stats, wg_stream_t stream);
 
 /*
- * Gridding phase (eq. gridding): for every run, grid[row0+i][a+j] += gamma * K[i][j] with
+ * Gridding phase (eq. gridding): for every run and polarisation p, grid[row0+i][a+j][p] +=
+ * gamma[p] * K[i][j] with
  * a = x + n/2 - H, row0 = y + n/2 - H, K the run's matrix. ACCUMULATES into `grid`
  * (complex64 [n][n], or [nc][n][n] with WG_GRID_PER_CHANNEL or [n_w][n][n] with
  * WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first. Accumulation is FP32 with Kahan
@@ -249,33 +266,38 @@ int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg
 
 /*
  * Adjoint of wg_compress + wg_grid with respect to the visibilities: per run
- * d = sum_ij conj(K[i][j]) * grid[row0+i][a+j] (grid complex64 [n][n], or [nc][n][n] / [n_w][n][n]
- * read at grid runs->grid[q] with WG_GRID_PER_CHANNEL / WG_W_STACKING; FP32, pairwise/tree summation; partial sums
- * of the waves sharing a run are combined with FP32 atomic adds into runs->work, so the last
- * bits depend on scheduling); record r of the run gets weight_r * (d, or conj(d) when
- * w_r(metres) < 0); records in no run get 0. OVERWRITES vis_out (complex64 [nb][nc][nt]) and
- * runs->work. uvw, weight and the sizes must be those given to wg_compress.
+ * d[p] = sum_ij conj(K[i][j]) * grid[row0+i][a+j][p] (grid complex64 [n][n][P], or
+ * [nc][n][n][P] / [n_w][n][n] read at grid runs->grid[q] with WG_GRID_PER_CHANNEL /
+ * WG_W_STACKING; FP32, pairwise/tree summation; partial sums of the waves sharing a run
+ * are combined with FP32 atomic adds into runs->work, so the last
+ * bits depend on scheduling); polarisation p of record r of the run gets weight_{r,p} *
+ * (1 - flag_{r,p}) * (d[p], or conj(d[s]) when w_r(metres) < 0, s the slot its value went
+ * to); records in no run get 0. OVERWRITES vis_out (complex64 [nb][nc][nt][P]) and
+ * runs->work. uvw, weight, flag and the sizes must be those given to wg_compress.
  * Errors: WG_EINVAL (runs->work NULL among others), WG_ECAPACITY, WG_EUNSUPPORTED, WG_EHIP.
  */
 int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg_stats *stats,
-              const float *grid, const double *uvw, const float *weight, int64_t nb, int32_t nc,
-              int32_t nt, float *vis_out, wg_stream_t stream);
+              const float *grid, const double *uvw, const float *weight, const uint8_t *flag, int64_t nb,
+              int32_t nc, int32_t nt, float *vis_out, wg_stream_t stream);
 
 /*
- * Image finaliser (Algorithm finalizer), one polarisation: inverse 2-D FFT of the grid, real
- * part over the normaliser N_p (eq. normalizer; read on the device from *normaliser, e.g.
- * &stats->normaliser, or &runs->norm[c] for channel c of per-channel grids),
- * divided by the prolate taper psi_0(3 pi, 2 l du) normalised to 1 at the centre (sec.
- * convgriddingmath) and by sinc(pi l du / beta) sinc(pi m du / beta) (eq. coversampled).
- * Image pixel [q][p] holds (l, m) = ((p - n/2), (q - n/2)) / (n du); the real part is taken
- * because each record is gridded once, at its w >= 0 representative (eq. conj). Pixels where
- * the taper is zero (first row and column) are 0; the whole image is 0 when the normaliser
- * is 0. FFTs in FP32.
- *   grid   complex64 [n][n] (device, read only)
- *   normaliser  device double
- *   image  float32 [n][n] (device, OVERWRITTEN)
- *   ws     device workspace of wg_finalise_ws_bytes bytes (two n x n complex64 buffers, one
- *          n x n float32 accumulator, twiddles, corrections; the same size serves
+ * Image finaliser (Algorithm finalizer): inverse 2-D FFT of each polarised grid, each over
+ * its normaliser N_p (eq. normalizer; read on the device, e.g. &stats->normaliser with P = 1,
+ * or runs->norm (+ c*P for channel c of per-channel grids)), combined into Stokes images and
+ * their real parts taken; then divided by the prolate taper psi_0(3 pi, 2 l du) normalised
+ * to 1 at the centre (sec. convgriddingmath) and by sinc(pi l du / beta) sinc(pi m du /
+ * beta) (eq. coversampled). Image pixel [q][p] holds (l, m) = ((p - n/2), (q - n/2)) /
+ * (n du); the real part is taken because each record is gridded once, at its w >= 0
+ * representative (eq. conj). Stokes images, by the feed relations XX = I + Q, XY = U + iV,
+ * YX = U - iV, YY = I - Q (linear) or RR = I + V, RL = Q + iU, LR = Q - iU, LL = I - V
+ * (WG_POL_CIRCULAR): P = 1 gives the one polarisation as I; P = 2 gives (I, Q), or (I, V)
+ * for circular feeds; P = 4 gives (I, Q, U, V). A polarisation whose normaliser is 0 adds
+ * 0. Pixels where the taper is zero (first row and column) are 0. FFTs in FP32.
+ *   grid   complex64 [n][n][P] (device, read only)
+ *   normaliser  P device doubles
+ *   image  float32 [P][n][n] (device, OVERWRITTEN), the Stokes images in the order above
+ *   ws     device workspace of wg_finalise_ws_bytes bytes (two n x n complex64 buffers,
+ *          P n x n float32 accumulators, twiddles, corrections; the same size serves
  *          wg_finalise_stacked)
  * n must be a power of two, 16..8192 (one FP32 complex row in 64 KB of LDS).
  * Errors: WG_EINVAL, WG_ECAPACITY (ws too small), WG_EUNSUPPORTED (n), WG_EHIP.

@@ -21,6 +21,7 @@ namespace {
 struct CArgs {
     int n, beta, lb, n_w, nc, nt, compress;
     int stack;  // w-stacking: every record takes plane 0's kernel; its w-plane picks its grid
+    int npol;   // polarisations per record (1, 2 or 4): vis, wt, flag are [record][npol]
     int64_t n_seg;
     double uv_scale;
     const double *uvw;
@@ -38,7 +39,8 @@ struct CArgs {
     int32_t *plan, *items, *segcnt, *tiles;
     wg_stats *stats;
     int16_t *grid_id;  // the grid of each run (its channel, or its w-plane when stacking), else NULL
-    double *norm;      // per-channel grids: the normaliser of each channel, else NULL
+    double *norm;      // normalisers [grid][npol] (per-channel grids or npol > 1), else NULL
+    int norm_per_ch;   // norm has one row per channel (per-channel grids), else one row
 };
 
 struct Key {
@@ -93,7 +95,7 @@ __global__ void k_init(CArgs a, int64_t n_records) {
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < kPlanHdr; i += blockDim.x) a.plan[i] = 0;
         if (a.norm)
-            for (int c = threadIdx.x; c < a.nc; c += blockDim.x) a.norm[c] = 0.0;
+            for (int c = threadIdx.x; c < (a.norm_per_ch ? a.nc : 1) * a.npol; c += blockDim.x) a.norm[c] = 0.0;
         if (threadIdx.x == 0) {
             a.stats->n_records = n_records;
             a.stats->n_griddable = 0;
@@ -122,7 +124,7 @@ struct BlockAgg {
     int2 items[kStage];
     int itemS[kStage];
     unsigned long long st[4];
-    double norm;
+    double norm;  // the first polarisation's normaliser (the statistics word)
 };
 
 template <bool EMIT>
@@ -143,10 +145,10 @@ __device__ inline void close_item(const CArgs &a, BlockAgg &agg, int S, int begi
     }
 }
 
-template <bool EMIT>
+template <bool EMIT, int NP>
 __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, const int *s_sup, BlockAgg &agg);
 
-template <bool EMIT>
+template <bool EMIT, int NP>
 __global__ __launch_bounds__(256) void k_segments(CArgs a) {
     __shared__ double s_wb[WG_MAX_PLANES];
     __shared__ int s_sup[WG_MAX_PLANES];
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256) void k_segments(CArgs a) {
     const int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (g < a.n_seg) {
         const int64_t nb = a.n_seg / a.nc, ch = g / nb, b = g - ch * nb;
-        walk_segment<EMIT>(a, b * a.nc + ch, s_wb, s_sup, agg);
+        walk_segment<EMIT, NP>(a, b * a.nc + ch, s_wb, s_sup, agg);
     }
     __syncthreads();
     if (!EMIT) {
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(256) void k_segments(CArgs a) {
     }
 }
 
-template <bool EMIT>
+template <bool EMIT, int NP>
 __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, const int *s_sup, BlockAgg &agg) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t b = seg / a.nc;
@@ -212,12 +214,16 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
     int item_begin = -1, item_S = 0;
     bool open = false;  // EMIT: a run still open at the end of the previous step
     int open_idx = 0, open_len = 0;
-    float og_r = 0.f, og_i = 0.f;
+    float og_r[NP], og_i[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) og_r[q] = og_i[q] = 0.f;
     int run_base = 0;
     if (EMIT) run_base = a.segcnt[seg] + a.tiles[seg / kScanTile];
     int64_t my_real = 0, my_saved = 0;
     int n_ok = 0, n_c = 0;
-    double my_norm = 0.0;
+    double my_norm[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) my_norm[q] = 0.0;
 
     for (int t0 = 0; t0 < a.nt; t0 += kWave) {
         const int t = t0 + lane;
@@ -229,7 +235,10 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
         key.psi = 1;
         if (valid) {
             const double *p = a.uvw + (b * a.nt + t) * 3;
-            const bool fl = a.flag ? (a.flag[r] != 0) : false;
+            bool fl = a.flag != nullptr;  // dropped only when every polarisation is flagged
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+                if (a.flag && a.flag[r * NP + q] == 0) fl = false;
             key = index_record(p[0], p[1], p[2], il, fl, a, s_wb, s_sup);
         }
         int pX = __shfl_up(key.X, 1, kWave), pY = __shfl_up(key.Y, 1, kWave);
@@ -247,7 +256,8 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
         if (EMIT && open && !(cm & 1ull)) {  // the carried run ended with the previous step
             if (lane == 0) {
                 a.len[open_idx] = open_len;
-                a.gamma[open_idx] = make_float2(og_r, og_i);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) a.gamma[(int64_t)open_idx * NP + q] = make_float2(og_r[q], og_i[q]);
             }
             open = false;
         }
@@ -274,28 +284,43 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
             if (g) my_real += (int64_t)S * S;
             if (c) my_saved += (int64_t)S * S;
         } else {
-            float vr = 0.f, vi = 0.f;
+            // slot q: weight * (1 - flag) * (vis, conjugated when flipped) of its source slot
+            float sr[NP], si[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) sr[q] = si[q] = 0.f;
             if (key.ok) {
-                const float e = a.wt ? a.wt[r] : 1.0f;
-                const float2 v = a.vis[r];
-                vr = e * v.x;
-                vi = e * ((float)key.psi * v.y);
                 const int sigma = (key.ov + (a.beta >> 1) - 1) * a.beta + (key.ou + (a.beta >> 1) - 1);
-                my_norm += (double)e * a.zeta[(int64_t)(a.stack ? 0 : key.k) * nbeta2 + sigma];
+                const double z = a.zeta[(int64_t)(a.stack ? 0 : key.k) * nbeta2 + sigma];
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    const int64_t e = r * NP + pol_source<NP>(q, key.psi);
+                    float w = a.wt ? a.wt[e] : 1.0f;
+                    if (NP > 1 && a.flag && a.flag[e]) w = 0.0f;
+                    const float2 v = a.vis[e];
+                    sr[q] = w * v.x;
+                    si[q] = w * ((float)key.psi * v.y);
+                    my_norm[q] += (double)w * z;
+                }
             }
             const uint64_t gle = gm & (lt | (1ull << lane));
             const int seg_start = gle ? 63 - __clzll(gle) : -1;
-            float sr = vr, si = vi;
             for (int d = 1; d < kWave; d <<= 1) {
-                const float ur = __shfl_up(sr, d, kWave), ui = __shfl_up(si, d, kWave);
-                if (lane >= d && lane - d >= seg_start) {
-                    sr += ur;
-                    si += ui;
+                const bool take = lane >= d && lane - d >= seg_start;
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    const float ur = __shfl_up(sr[q], d, kWave), ui = __shfl_up(si[q], d, kWave);
+                    if (take) {
+                        sr[q] += ur;
+                        si[q] += ui;
+                    }
                 }
             }
             if (seg_start < 0 && open) {
-                sr += og_r;
-                si += og_i;
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    sr[q] += og_r[q];
+                    si[q] += og_i[q];
+                }
             }
             if (g) {
                 const int j = run_base + runs_before + __popcll(gbelow);
@@ -320,11 +345,17 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
                     ln = open_len + lane + 1;
                 }
                 a.len[j] = ln;
-                a.gamma[j] = make_float2(sr, si);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) a.gamma[(int64_t)j * NP + q] = make_float2(sr[q], si[q]);
             }
             const int carry = __shfl((int)(key.ok && !is_end), kWave - 1, kWave);
             const int ss63 = __shfl(seg_start, kWave - 1, kWave);
-            const float cr = __shfl(sr, kWave - 1, kWave), ci = __shfl(si, kWave - 1, kWave);
+            float cr[NP], ci[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                cr[q] = __shfl(sr[q], kWave - 1, kWave);
+                ci[q] = __shfl(si[q], kWave - 1, kWave);
+            }
             if (carry) {
                 if (ss63 >= 0) {
                     open_idx = run_base + runs_before + __popcll(gm) - 1;
@@ -332,8 +363,11 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
                 } else {
                     open_len += kWave;
                 }
-                og_r = cr;
-                og_i = ci;
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    og_r[q] = cr[q];
+                    og_i[q] = ci[q];
+                }
                 open = true;
             } else {
                 open = false;
@@ -359,10 +393,15 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
             atomicAdd(&agg.st[3], (unsigned long long)saved);
         }
     } else {
-        const double nsum = wave_sum(my_norm);
+        double nsum[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) nsum[q] = wave_sum(my_norm[q]);
         if (lane == 0) {
-            atomicAdd(&agg.norm, nsum);
-            if (a.norm) atomicAdd(&a.norm[ch], nsum);
+            atomicAdd(&agg.norm, nsum[0]);
+            if (a.norm)
+#pragma unroll
+                for (int q = 0; q < NP; ++q)
+                    if (nsum[q] != 0.0) atomicAdd(&a.norm[(a.norm_per_ch ? ch : 0) * NP + q], nsum[q]);
         }
     }
 }
@@ -459,6 +498,8 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
     const int64_t n_seg = nb * nc;
     const bool per_channel = (g->flags & WG_GRID_PER_CHANNEL) != 0;
     const bool stack = (g->flags & WG_W_STACKING) != 0;
+    const int npol = npol_of(g);
+    if (npol > 1 && !runs->norm) return WG_EINVAL;
     if (per_channel) {
         if (!runs->grid || !runs->norm) return WG_EINVAL;
         if (nc > 32767 || (int64_t)nc * g->n * g->n >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
@@ -480,6 +521,7 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
     a.nt = nt;
     a.compress = (g->flags & WG_COMPRESS) ? 1 : 0;
     a.stack = stack ? 1 : 0;
+    a.npol = npol;
     a.n_seg = n_seg;
     a.uv_scale = (double)g->beta / g->du;
     a.uvw = uvw;
@@ -504,15 +546,22 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
     a.tiles = runs->plan + plan_tiles_at(runs->capacity, n_seg);
     a.stats = stats;
     a.grid_id = (per_channel || stack) ? runs->grid : nullptr;
-    a.norm = per_channel ? runs->norm : nullptr;
+    a.norm = (per_channel || npol > 1) ? runs->norm : nullptr;
+    a.norm_per_ch = per_channel ? 1 : 0;
 
     hipStream_t s = (hipStream_t)stream;
     const int64_t n_tiles = n_scan_tiles(n_seg);
     const int64_t seg_blocks = (n_seg + 3) / 4;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, a, n_rec);
-    hipLaunchKernelGGL(k_segments<false>, dim3((unsigned)seg_blocks), dim3(256), 0, s, a);
+    auto segments = [&](bool emit) {
+        void (*k)(CArgs) = npol == 4   ? (emit ? k_segments<true, 4> : k_segments<false, 4>)
+                           : npol == 2 ? (emit ? k_segments<true, 2> : k_segments<false, 2>)
+                                       : (emit ? k_segments<true, 1> : k_segments<false, 1>);
+        hipLaunchKernelGGL(k, dim3((unsigned)seg_blocks), dim3(256), 0, s, a);
+    };
+    segments(false);
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, a, n_tiles);
-    hipLaunchKernelGGL(k_segments<true>, dim3((unsigned)seg_blocks), dim3(256), 0, s, a);
+    segments(true);
     return launch_status();
 }

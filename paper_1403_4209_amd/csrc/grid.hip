@@ -16,6 +16,7 @@ namespace {
 
 struct GArgs {
     int n, beta, n_w, nc, nt;
+    int npol;  // polarisations per record, run and cell (1, 2 or 4)
     int64_t n_rec, data_cap;
     const int32_t *start, *len, *x, *y;
     const int16_t *plane;
@@ -33,6 +34,7 @@ struct GArgs {
     const wg_stats *stats;
     const double *uvw;
     const float *wt;
+    const uint8_t *flag;
 };
 
 template <int DT>
@@ -114,25 +116,27 @@ __device__ void build_units(const int32_t *plan, int slots, UnitTable *t) {
 
 // Run records of up to 64 consecutive runs, one per lane, with everything the per-run loop
 // needs precomputed in parallel; the loop then broadcasts run t with v_readlane.
+template <int NP>
 struct RunBatch {
     int cell0, ph, kb, ok;  // ph: footprint origin phases, (row0 mod S) << 16 | (ax mod S)
-    float gr, gi;
+    float gr[NP], gi[NP];   // the run's weighted visibility sum per polarisation
 };
 
 __device__ inline int rl(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
 __device__ inline float rlf(float v, int t) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t)); }
 __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ inline RunBatch load_batch(const GArgs &a, int S, int j, bool valid, const int64_t *koff) {
-    RunBatch b;
+template <int NP>
+__device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool valid, const int64_t *koff) {
+    RunBatch<NP> b;
     b.ok = 0;
     b.cell0 = b.ph = b.kb = 0;
-    b.gr = b.gi = 0.f;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) b.gr[p] = b.gi[p] = 0.f;
     if (valid) {
         const int H = (S - 1) >> 1, half = a.n >> 1, hb = a.beta >> 1;
         const int X = a.x[j], Y = a.y[j], k = a.plane[j];
         const int sigma = (a.ov[j] + hb - 1) * a.beta + (a.ou[j] + hb - 1);
-        const float2 g = a.gamma[j];
         const int ax = X + half - H, row0 = Y + half - H;
         const int64_t kbase = koff[k] + (int64_t)sigma * S * S;
         // runs from wg_compress with the same geometry and table always pass; anything else
@@ -143,8 +147,12 @@ __device__ inline RunBatch load_batch(const GArgs &a, int S, int j, bool valid, 
             b.cell0 = row0 * a.n + ax + (a.grid_id ? (int)(a.grid_id[j] * a.cells) : 0);
             b.ph = (row0 % S) << 16 | (ax % S);
             b.kb = (int)kbase;
-            b.gr = g.x;
-            b.gi = g.y;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const float2 g = a.gamma[(int64_t)j * NP + p];
+                b.gr[p] = g.x;
+                b.gi[p] = g.y;
+            }
         }
     }
     return b;
@@ -244,7 +252,7 @@ __device__ inline void for_each_unit(int nunits, int32_t *q, F &&body) {
     }
 }
 
-template <int DT, int NS>
+template <int DT, int NP, int NS>
 __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
                               const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
@@ -259,29 +267,35 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
     const u16x2 mul_k = {(unsigned short)esz, (unsigned short)(S * esz)};  // byte offset in a matrix
     const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};           // cell offset in the grid
-    float acc_r[kSlots], acc_i[kSlots], cmp_r[kSlots], cmp_i[kSlots];
+    // per slot and polarisation: Kahan sum and compensation of the owned cell
+    float acc_r[NS][NP], acc_i[NS][NP], cmp_r[NS][NP], cmp_i[NS][NP];
     int cur[kSlots];  // owned cell (y*n + x); set from the chunk's first run
     // Footprint positions of the lane's classes, recomputed only when the footprint moves
     // (consecutive runs of a chunk mostly differ in oversampling offsets or plane alone).
     u16x2 wpos[kSlots];
     unsigned last_cell0 = kNoCell;
 #pragma unroll
-    for (int m = 0; m < NS; ++m) acc_r[m] = acc_i[m] = cmp_r[m] = cmp_i[m] = 0.f;
-    // Commit the cell's compensated sum (acc - cmp); the next cell starts from acc = cmp,
-    // i.e. from the value zero, with the compensation term left as it is (Kahan's recurrence
-    // holds from any starting pair).
+    for (int m = 0; m < NS; ++m)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) acc_r[m][p] = acc_i[m][p] = cmp_r[m][p] = cmp_i[m][p] = 0.f;
+    // Commit the cell's compensated sums (acc - cmp) of every polarisation; the next cell
+    // starts from acc = cmp, i.e. from the value zero, with the compensation term left as it
+    // is (Kahan's recurrence holds from any starting pair).
     auto commit = [&](int m) {
-        float *cell = a.grid + 2 * (int64_t)(unsigned)cur[m];
-        unsafeAtomicAdd(cell, acc_r[m] - cmp_r[m]);
-        unsafeAtomicAdd(cell + 1, acc_i[m] - cmp_i[m]);
-        acc_r[m] = cmp_r[m];
-        acc_i[m] = cmp_i[m];
+        float *cell = a.grid + 2 * (int64_t)(unsigned)cur[m] * NP;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            unsafeAtomicAdd(cell + 2 * p, acc_r[m][p] - cmp_r[m][p]);
+            unsafeAtomicAdd(cell + 2 * p + 1, acc_i[m][p] - cmp_i[m][p]);
+            acc_r[m][p] = cmp_r[m][p];
+            acc_i[m][p] = cmp_i[m][p];
+        }
     };
     bool first = true;
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
-        const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
+        const RunBatch<NP> b = load_batch<NP>(a, S, base + lane, lane < n, koff);
 
         // cells (when the footprint moved) and samples of the lane's classes for run t
         auto fetch = [&](int t, Stage<DT> &st) {
@@ -303,7 +317,12 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
         };
         auto accumulate = [&](int t, const Stage<DT> &st) {
             if (!rl(b.ok, t)) return;
-            const float gr = rlf(b.gr, t), gi = rlf(b.gi, t);
+            float gr[NP], gi[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                gr[p] = rlf(b.gr[p], t);
+                gi[p] = rlf(b.gi[p], t);
+            }
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 if (m < nslots - 1 || last_ok) {
@@ -312,15 +331,19 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
                         cur[m] = st.yc[m];
                     }
                     // Kahan step with the product fused into the compensation:
-                    // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t
+                    // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t; one sample serves
+                    // every polarisation
                     const float2 kv = to_float2<DT>(st.k[m]);
-                    const float yr = fmaf(gr, kv.x, -fmaf(gi, kv.y, cmp_r[m]));
-                    const float yi = fmaf(gr, kv.y, fmaf(gi, kv.x, -cmp_i[m]));
-                    const float tr = acc_r[m] + yr, ti = acc_i[m] + yi;
-                    cmp_r[m] = (tr - acc_r[m]) - yr;
-                    cmp_i[m] = (ti - acc_i[m]) - yi;
-                    acc_r[m] = tr;
-                    acc_i[m] = ti;
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const float yr = fmaf(gr[p], kv.x, -fmaf(gi[p], kv.y, cmp_r[m][p]));
+                        const float yi = fmaf(gr[p], kv.y, fmaf(gi[p], kv.x, -cmp_i[m][p]));
+                        const float tr = acc_r[m][p] + yr, ti = acc_i[m][p] + yi;
+                        cmp_r[m][p] = (tr - acc_r[m][p]) - yr;
+                        cmp_i[m][p] = (ti - acc_i[m][p]) - yi;
+                        acc_r[m][p] = tr;
+                        acc_i[m][p] = ti;
+                    }
                 }
             }
         };
@@ -358,36 +381,39 @@ __device__ inline void chunk_classes(int S, int chunk, int slots, int &c0, int &
 
 // Slot count as a template parameter, instantiated for 1..MAX only (the kernel's register
 // allocation is the largest over its instantiations).
-template <int DT, int NS, int MAX>
+template <int DT, int NP, int NS, int MAX>
 __device__ inline void grid_dispatch(int ns, const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
                                      const int64_t *koff) {
     if constexpr (NS < MAX) {
         if (ns == NS) {
-            grid_chunk_ns<DT, NS>(a, S, c0, c1, rb, re, lane, koff);
+            grid_chunk_ns<DT, NP, NS>(a, S, c0, c1, rb, re, lane, koff);
             return;
         }
-        grid_dispatch<DT, NS + 1, MAX>(ns, a, S, c0, c1, rb, re, lane, koff);
+        grid_dispatch<DT, NP, NS + 1, MAX>(ns, a, S, c0, c1, rb, re, lane, koff);
     } else {
-        grid_chunk_ns<DT, MAX>(a, S, c0, c1, rb, re, lane, koff);
+        grid_chunk_ns<DT, NP, MAX>(a, S, c0, c1, rb, re, lane, koff);
     }
 }
 
-// Most classes per lane of the gridder: 8 with FP32 tables, 6 with 16-bit tables.
-template <int DT>
-constexpr int grid_slots() { return DT == WG_KF32 ? kSlots : kSlotsNarrow; }
-
-template <int DT>
-__device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
-    int c0, c1, ns;
-    chunk_classes(S, chunk, grid_slots<DT>(), c0, c1, ns);
-    grid_dispatch<DT, 1, grid_slots<DT>()>(ns, a, S, c0, c1, rb, re, lane, koff);
+// Most classes per lane of the gridder: 8 with FP32 tables, 6 with 16-bit tables, for one
+// polarisation; the accumulators of more polarisations take the registers of more slots.
+template <int DT, int NP>
+constexpr int grid_slots() {
+    return NP == 4 ? kSlotsPol4 : NP == 2 ? kSlotsPol2 : DT == WG_KF32 ? kSlots : kSlotsNarrow;
 }
 
-template <int DT>
+template <int DT, int NP>
+__device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
+    int c0, c1, ns;
+    chunk_classes(S, chunk, grid_slots<DT, NP>(), c0, c1, ns);
+    grid_dispatch<DT, NP, 1, grid_slots<DT, NP>()>(ns, a, S, c0, c1, rb, re, lane, koff);
+}
+
+template <int DT, int NP>
 __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, grid_slots<DT>(), &ut);
+    if (threadIdx.x == 0) build_units(a.plan, grid_slots<DT, NP>(), &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -395,11 +421,11 @@ __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     for_each_unit_static(nunits, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_of(S, grid_slots<DT>());
+        const int S = uni(ut.S[m]), nch = nchunk_of(S, grid_slots<DT, NP>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;
-        grid_chunk<DT>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
+        grid_chunk<DT, NP>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
     });
 }
 
@@ -425,12 +451,28 @@ __device__ inline float wave_total(float v) {
 // product of conj(K) with those values (a short FMA chain per lane, then a DPP tree over the
 // wave). The waves sharing a
 // chunk add their partial sums into work[run]; k_degrid_finish hands d to the run's records.
-template <int DT>
+template <int DT, int NP>
 struct DStage {
     typename KRaw<DT>::type k[kSlots];
-    float2 g[kSlots];  // grid values of the run's cells (loaded when the footprint moved)
-    bool moved;        // wave-uniform: the run's footprint origin differs from the previous run's
+    float2 g[kSlots][NP];  // grid values of the run's cells (loaded when the footprint moved)
+    bool moved;            // wave-uniform: the run's footprint origin differs from the previous run's
 };
+
+// The NP complex values of one cell ([n][n][NP] grid), as one or two 16-byte loads.
+template <int NP>
+__device__ inline void load_cell(const float2 *grid, unsigned cell, float2 *v) {
+    if constexpr (NP == 1) {
+        v[0] = grid[cell];
+    } else {
+        const float4 *g4 = (const float4 *)grid + (size_t)cell * (NP / 2);
+#pragma unroll
+        for (int h = 0; h < NP / 2; ++h) {
+            const float4 q = g4[h];
+            v[2 * h] = make_float2(q.x, q.y);
+            v[2 * h + 1] = make_float2(q.z, q.w);
+        }
+    }
+}
 
 // A wave-uniform value held in a VGPR, so that an instruction taking it together with a
 // per-run scalar needs only one scalar operand.
@@ -440,7 +482,7 @@ __device__ inline unsigned in_vgpr(unsigned x) {
     return r;
 }
 
-template <int DT, int NS>
+template <int DT, int NP, int NS>
 __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
                                 const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
@@ -453,17 +495,19 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
     const u16x2 mul_k = as_u16x2(in_vgpr((unsigned)(S * esz) << 16 | (unsigned)esz));
     const u16x2 mul_c = as_u16x2(in_vgpr((unsigned)a.n << 16 | 1u));
-    float2 gv[kSlots];    // grid values of the owned cells
+    float2 gv[NS][NP];    // grid values of the owned cells
     u16x2 wpos[kSlots];   // footprint positions, recomputed only when the footprint moves
     unsigned last_cell0 = kNoCell;
 #pragma unroll
-    for (int m = 0; m < NS; ++m) gv[m] = make_float2(0.f, 0.f);
+    for (int m = 0; m < NS; ++m)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) gv[m][p] = make_float2(0.f, 0.f);
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
-        const RunBatch b = load_batch(a, S, base + lane, lane < n, koff);
+        const RunBatch<NP> b = load_batch<NP>(a, S, base + lane, lane < n, koff);
 
-        auto fetch = [&](int t, DStage<DT> &st) {
+        auto fetch = [&](int t, DStage<DT, NP> &st) {
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
             const bool ok = rl(b.ok, t) != 0;
@@ -474,33 +518,45 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
 #pragma unroll
                 for (int m = 0; m < NS; ++m) {
                     wpos[m] = footprint_pos(cls[m], ph, ss);
-                    st.g[m] = grid[dot2(wpos[m], mul_c, cell0)];
+                    load_cell<NP>(grid, dot2(wpos[m], mul_c, cell0), st.g[m]);
                 }
             }
 #pragma unroll
             for (int m = 0; m < NS; ++m) st.k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
         };
-        float sum_r = 0.f, sum_i = 0.f;  // lane t: this wave's sum for run base + t
-        auto consume = [&](int t, const DStage<DT> &st) {
-            float pr = 0.f, pim = 0.f;
+        float sum_r[NP], sum_i[NP];  // lane t: this wave's sums for run base + t
+#pragma unroll
+        for (int p = 0; p < NP; ++p) sum_r[p] = sum_i[p] = 0.f;
+        auto consume = [&](int t, const DStage<DT, NP> &st) {
+            float pr[NP], pim[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) pr[p] = pim[p] = 0.f;
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 if (m < nslots) {
-                    if (st.moved) gv[m] = st.g[m];
+                    if (st.moved)
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) gv[m][p] = st.g[m][p];
                     if (m < nslots - 1 || last_ok) {
                         const float2 kv = to_float2<DT>(st.k[m]);
-                        pr = fmaf(kv.x, gv[m].x, fmaf(kv.y, gv[m].y, pr));
-                        pim = fmaf(kv.x, gv[m].y, fmaf(-kv.y, gv[m].x, pim));
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) {
+                            pr[p] = fmaf(kv.x, gv[m][p].x, fmaf(kv.y, gv[m][p].y, pr[p]));
+                            pim[p] = fmaf(kv.x, gv[m][p].y, fmaf(-kv.y, gv[m][p].x, pim[p]));
+                        }
                     }
                 }
             }
-            // the wave's sum for run t waits in lane t; one atomic per batch adds them all
-            const float dr = wave_total(pr), di = wave_total(pim);
-            sum_r = lane == t ? dr : sum_r;
-            sum_i = lane == t ? di : sum_i;
+            // the wave's sums for run t wait in lane t; one atomic per batch adds them all
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const float dr = wave_total(pr[p]), di = wave_total(pim[p]);
+                sum_r[p] = lane == t ? dr : sum_r[p];
+                sum_i[p] = lane == t ? di : sum_i[p];
+            }
         };
 
-        DStage<DT> sa, sb;
+        DStage<DT, NP> sa, sb;
         fetch(0, sa);
         for (int t = 0; t < n; t += 2) {
             if (t + 1 < n) fetch(t + 1, sb);
@@ -511,39 +567,45 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
             }
         }
         if (lane < n && b.ok) {
-            float *w = (float *)(a.work + base + lane);
-            unsafeAtomicAdd(w, sum_r);
-            unsafeAtomicAdd(w + 1, sum_i);
+            float *w = (float *)(a.work + (int64_t)(base + lane) * NP);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                unsafeAtomicAdd(w + 2 * p, sum_r[p]);
+                unsafeAtomicAdd(w + 2 * p + 1, sum_i[p]);
+            }
         }
     }
 }
 
-template <int DT, int NS, int MAX>
+template <int DT, int NP, int NS, int MAX>
 __device__ inline void degrid_dispatch(int ns, const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
                                        const int64_t *koff) {
     if constexpr (NS < MAX) {
         if (ns == NS) {
-            degrid_chunk_ns<DT, NS>(a, S, c0, c1, rb, re, lane, koff);
+            degrid_chunk_ns<DT, NP, NS>(a, S, c0, c1, rb, re, lane, koff);
             return;
         }
-        degrid_dispatch<DT, NS + 1, MAX>(ns, a, S, c0, c1, rb, re, lane, koff);
+        degrid_dispatch<DT, NP, NS + 1, MAX>(ns, a, S, c0, c1, rb, re, lane, koff);
     } else {
-        degrid_chunk_ns<DT, MAX>(a, S, c0, c1, rb, re, lane, koff);
+        degrid_chunk_ns<DT, NP, MAX>(a, S, c0, c1, rb, re, lane, koff);
     }
 }
 
-template <int DT>
+template <int NP>
+constexpr int degrid_slots() { return NP == 4 ? kDegridSlotsPol4 : NP == 2 ? kDegridSlotsPol2 : kDegridSlots; }
+
+template <int DT, int NP>
 __device__ void degrid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
     int c0, c1, ns;
-    chunk_classes(S, chunk, kDegridSlots, c0, c1, ns);
-    degrid_dispatch<DT, 1, kDegridSlots>(ns, a, S, c0, c1, rb, re, lane, koff);
+    chunk_classes(S, chunk, degrid_slots<NP>(), c0, c1, ns);
+    degrid_dispatch<DT, NP, 1, degrid_slots<NP>()>(ns, a, S, c0, c1, rb, re, lane, koff);
 }
 
-template <int DT>
+template <int DT, int NP>
 __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, kDegridSlots, &ut);
+    if (threadIdx.x == 0) build_units(a.plan, degrid_slots<NP>(), &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -551,27 +613,31 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     for_each_unit(nunits, a.queue, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_of(S, kDegridSlots);
+        const int S = uni(ut.S[m]), nch = nchunk_of(S, degrid_slots<NP>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;
-        degrid_chunk<DT>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
+        degrid_chunk<DT, NP>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
     });
 }
 
-// Clears the per-run accumulators (n_runs entries, read on the device).
+// Clears the per-run accumulators (n_runs * npol entries, read on the device).
 __global__ void k_zero_work(GArgs a) {
-    const int64_t n = a.stats->n_runs;
+    const int64_t n = a.stats->n_runs * a.npol;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
         a.work[j] = make_float2(0.f, 0.f);
 }
 
-// Hands each run's dot product to its records: weight * (d, or conj d when w < 0).
+// Hands each run's dot products to its records: polarisation p gets weight * (1 - flag) *
+// (d[p], or conj d[s] when w < 0, s the slot its value went to).
+template <int NP>
 __global__ void k_degrid_finish(GArgs a) {
     const int64_t n = a.stats->n_runs;
     const int64_t seglen = (int64_t)a.nt * a.nc;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        const float2 d = a.work[j];
+        float2 d[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) d[p] = a.work[j * NP + p];
         const int64_t r0 = a.start[j];
         const int cnt = a.len[j];
         for (int m = 0; m < cnt; ++m) {
@@ -579,8 +645,15 @@ __global__ void k_degrid_finish(GArgs a) {
             if (r < 0 || r >= a.n_rec) break;
             const int64_t bb = r / seglen, tt = r - (r / a.nt) * a.nt;
             const double wm = a.uvw[(bb * a.nt + tt) * 3 + 2];
-            const float e = a.wt ? a.wt[r] : 1.0f;
-            a.vis_out[r] = make_float2(e * d.x, e * ((wm >= 0.0) ? d.y : -d.y));
+            const int psi = (wm >= 0.0) ? 1 : -1;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int64_t e = r * NP + p;
+                float w = a.wt ? a.wt[e] : 1.0f;
+                if (NP > 1 && a.flag && a.flag[e]) w = 0.0f;
+                const float2 v = d[pol_source<NP>(p, psi)];
+                a.vis_out[e] = make_float2(w * v.x, w * (psi > 0 ? v.y : -v.y));
+            }
         }
     }
 }
@@ -619,6 +692,8 @@ GArgs make_args(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs) {
     a.stats = nullptr;
     a.uvw = nullptr;
     a.wt = nullptr;
+    a.flag = nullptr;
+    a.npol = npol_of(g);
     return a;
 }
 
@@ -631,6 +706,19 @@ int check_runs(const wg_geom *g, const wg_runs *runs) {
 }
 
 constexpr int kPersistentBlocks = 4096;
+
+// The gridder (GRID) or degridder kernel for a table type and polarisation count.
+template <bool GRID>
+void (*pick_kernel(int dtype, int npol))(GArgs) {
+    if (dtype == WG_KF32)
+        return GRID ? (npol == 4 ? k_grid<WG_KF32, 4> : npol == 2 ? k_grid<WG_KF32, 2> : k_grid<WG_KF32, 1>)
+                    : (npol == 4 ? k_degrid<WG_KF32, 4> : npol == 2 ? k_degrid<WG_KF32, 2> : k_degrid<WG_KF32, 1>);
+    if (dtype == WG_KBF16)
+        return GRID ? (npol == 4 ? k_grid<WG_KBF16, 4> : npol == 2 ? k_grid<WG_KBF16, 2> : k_grid<WG_KBF16, 1>)
+                    : (npol == 4 ? k_degrid<WG_KBF16, 4> : npol == 2 ? k_degrid<WG_KBF16, 2> : k_degrid<WG_KBF16, 1>);
+    return GRID ? (npol == 4 ? k_grid<WG_KF16, 4> : npol == 2 ? k_grid<WG_KF16, 2> : k_grid<WG_KF16, 1>)
+                : (npol == 4 ? k_degrid<WG_KF16, 4> : npol == 2 ? k_degrid<WG_KF16, 2> : k_degrid<WG_KF16, 1>);
+}
 
 }  // namespace
 }  // namespace wg
@@ -647,17 +735,13 @@ extern "C" int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *run
     GArgs a = make_args(g, kt, runs);
     a.grid = grid;
     hipStream_t s = (hipStream_t)stream;
-    switch (kt->dtype) {
-    case WG_KF32: hipLaunchKernelGGL(k_grid<WG_KF32>, dim3(kPersistentBlocks), dim3(256), 0, s, a); break;
-    case WG_KBF16: hipLaunchKernelGGL(k_grid<WG_KBF16>, dim3(kPersistentBlocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_grid<WG_KF16>, dim3(kPersistentBlocks), dim3(256), 0, s, a); break;
-    }
+    hipLaunchKernelGGL(pick_kernel<true>(kt->dtype, a.npol), dim3(kPersistentBlocks), dim3(256), 0, s, a);
     return launch_status();
 }
 
 extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg_stats *stats,
-                         const float *grid, const double *uvw, const float *weight, int64_t nb, int32_t nc,
-                         int32_t nt, float *vis_out, wg_stream_t stream) {
+                         const float *grid, const double *uvw, const float *weight, const uint8_t *flag,
+                         int64_t nb, int32_t nc, int32_t nt, float *vis_out, wg_stream_t stream) {
     using namespace wg;
     int st = check_geom(g);
     if (st != WG_OK) return st;
@@ -673,19 +757,17 @@ extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *r
     a.queue = runs->plan + kPlanQueueDegrid;
     a.uvw = uvw;
     a.wt = weight;
+    a.flag = flag;
     a.nc = nc;
     a.nt = nt;
     a.n_rec = n_rec;
     a.stats = stats;
     hipStream_t s = (hipStream_t)stream;
     // records in no run get 0: clear the output and the per-run accumulators first
-    hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, s, (float2 *)vis_out, n_rec);
+    hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, s, (float2 *)vis_out, n_rec * a.npol);
     hipLaunchKernelGGL(k_zero_work, dim3(2048), dim3(256), 0, s, a);
-    switch (kt->dtype) {
-    case WG_KF32: hipLaunchKernelGGL(k_degrid<WG_KF32>, dim3(kPersistentBlocks), dim3(256), 0, s, a); break;
-    case WG_KBF16: hipLaunchKernelGGL(k_degrid<WG_KBF16>, dim3(kPersistentBlocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_degrid<WG_KF16>, dim3(kPersistentBlocks), dim3(256), 0, s, a); break;
-    }
-    hipLaunchKernelGGL(k_degrid_finish, dim3(2048), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pick_kernel<false>(kt->dtype, a.npol), dim3(kPersistentBlocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(a.npol == 4 ? k_degrid_finish<4> : a.npol == 2 ? k_degrid_finish<2> : k_degrid_finish<1>,
+                       dim3(2048), dim3(256), 0, s, a);
     return launch_status();
 }

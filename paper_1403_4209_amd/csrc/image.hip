@@ -10,6 +10,12 @@
 // Pixels where the taper is zero (the first row and column, l or m = -FOV/2) are 0, and the
 // whole image is 0 when the normaliser is 0 (nothing was gridded).
 //
+// Polarised grids ([n][n][P], P = 2 or 4): each polarisation is transformed on its own and
+// divided by its normaliser, and the Stokes images are the real parts of the linear
+// combinations given by the feed relations (XX = I + Q, XY = U + iV, YX = U - iV, YY = I - Q;
+// RR = I + V, RL = Q + iU, LR = Q - iU, LL = I - V), accumulated pixel by pixel in FP32 as
+// the polarisations are transformed one after the other.
+//
 // W-stacking (eq. stacking) adds, before step 2, the sum over the w-plane grids of their
 // transforms times the plane's image-plane w-term correction exp(+2 pi i w_k (n - 1)),
 // n = sqrt(1 - l^2 - m^2): the factor that the w-projection kernel of plane k carries
@@ -91,7 +97,7 @@ __device__ inline void idft_reg(float2 *v) {
 // and writes to `out` (global, shifted) when last, else back to LDS.
 template <int R>
 __device__ inline void ifft_pass(float2 *buf, const float2 *in, float2 *out, int n, int ns, bool first,
-                                 bool last, bool active, const float2 *tw) {
+                                 bool last, bool active, const float2 *tw, int stride) {
     const int T = n >> 4, t = threadIdx.x, nb = n / R, half = n >> 1;
     float2 v[16];
     if (active) {
@@ -101,7 +107,7 @@ __device__ inline void ifft_pass(float2 *buf, const float2 *in, float2 *out, int
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int e = j + r * nb;
-                float2 x = first ? in[e ^ half] : buf[e];
+                float2 x = first ? in[(size_t)(e ^ half) * stride] : buf[e];
                 if (r > 0 && ns > 1) x = fmulc(x, tw[jm * r * (n / (ns * R))]);
                 v[b * R + r] = x;
             }
@@ -127,12 +133,12 @@ __device__ inline void ifft_pass(float2 *buf, const float2 *in, float2 *out, int
     __syncthreads();
 }
 
-// Rows of src (N x N, complex) -> inverse transforms in dst; ifftshift on input and
-// fftshift on output. blockDim >= N/16.
+// Rows of src (N x N complex values, `stride` apart: one polarisation of a polarised grid)
+// -> inverse transforms in dst; ifftshift on input and fftshift on output. blockDim >= N/16.
 __global__ __launch_bounds__(512) void k_ifft_rows(const float2 *__restrict__ src, float2 *__restrict__ dst,
-                                                   int n, int lg, const float2 *__restrict__ tw) {
+                                                   int n, int lg, const float2 *__restrict__ tw, int stride) {
     extern __shared__ float2 buf[];
-    const float2 *in = src + (size_t)blockIdx.x * n;
+    const float2 *in = src + (size_t)blockIdx.x * n * stride;
     float2 *out = dst + (size_t)blockIdx.x * n;
     const bool active = (int)threadIdx.x < (n >> 4);
     const int P = (lg + 3) >> 2;
@@ -142,10 +148,10 @@ __global__ __launch_bounds__(512) void k_ifft_rows(const float2 *__restrict__ sr
         rem -= bits;
         const bool first = p == 0, last = rem == 0;
         switch (bits) {
-        case 1: ifft_pass<2>(buf, in, out, n, ns, first, last, active, tw); break;
-        case 2: ifft_pass<4>(buf, in, out, n, ns, first, last, active, tw); break;
-        case 3: ifft_pass<8>(buf, in, out, n, ns, first, last, active, tw); break;
-        default: ifft_pass<16>(buf, in, out, n, ns, first, last, active, tw); break;
+        case 1: ifft_pass<2>(buf, in, out, n, ns, first, last, active, tw, stride); break;
+        case 2: ifft_pass<4>(buf, in, out, n, ns, first, last, active, tw, stride); break;
+        case 3: ifft_pass<8>(buf, in, out, n, ns, first, last, active, tw, stride); break;
+        default: ifft_pass<16>(buf, in, out, n, ns, first, last, active, tw, stride); break;
         }
         ns <<= bits;
     }
@@ -178,6 +184,29 @@ __global__ void k_fin_setup(float2 *tw, double *corr, int n, int beta, TaperCoef
     const double y = (double)(j - n / 2) / ((double)n * (double)beta);
     const double sinc = (j == n / 2) ? 1.0 : sinpi(y) / (M_PI * y);
     corr[j] = taper(x, tc) / taper(0.0, tc) * sinc;
+}
+
+// Stokes coefficients of each polarisation: image s += Re(c[s][p] * T_p) / N_p.
+struct StokesCoef {
+    float re[4][4], im[4][4];
+    int ns;
+};
+
+// acc[s][p][q] (+)= Re(c[s][pol] * T[p][q]) / normaliser[pol] for the Stokes images s, T the
+// transformed, transposed grid of polarisation `pol`; the first polarisation writes. A zero
+// normaliser adds 0.
+__global__ void k_stokes_acc(const float2 *__restrict__ T, float *__restrict__ acc, int64_t nn,
+                             const double *__restrict__ normaliser, int pol, StokesCoef c) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nn) return;
+    const double np = normaliser[pol];
+    const double inv = np != 0.0 ? 1.0 / np : 0.0;
+    const float2 t = T[e];
+    for (int s = 0; s < c.ns; ++s) {
+        const float v = (float)(((double)c.re[s][pol] * t.x - (double)c.im[s][pol] * t.y) * inv);
+        float *a = acc + (size_t)s * nn + e;
+        *a = pol == 0 ? v : *a + v;
+    }
 }
 
 __device__ inline float re_of(float2 v) { return v.x; }
@@ -216,7 +245,7 @@ __global__ void k_fin_out(const In *__restrict__ T, const double *__restrict__ c
         if (r < n && c < n) tile[i][threadIdx.x] = re_of(T[(size_t)r * n + c]);
     }
     __syncthreads();
-    const double norm = *normaliser;
+    const double norm = normaliser ? *normaliser : 1.0;  // NULL: the input is normalised
     for (int i = threadIdx.y; i < 32; i += blockDim.y) {
         const int q = bx + i, p = by + threadIdx.x;
         if (q < n && p < n) {
@@ -232,13 +261,13 @@ struct FinLayout {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-FinLayout fin_layout(int n) {
+FinLayout fin_layout(int n, int npol) {
     FinLayout l;
     const size_t nn = (size_t)n * n;
     l.a = 0;
     l.b = align256(l.a + sizeof(float2) * nn);
     l.acc = align256(l.b + sizeof(float2) * nn);
-    l.tw = align256(l.acc + sizeof(float) * nn);
+    l.tw = align256(l.acc + sizeof(float) * nn * npol);
     l.corr = align256(l.tw + sizeof(float2) * n);
     l.total = align256(l.corr + sizeof(double) * n);
     return l;
@@ -260,12 +289,43 @@ extern "C" int wg_finalise_ws_bytes(const wg_geom *g, size_t *ws_bytes) {
     if (st != WG_OK) return st;
     if (!ws_bytes) return WG_EINVAL;
     if (image_lg(g->n) < 0) return WG_EUNSUPPORTED;
-    *ws_bytes = fin_layout(g->n).total;
+    *ws_bytes = fin_layout(g->n, npol_of(g)).total;
     return WG_OK;
 }
 
 namespace wg {
 namespace {
+
+// Coefficients of the Stokes images (feed relations above), in the order I, Q, U, V of those
+// the polarisations give.
+StokesCoef stokes_coef(int npol, bool circular) {
+    StokesCoef c;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) c.re[i][j] = c.im[i][j] = 0.f;
+    if (npol == 2) {  // (XX, YY) -> I, Q; (RR, LL) -> I, V
+        c.ns = 2;
+        c.re[0][0] = c.re[0][1] = 0.5f;
+        c.re[1][0] = 0.5f;
+        c.re[1][1] = -0.5f;
+    } else {  // four products -> I, Q, U, V
+        c.ns = 4;
+        c.re[0][0] = c.re[0][3] = 0.5f;  // I
+        if (!circular) {
+            c.re[1][0] = 0.5f;  // Q = (XX - YY) / 2
+            c.re[1][3] = -0.5f;
+            c.re[2][1] = c.re[2][2] = 0.5f;  // U = (XY + YX) / 2
+            c.im[3][1] = -0.5f;  // V = -i (XY - YX) / 2
+            c.im[3][2] = 0.5f;
+        } else {
+            c.re[1][1] = c.re[1][2] = 0.5f;  // Q = (RL + LR) / 2
+            c.im[2][1] = -0.5f;  // U = -i (RL - LR) / 2
+            c.im[2][2] = 0.5f;
+            c.re[3][0] = 0.5f;  // V = (RR - LL) / 2
+            c.re[3][3] = -0.5f;
+        }
+    }
+    return c;
+}
 
 // Both finalisers: one grid (stacked = false) or the n_w w-plane grids of w-stacking.
 int finalise(const wg_geom *g, const float *grid, const double *normaliser, float *image, void *ws,
@@ -276,7 +336,8 @@ int finalise(const wg_geom *g, const float *grid, const double *normaliser, floa
     if (stacked && !(g->flags & WG_W_STACKING)) return WG_EINVAL;
     const int n = g->n, lg = image_lg(n);
     if (lg < 0) return WG_EUNSUPPORTED;
-    const FinLayout lay = fin_layout(n);
+    const int npol = npol_of(g);
+    const FinLayout lay = fin_layout(n, npol);
     if (ws_bytes < lay.total) return WG_ECAPACITY;
     char *base = (char *)ws;
     float2 *A = (float2 *)(base + lay.a), *B = (float2 *)(base + lay.b), *tw = (float2 *)(base + lay.tw);
@@ -290,23 +351,38 @@ int finalise(const wg_geom *g, const float *grid, const double *normaliser, floa
     const dim3 tiles((n + 31) / 32, (n + 31) / 32), tb(32, 8);
     hipLaunchKernelGGL(k_fin_setup, dim3((n + 255) / 256), dim3(256), 0, s, tw, corr, n, g->beta, tc);
     const int64_t nn = (int64_t)n * n;
+    float *acc = (float *)(base + lay.acc);
+    if (npol > 1) {
+        StokesCoef c = stokes_coef(npol, (g->flags & WG_POL_CIRCULAR) != 0);
+        for (int p = 0; p < npol; ++p) {
+            hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, (const float2 *)grid + p, A, n, lg, tw,
+                               npol);
+            hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
+            hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw, 1);
+            hipLaunchKernelGGL(k_stokes_acc, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, acc, nn,
+                               normaliser, p, c);
+        }
+        for (int k = 0; k < c.ns; ++k)
+            hipLaunchKernelGGL(k_fin_out<float>, tiles, tb, 0, s, (const float *)(acc + (size_t)k * nn), corr,
+                               (const double *)nullptr, image + (size_t)k * nn, n);
+        return launch_status();
+    }
     const int planes = stacked ? g->n_w : 1;
     for (int k = 0; k < planes; ++k) {
         const float2 *G = (const float2 *)grid + (size_t)k * nn;
-        hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, G, A, n, lg, tw);
+        hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, G, A, n, lg, tw, 1);
         hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
-        hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw);
+        hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw, 1);
         if (stacked) {
             // the plane's w, computed as the table generator places its planes
             const double q = g->n_w > 1 ? (double)k / (double)(g->n_w - 1) : 0.0;
             const double w = g->w_max * (q * q);
-            hipLaunchKernelGGL(k_stack_acc, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A,
-                               (float *)(base + lay.acc), n, g->du, w, k == 0 ? 1 : 0);
+            hipLaunchKernelGGL(k_stack_acc, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, acc, n, g->du, w,
+                               k == 0 ? 1 : 0);
         }
     }
     if (stacked)
-        hipLaunchKernelGGL(k_fin_out<float>, tiles, tb, 0, s, (const float *)(base + lay.acc), corr, normaliser,
-                           image, n);
+        hipLaunchKernelGGL(k_fin_out<float>, tiles, tb, 0, s, (const float *)acc, corr, normaliser, image, n);
     else
         hipLaunchKernelGGL(k_fin_out<float2>, tiles, tb, 0, s, A, corr, normaliser, image, n);
     return launch_status();

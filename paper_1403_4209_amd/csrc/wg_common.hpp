@@ -13,6 +13,10 @@ constexpr int kMaxS = WG_MAX_SUPPORT;
 constexpr int kSlots = 8;          // most cell classes per lane in the gridder (register budget)
 constexpr int kSlotsNarrow = 6;    // the same with BF16/FP16 tables (measured faster there)
 constexpr int kDegridSlots = 5;    // the same for the degridder
+constexpr int kSlotsPol2 = 5;      // gridder with two polarisations (any table type)
+constexpr int kSlotsPol4 = 3;      // gridder with four polarisations
+constexpr int kDegridSlotsPol2 = 4;
+constexpr int kDegridSlotsPol4 = 2;
 
 // ---------------------------------------------------------------------------------------
 // Plan layout (int32 words). Items are local chunks (first run, one past last run) of
@@ -49,6 +53,17 @@ __host__ __device__ inline int nchunk_of(int S, int slots) { return (S * S + kWa
         hipError_t e_ = (expr);                              \
         if (e_ != hipSuccess) return WG_EHIP;                \
     } while (0)
+
+// Polarisation slot whose value (weight, flag) a record puts into slot q: with four products
+// a flipped record (psi < 0) exchanges the cross hands (V_pq(-u) = conj V_qp(u)). The
+// exchange is its own inverse, so the adjoint reads slot pol_source(p) for value p.
+template <int NP>
+__device__ inline int pol_source(int q, int psi) {
+    return (NP == 4 && psi < 0 && (q == 1 || q == 2)) ? 3 - q : q;
+}
+
+// Polarisations per record (n_pol 0 is read as 1).
+inline int npol_of(const wg_geom *g) { return g->n_pol > 1 ? g->n_pol : 1; }
 
 inline int launch_status() { return hipGetLastError() == hipSuccess ? WG_OK : WG_EHIP; }
 

@@ -25,6 +25,7 @@ WG_KF32, WG_KBF16, WG_KF16 = 0, 1, 2
 WG_COMPRESS = 1
 WG_GRID_PER_CHANNEL = 2
 WG_W_STACKING = 4
+WG_POL_CIRCULAR = 8
 DTYPES = {"f32": WG_KF32, "bf16": WG_KBF16, "f16": WG_KF16}
 _ELEM_BYTES = {WG_KF32: 8, WG_KBF16: 4, WG_KF16: 4}
 
@@ -39,7 +40,7 @@ class WgGeom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("beta", ctypes.c_int32), ("n_w", ctypes.c_int32),
                 ("s_lo", ctypes.c_int32), ("s_hi", ctypes.c_int32), ("m_img", ctypes.c_int32),
                 ("du", ctypes.c_double), ("w_max", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32)]
+                ("n_pol", ctypes.c_int32)]
 
 
 class WgKtable(ctypes.Structure):
@@ -82,7 +83,7 @@ def lib():
         L.wg_grid.restype = ctypes.c_int
         L.wg_grid.argtypes = [P, P, P, P, P, P]
         L.wg_degrid.restype = ctypes.c_int
-        L.wg_degrid.argtypes = [P, P, P, P, P, P, P, I64, I32, I32, P, P]
+        L.wg_degrid.argtypes = [P, P, P, P, P, P, P, P, I64, I32, I32, P, P]
         L.wg_finalise_ws_bytes.restype = ctypes.c_int
         L.wg_finalise_ws_bytes.argtypes = [P, P]
         L.wg_finalise.restype = ctypes.c_int
@@ -155,9 +156,10 @@ def wg_grid(geom, kt, runs: WgRuns, stats: torch.Tensor, grid: torch.Tensor, str
                          _stream(stream)), "wg_grid")
 
 
-def wg_degrid(geom, kt, runs: WgRuns, stats, grid, uvw, weight, nb, nc, nt, vis_out, stream=None):
+def wg_degrid(geom, kt, runs: WgRuns, stats, grid, uvw, weight, flag, nb, nc, nt, vis_out, stream=None):
     _check(lib().wg_degrid(ctypes.byref(geom), ctypes.byref(kt), ctypes.byref(runs), _p(stats), _p(grid), _p(uvw),
-                           _p(weight), int(nb), int(nc), int(nt), _p(vis_out), _stream(stream)), "wg_degrid")
+                           _p(weight), _p(flag), int(nb), int(nc), int(nt), _p(vis_out), _stream(stream)),
+           "wg_degrid")
 
 
 def wg_finalise_ws_bytes(geom: WgGeom) -> int:
@@ -179,11 +181,14 @@ def wg_finalise_stacked(geom: WgGeom, grids: torch.Tensor, normaliser: torch.Ten
 
 
 def finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, out=None, ws=None, stream=None) -> torch.Tensor:
-    """Dirty image float32 [n][n] from a complex64 [n][n] grid; `normaliser` is a one-element
-    float64 device tensor (a view of the statistics or of the per-channel normalisers)."""
+    """Dirty image float32 [n][n] from a complex64 [n][n] grid; with P = geom.n_pol > 1
+    polarisations, the Stokes images float32 [P][n][n] from a [n][n][P] grid. `normaliser`
+    holds P float64 values on the device (a view of the statistics or of the normalisers in
+    the runs)."""
     n = geom.n
+    npol = max(1, geom.n_pol)
     if out is None:
-        out = torch.empty((n, n), dtype=torch.float32, device=grid.device)
+        out = torch.empty((n, n) if npol == 1 else (npol, n, n), dtype=torch.float32, device=grid.device)
     if ws is None:
         ws = torch.empty(wg_finalise_ws_bytes(geom), dtype=torch.uint8, device=grid.device)
     wg_finalise(geom, torch.view_as_real(grid.contiguous()), normaliser, out, ws, stream)
@@ -192,15 +197,16 @@ def finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, out=Non
 
 # -------------------------------------------------------------------------- owning helpers
 def make_geom(n, beta, n_w, s_lo, s_hi, m_img, du, w_max, compress=True, per_channel=False,
-              w_stacking=False) -> WgGeom:
+              w_stacking=False, n_pol=1, circular=False) -> WgGeom:
     flags = ((WG_COMPRESS if compress else 0) | (WG_GRID_PER_CHANNEL if per_channel else 0)
-             | (WG_W_STACKING if w_stacking else 0))
-    return WgGeom(int(n), int(beta), int(n_w), int(s_lo), int(s_hi), int(m_img), float(du), float(w_max), flags, 0)
+             | (WG_W_STACKING if w_stacking else 0) | (WG_POL_CIRCULAR if circular else 0))
+    return WgGeom(int(n), int(beta), int(n_w), int(s_lo), int(s_hi), int(m_img), float(du), float(w_max), flags,
+                  int(n_pol))
 
 
-def geom_from_dict(d: dict, compress=True, per_channel=False, w_stacking=False) -> WgGeom:
+def geom_from_dict(d: dict, compress=True, per_channel=False, w_stacking=False, n_pol=1, circular=False) -> WgGeom:
     return make_geom(d["n"], d["beta"], d["n_w"], d["s_lo"], d["s_hi"], d["m_img"], d["du"], d["w_max"], compress,
-                     per_channel, w_stacking)
+                     per_channel, w_stacking, n_pol, circular)
 
 
 class KernelTable:
@@ -246,10 +252,12 @@ class Stats:
 class Runs:
     """Run list + plan + device statistics for one record batch."""
 
-    def __init__(self, capacity: int, n_segments: int, device="cuda", grid_ids: bool = False, n_norms: int = 0):
+    def __init__(self, capacity: int, n_segments: int, device="cuda", grid_ids: bool = False, n_norms: int = 0,
+                 n_pol: int = 1):
         dev = torch.device(device)
         cap = max(1, int(capacity))
         self.capacity = cap
+        self.n_pol = max(1, int(n_pol))
         self.start = torch.empty(cap, dtype=torch.int32, device=dev)
         self.len = torch.empty(cap, dtype=torch.int32, device=dev)
         self.x = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -257,23 +265,29 @@ class Runs:
         self.plane = torch.empty(cap, dtype=torch.int16, device=dev)
         self.ou = torch.empty(cap, dtype=torch.int8, device=dev)
         self.ov = torch.empty(cap, dtype=torch.int8, device=dev)
-        self.gamma = torch.empty(2 * cap, dtype=torch.float32, device=dev)
+        self.gamma = torch.empty(2 * cap * self.n_pol, dtype=torch.float32, device=dev)
         pe = wg_plan_elems(cap, n_segments)
         self.plan = torch.empty(pe, dtype=torch.int32, device=dev)
-        self.work = torch.empty(2 * cap, dtype=torch.float32, device=dev)
+        self.work = torch.empty(2 * cap * self.n_pol, dtype=torch.float32, device=dev)
         self.stats_d = torch.zeros(8, dtype=torch.int64, device=dev)
-        # per-channel grids and w-stacking: the grid of each run; per-channel grids: the
-        # normaliser of each grid
+        # per-channel grids and w-stacking: the grid of each run; per-channel grids or several
+        # polarisations: the normalisers [grid][polarisation]
         self.grid = torch.empty(cap, dtype=torch.int16, device=dev) if grid_ids else None
         self.norm = torch.zeros(n_norms, dtype=torch.float64, device=dev) if n_norms > 0 else None
         self.c = WgRuns(cap, _p(self.start), _p(self.len), _p(self.x), _p(self.y), _p(self.plane), _p(self.ou),
                         _p(self.ov), _p(self.gamma), _p(self.plan), pe, _p(self.work), _p(self.grid), _p(self.norm))
 
     def normaliser(self, g: int | None = None) -> torch.Tensor:
-        """One-element float64 device view of the normaliser (of grid g with per-channel grids)."""
-        if g is None:
+        """float64 device view of the normaliser(s): P values (of grid g with per-channel
+        grids; the one in the statistics when P = 1 and the grid is shared)."""
+        if self.norm is None:
             return self.stats_d.view(torch.float64)[6:7]
-        return self.norm[g:g + 1]
+        g = 0 if g is None else g
+        return self.norm[g * self.n_pol:(g + 1) * self.n_pol]
+
+    def _gamma_host(self, n):
+        g = torch.view_as_complex(self.gamma[: 2 * n * self.n_pol].view(n * self.n_pol, 2)).cpu().numpy()
+        return g if self.n_pol == 1 else g.reshape(n, self.n_pol)
 
     def stats(self) -> Stats:
         h = self.stats_d.cpu()
@@ -286,7 +300,7 @@ class Runs:
                     x=self.x[:n].cpu().numpy(), y=self.y[:n].cpu().numpy(),
                     plane=self.plane[:n].cpu().numpy(), ou=self.ou[:n].cpu().numpy(),
                     ov=self.ov[:n].cpu().numpy(),
-                    gamma=torch.view_as_complex(self.gamma[: 2 * n].view(n, 2)).cpu().numpy(), n_runs=n,
+                    gamma=self._gamma_host(n), n_runs=n,
                     grid=None if self.grid is None else self.grid[:n].cpu().numpy(),
                     norm=None if self.norm is None else self.norm.cpu().numpy())
 
@@ -309,21 +323,36 @@ class Gridder:
         self.per_channel = bool(geom.flags & WG_GRID_PER_CHANNEL)
         self.w_stacking = bool(geom.flags & WG_W_STACKING)
         self.n_grids = self.nc if self.per_channel else geom.n_w if self.w_stacking else 1
+        self.n_pol = max(1, geom.n_pol)
+        for name, arr in (("weight", self.weight), ("flag", self.flag)):
+            if arr is not None and arr.numel() != self.n_rec * self.n_pol:
+                raise ValueError(f"{name} has {arr.numel()} values, expected {self.n_rec} records x {self.n_pol}")
+        n_norms = self.nc * self.n_pol if self.per_channel else self.n_pol if self.n_pol > 1 else 0
         self.runs = Runs(self.n_rec, self.nb * self.nc, device=uvw.device,
-                         grid_ids=self.per_channel or self.w_stacking, n_norms=self.nc if self.per_channel else 0)
+                         grid_ids=self.per_channel or self.w_stacking, n_norms=n_norms, n_pol=self.n_pol)
 
     def grid_shape(self):
         n = self.geom.n
-        return (self.n_grids, n, n) if (self.per_channel or self.w_stacking) else (n, n)
+        shape = (self.n_grids, n, n) if (self.per_channel or self.w_stacking) else (n, n)
+        return shape if self.n_pol == 1 else shape + (self.n_pol,)
+
+    def vis_shape(self):
+        shape = (self.nb, self.nc, self.nt)
+        return shape if self.n_pol == 1 else shape + (self.n_pol,)
 
     def compress(self, vis, stream=None):
+        if vis.numel() != self.n_rec * self.n_pol * (1 if vis.is_complex() else 2):
+            raise ValueError(f"vis has shape {tuple(vis.shape)}, expected {self.vis_shape()} complex values")
         wg_compress(self.geom, self.table.kt, self.uvw, self.inv_lambda, _f32_view(vis.contiguous()), self.weight,
                     self.flag, self.nb, self.nc, self.nt, self.runs.c, self.runs.stats_d, stream)
 
     def grid(self, out=None, stream=None):
-        """Accumulate the batch into a complex64 grid ([n][n], or [nc][n][n] per channel)."""
+        """Accumulate the batch into a complex64 grid ([n][n], or [nc][n][n] per channel, or
+        [n_w][n][n] with w-stacking; [..., P] with P polarisations)."""
         if out is None:
             out = torch.zeros(self.grid_shape(), dtype=torch.complex64, device=self.uvw.device)
+        elif tuple(out.shape) != self.grid_shape():
+            raise ValueError(f"grid shape {tuple(out.shape)} != {self.grid_shape()}")
         wg_grid(self.geom, self.table.kt, self.runs.c, self.runs.stats_d, torch.view_as_real(out), stream)
         return out
 
@@ -331,15 +360,18 @@ class Gridder:
         if tuple(grid.shape) != self.grid_shape():
             raise ValueError(f"grid shape {tuple(grid.shape)} != {self.grid_shape()}")
         if out is None:
-            out = torch.empty((self.nb, self.nc, self.nt), dtype=torch.complex64, device=self.uvw.device)
+            out = torch.empty(self.vis_shape(), dtype=torch.complex64, device=self.uvw.device)
+        elif tuple(out.shape) != self.vis_shape():
+            raise ValueError(f"out shape {tuple(out.shape)} != {self.vis_shape()}")
         wg_degrid(self.geom, self.table.kt, self.runs.c, self.runs.stats_d, torch.view_as_real(grid.contiguous()),
-                  self.uvw, self.weight, self.nb, self.nc, self.nt, torch.view_as_real(out), stream)
+                  self.uvw, self.weight, self.flag, self.nb, self.nc, self.nt, torch.view_as_real(out), stream)
         return out
 
     def finalise(self, grid, out=None, stream=None):
         """Dirty image(s) of `grid` with this batch's normaliser(s) (wg_finalise): float32
         [n][n], or [nc][n][n] for per-channel grids (each with its channel's normaliser); one
-        [n][n] image of the w-plane grids with w-stacking (wg_finalise_stacked)."""
+        [n][n] image of the w-plane grids with w-stacking (wg_finalise_stacked). With P > 1
+        polarisations each image becomes P Stokes images ([P][n][n], [nc][P][n][n])."""
         if self.w_stacking:
             n = self.geom.n
             if out is None:
@@ -352,7 +384,8 @@ class Gridder:
             return finalise(self.geom, grid, self.runs.normaliser(), out=out, stream=stream)
         n = self.geom.n
         if out is None:
-            out = torch.empty((self.nc, n, n), dtype=torch.float32, device=grid.device)
+            shape = (self.nc, n, n) if self.n_pol == 1 else (self.nc, self.n_pol, n, n)
+            out = torch.empty(shape, dtype=torch.float32, device=grid.device)
         ws = torch.empty(wg_finalise_ws_bytes(self.geom), dtype=torch.uint8, device=grid.device)
         for c in range(self.nc):
             finalise(self.geom, grid[c], self.runs.normaliser(c), out=out[c], ws=ws, stream=stream)

@@ -85,10 +85,10 @@ def test_entry_points_reject_null_arguments(wg):
     assert L.wg_compress(by(g), by(kt_bad), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
     assert L.wg_grid(by(g), by(kt), by(runs), 1, None, None) == wg.WG_EINVAL
     assert L.wg_grid(by(g), None, by(runs), 1, 1, None) == wg.WG_EINVAL
-    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, None, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
-    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, 5, 1, 3, 1, None) == wg.WG_ECAPACITY
+    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, None, None, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
+    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, None, 5, 1, 3, 1, None) == wg.WG_ECAPACITY
     runs_nowork = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, None, None, None)
-    assert L.wg_degrid(by(g), by(kt), by(runs_nowork), 1, 1, 1, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
+    assert L.wg_degrid(by(g), by(kt), by(runs_nowork), 1, 1, 1, None, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
     assert L.wg_ktable_build(by(g), None, 1, 10, None, None, None) == wg.WG_EINVAL
     kt_small = wg.WgKtable(0, 8, 8, 0, 1, 1, 1, 1, 1, 10)
     assert L.wg_ktable_build(by(g), by(kt_small), 1, 10, None, None, None) == wg.WG_ECAPACITY
@@ -125,13 +125,13 @@ def test_per_channel_grids_need_their_arrays(wg):
     runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, 1, None, None)
     assert L.wg_compress(by(g), by(kt), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
     assert L.wg_grid(by(g), by(kt), by(runs), 1, 1, None) == wg.WG_EINVAL
-    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
+    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
     big = wg.WgRuns(1 << 20, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 24, 1, 1, 1)
     # 32 channels of 8192^2 cells (2^31) exceed the 31-bit cell index of per-channel grids
     g2 = wg.make_geom(8192, 8, 8, 7, 7, 256, 15.0, 100.0, per_channel=True)
     assert L.wg_compress(by(g2), by(kt), 1, 1, 1, None, None, 1, 32, 1, by(big), 1, None) == wg.WG_EUNSUPPORTED
     g_bad = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)
-    g_bad.flags = 8
+    g_bad.flags = 16
     size = ctypes.c_int64(0), ctypes.c_size_t(0)
     assert L.wg_ktable_sizes(by(g_bad), by(size[0]), by(size[1])) == wg.WG_EINVAL
 
@@ -146,7 +146,7 @@ def test_w_stacking_needs_grid_ids_and_excludes_per_channel(wg):
     runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, 1, None, None)
     assert L.wg_compress(by(g), by(kt), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
     assert L.wg_grid(by(g), by(kt), by(runs), 1, 1, None) == wg.WG_EINVAL
-    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
+    assert L.wg_degrid(by(g), by(kt), by(runs), 1, 1, 1, None, None, 1, 1, 1, 1, None) == wg.WG_EINVAL
     # 128 w-planes of 4096^2 cells (2^31) exceed the 31-bit cell index
     big = wg.WgRuns(1 << 20, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 24, 1, 1, None)
     g2 = wg.make_geom(4096, 8, 128, 7, 7, 256, 15.0, 100.0, w_stacking=True)
@@ -160,3 +160,25 @@ def test_w_stacking_needs_grid_ids_and_excludes_per_channel(wg):
     ws = ctypes.c_size_t(0)
     assert L.wg_finalise_ws_bytes(by(g), by(ws)) == wg.WG_OK
     assert ws.value >= 256 * 256 * (8 + 8 + 4)
+
+
+def test_polarisation_count_and_normalisers(wg):
+    """n_pol is 1 (or 0), 2 or 4; w-stacking takes one polarisation; several polarisations
+    need the per-polarisation normalisers in wg_runs."""
+    L = wg.lib()
+    by = ctypes.byref
+    size = ctypes.c_int64(0), ctypes.c_size_t(0)
+    for npol, want in [(0, wg.WG_OK), (1, wg.WG_OK), (2, wg.WG_OK), (4, wg.WG_OK), (3, wg.WG_EINVAL),
+                       (8, wg.WG_EINVAL), (-1, wg.WG_EINVAL)]:
+        g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, n_pol=npol)
+        assert L.wg_ktable_sizes(by(g), by(size[0]), by(size[1])) == want, npol
+    g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, w_stacking=True, n_pol=2)
+    assert L.wg_ktable_sizes(by(g), by(size[0]), by(size[1])) == wg.WG_EUNSUPPORTED
+    g4 = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, n_pol=4, circular=True)
+    kt = wg.WgKtable(0, 8, 8, 7, 1, 1, 1, 1, 1, 10)
+    runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, 1, None, None)
+    assert L.wg_compress(by(g4), by(kt), 1, 1, 1, None, None, 1, 1, 1, by(runs), 1, None) == wg.WG_EINVAL
+    ws1, ws4 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.wg_finalise_ws_bytes(by(wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)), by(ws1)) == wg.WG_OK
+    assert L.wg_finalise_ws_bytes(by(g4), by(ws4)) == wg.WG_OK
+    assert ws4.value >= ws1.value + 3 * 256 * 256 * 4

@@ -55,9 +55,9 @@ class Workload:
     cfg: int
     uvw: np.ndarray            # float64 [B, T, 3], metres
     inv_lambda: np.ndarray     # float64 [C], 1/m
-    vis: np.ndarray            # complex64 [B, C, T]
-    weight: np.ndarray         # float32 [B, C, T]
-    flag: np.ndarray           # uint8 [B, C, T]
+    vis: np.ndarray            # complex64 [B, C, T], or [B, C, T, P] (polarised)
+    weight: np.ndarray         # float32, the shape of vis
+    flag: np.ndarray           # uint8, the shape of vis
     geom: dict                 # n, beta, n_w, s_lo, s_hi, m_img, du, w_max
     sources: np.ndarray        # float64 [n_src, 3]: l, m, flux
     params: dict = field(default_factory=dict)
@@ -175,6 +175,55 @@ def make(cfg: int, device=None, **overrides) -> Workload:
     geom = dict(n=p["n"], beta=p["beta"], n_w=p["n_w"], s_lo=p["s_lo"], s_hi=p["s_hi"],
                 m_img=p["m_img"], du=float(du), w_max=w_max)
     return Workload(cfg, uvw, inv_lambda, vis, weight, flag, geom, sources, p)
+
+
+def polarised(cfg: int, n_pol: int = 4, circular: bool = False, device=None, flag_frac: float = 0.02,
+              **overrides) -> Workload:
+    """Workload `cfg` with P = n_pol products per record, [B, C, T, P]. Every source of the
+    total-intensity workload gets seeded fractional polarisation (|Q|, |U|, |V| up to 0.3 of
+    I); the products follow the feed relations XX = I + Q, XY = U + iV, YX = U - iV,
+    YY = I - Q (circular: RR = I + V, RL = Q + iU, LR = Q - iU, LL = I - V), P = 2 keeping
+    the parallel hands; each product gets its own noise (sigma 0.1), its own natural weight
+    (uniform 0.5..2, as from per-polarisation variances) and `flag_frac` of flags, and one
+    record in 200 is flagged in every product."""
+    assert n_pol in (2, 4)
+    w = make(cfg, device=device, **overrides)
+    rng = np.random.default_rng(5000 + cfg)
+    S = w.sources.shape[0]
+    frac = rng.uniform(-0.3, 0.3, (S, 3))
+    stokes = [w.vis]
+    for k in range(3):
+        src = w.sources.copy()
+        src[:, 2] = w.sources[:, 2] * frac[:, k]
+        stokes.append(point_source_vis(w.uvw, w.inv_lambda, src, 0.0, 3100 + 10 * cfg + k, device=device))
+    if device is not None and not isinstance(w.vis, np.ndarray):
+        import torch
+        xp_stack, j = torch.stack, 1j
+    else:
+        xp_stack, j = np.stack, 1j
+    I, Q, U, V = stokes
+    if circular:
+        prods = [I + V, Q + j * U, Q - j * U, I - V]
+    else:
+        prods = [I + Q, U + j * V, U - j * V, I - Q]
+    if n_pol == 2:
+        prods = [prods[0], prods[3]]
+    B, C, T = w.vis.shape
+    shp = (B, C, T, n_pol)
+    noise = rng.standard_normal(shp + (2,)).astype(np.float32) * np.float32(0.1)
+    wt = rng.uniform(0.5, 2.0, shp).astype(np.float32)
+    fl = (rng.uniform(size=shp) < flag_frac).astype(np.uint8)
+    fl[rng.uniform(size=(B, C, T)) < 0.005] = 1
+    if device is not None and not isinstance(w.vis, np.ndarray):
+        import torch
+        vis = xp_stack(prods, -1).to(torch.complex64)
+        nz = torch.as_tensor(noise, device=vis.device)
+        vis = vis + torch.complex(nz[..., 0], nz[..., 1])
+        wt, fl = torch.as_tensor(wt, device=vis.device), torch.as_tensor(fl, device=vis.device)
+    else:
+        vis = (xp_stack(prods, -1) + noise[..., 0] + 1j * noise[..., 1]).astype(np.complex64)
+    p = dict(w.params, n_pol=n_pol, circular=circular)
+    return Workload(cfg, w.uvw, w.inv_lambda, vis, wt, fl, w.geom, w.sources, p)
 
 
 def target_image(w: Workload, n_src: int = 100, seed: int = 4000) -> np.ndarray:
