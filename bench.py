@@ -10,7 +10,8 @@ rotation tracks and point-source visibilities) and resident in HBM before timing
 Prints ONE JSON line. `value` = grid-point updates per second over the step (the gridder's
 updates plus the degridder's, each sum over runs of S^2). Per-phase times, the BF16-table
 variant, the uncompressed variant, the w-stacking variant (grid per w-plane + stacked image
-against w-projection's grid + image), the image finaliser, the table-generation study, the
+against w-projection's grid + image), the polarisation variant (the same records as 2 and 4
+products), the image finaliser, the table-generation study, the
 gridder's roofline and the CPU oracle baseline are extra fields.
 """
 from __future__ import annotations
@@ -334,6 +335,47 @@ def main():
                              "image_ms": round(tcs + tgs + tfs, 4),
                              "w_projection_image_ms": round(t_comp + t_grid + out["finalise_ms"], 4)}
         del gs_, grids, img_s
+
+        # polarisations (the thesis's experiment batch 4): the same records as 4 and 2
+        # products (seeded polarised sources, per-product weights and flags); grid and degrid
+        # times against the single-polarisation step, record rates and product updates per second
+        pol = {}
+        wp = workloads.polarised(2, 4, device=dev)
+        for npol in (4, 2):
+            vp = wp.vis if npol == 4 else wp.vis[..., [0, 3]].contiguous()
+            wtp = wp.weight if npol == 4 else wp.weight[..., [0, 3]].contiguous()
+            flp = wp.flag if npol == 4 else wp.flag[..., [0, 3]].contiguous()
+            gp_ = wg.geom_from_dict(w.geom, n_pol=npol)
+            gpp = wg.Gridder(gp_, table, uvw, il, wtp, flp)
+            gridp = torch.zeros(gpp.grid_shape(), dtype=torch.complex64, device=dev)
+            voutp = torch.empty(gpp.vis_shape(), dtype=torch.complex64, device=dev)
+            tcp = tgp = tdp = 0.0
+            for i in range(args.steps + 1):
+                gridp.zero_()
+                ev[0].record()
+                gpp.compress(vp)
+                ev[1].record()
+                gpp.grid(out=gridp)
+                ev[2].record()
+                gpp.degrid(gridp, out=voutp)
+                ev[3].record()
+                torch.cuda.synchronize()
+                if i:
+                    tcp += ev[0].elapsed_time(ev[1])
+                    tgp += ev[1].elapsed_time(ev[2])
+                    tdp += ev[2].elapsed_time(ev[3])
+            tcp, tgp, tdp = tcp / args.steps, tgp / args.steps, tdp / args.steps
+            sp = gpp.runs.stats()
+            pol[str(npol)] = {"compress_ms": round(tcp, 4), "grid_ms": round(tgp, 4), "degrid_ms": round(tdp, 4),
+                              "runs": int(sp.n_runs),
+                              "grid_gupds_products": round(sp.upd_real * npol / (tgp * 1e-3) / 1e9, 2),
+                              "degrid_gupds_products": round(sp.upd_real * npol / (tdp * 1e-3) / 1e9, 2),
+                              "grid_record_rate_vs_1pol": round(t_grid / tgp, 3)}
+            del gpp, gridp, voutp
+        pol["1"] = {"grid_ms": round(t_grid, 4), "degrid_ms": round(t_degrid, 4),
+                    "grid_gupds_products": round(U / (t_grid * 1e-3) / 1e9, 2)}
+        out["polarisations"] = pol
+        del wp
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, vis.cpu().numpy(), U)
