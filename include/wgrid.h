@@ -27,8 +27,9 @@
  *     float32 [nb][nc][nt][P] (I-3; NULL means 1), flag uint8 [nb][nc][nt][P] (I-4;
  *     nonzero = flagged; NULL means none), with P = g->n_pol polarisations per record
  *     (WImager inputs: flags, weights and visibilities per polarisation).
- *   - Grid: complex64 [n][n][P] interleaved, row y follows v, column x follows u, cell
- *     (n/2, n/2) is u = v = 0 (gridding phase, Convolution Position sequence).
+ *   - Grid: complex64 [P][n][n] interleaved, one plane per polarisation, row y follows v,
+ *     column x follows u, cell (n/2, n/2) is u = v = 0 (gridding phase, Convolution Position
+ *     sequence). Per-channel grids are [nc][P][n][n].
  *   - Off-grid, flagged or non-finite records are not errors: they are not griddable
  *     (gridding indicator g = 0) and are counted in wg_stats. A record with at least one
  *     unflagged polarisation is griddable; its flagged polarisations add 0.
@@ -252,10 +253,10 @@ int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const 
                 int32_t nt, wg_runs *runs, wg_stats *stats, wg_stream_t stream);
 
 /*
- * Gridding phase (eq. gridding): for every run and polarisation p, grid[row0+i][a+j][p] +=
+ * Gridding phase (eq. gridding): for every run and polarisation p, grid[p][row0+i][a+j] +=
  * gamma[p] * K[i][j] with
  * a = x + n/2 - H, row0 = y + n/2 - H, K the run's matrix. ACCUMULATES into `grid`
- * (complex64 [n][n], or [nc][n][n] with WG_GRID_PER_CHANNEL or [n_w][n][n] with
+ * (complex64 [P][n][n], or [nc][P][n][n] with WG_GRID_PER_CHANNEL or [n_w][n][n] with
  * WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first. Accumulation is FP32 with Kahan
  * compensation per owned cell between commits; commits use FP32 atomic adds, so the last
  * bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
@@ -266,8 +267,8 @@ int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg
 
 /*
  * Adjoint of wg_compress + wg_grid with respect to the visibilities: per run
- * d[p] = sum_ij conj(K[i][j]) * grid[row0+i][a+j][p] (grid complex64 [n][n][P], or
- * [nc][n][n][P] / [n_w][n][n] read at grid runs->grid[q] with WG_GRID_PER_CHANNEL /
+ * d[p] = sum_ij conj(K[i][j]) * grid[p][row0+i][a+j] (grid complex64 [P][n][n], or
+ * [nc][P][n][n] / [n_w][n][n] read at grid runs->grid[q] with WG_GRID_PER_CHANNEL /
  * WG_W_STACKING; FP32, pairwise/tree summation; partial sums of the waves sharing a run
  * are combined with FP32 atomic adds into runs->work, so the last
  * bits depend on scheduling); polarisation p of record r of the run gets weight_{r,p} *
@@ -293,7 +294,7 @@ int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const 
  * (WG_POL_CIRCULAR): P = 1 gives the one polarisation as I; P = 2 gives (I, Q), or (I, V)
  * for circular feeds; P = 4 gives (I, Q, U, V). A polarisation whose normaliser is 0 adds
  * 0. Pixels where the taper is zero (first row and column) are 0. FFTs in FP32.
- *   grid   complex64 [n][n][P] (device, read only)
+ *   grid   complex64 [P][n][n] (device, read only)
  *   normaliser  P device doubles
  *   image  float32 [P][n][n] (device, OVERWRITTEN), the Stokes images in the order above
  *   ws     device workspace of wg_finalise_ws_bytes bytes (two n x n complex64 buffers,

@@ -131,11 +131,11 @@ def compress(geom, table, uvw, inv_lambda, vis, weight=None, flag=None, compress
 
 
 def grid(geom, table, runs, grid_in=None):
-    """eq. gridding in FP64 over `runs`; returns a complex128 [n, n] grid, [n, n, P] with P
+    """eq. gridding in FP64 over `runs`; returns a complex128 [n, n] grid, [P, n, n] with P
     polarisations (accumulates onto grid_in when given)."""
     n = geom["n"]
     npol = runs.get("npol", 1)
-    shape = (n, n) if npol == 1 else (n, n, npol)
+    shape = (n, n) if npol == 1 else (npol, n, n)
     g = np.zeros(shape, dtype=np.complex128) if grid_in is None else np.array(grid_in, dtype=np.complex128)
     data = np.ascontiguousarray(table["data"], dtype=np.complex128)
     gam = np.ascontiguousarray(runs["gamma"], dtype=np.complex128)

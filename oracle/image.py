@@ -115,16 +115,16 @@ STOKES = {
 
 
 def finalise_stokes(geom: dict, grid: np.ndarray, normalisers, circular: bool = False) -> dict:
-    """Dirty Stokes images {name: float64 [N][N]} from a [N][N][P] polarised grid (P = 1, 2
+    """Dirty Stokes images {name: float64 [N][N]} from a [P][N][N] polarised grid (P = 1, 2
     or 4) and its per-polarisation normalisers."""
     g = np.asarray(grid, dtype=np.complex128)
     if g.ndim == 2:
-        g = g[:, :, None]
-    npol = g.shape[2]
+        g = g[None]
+    npol = g.shape[0]
     norms = np.atleast_1d(np.asarray(normalisers, dtype=np.float64))
     pol_img = []
     for p in range(npol):
-        pol_img.append(transform(geom, g[:, :, p]) / norms[p] if norms[p] != 0.0 else None)
+        pol_img.append(transform(geom, g[p]) / norms[p] if norms[p] != 0.0 else None)
     c = axis_correction(geom)
     corr = np.outer(c, c)
     nz = corr != 0.0

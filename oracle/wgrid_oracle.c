@@ -34,7 +34,8 @@
  * [record][p]: P = 2 holds the two parallel hands (XX, YY or RR, LL), P = 4 the four
  * products (XX, XY, YX, YY or RR, RL, LR, LL). A record is griddable when it is on the grid
  * and at least one polarisation is unflagged; a flagged polarisation adds 0 (its (1 - f)
- * factor). The grid is [n][n][P], the normaliser one value per polarisation.
+ * factor). The grid is [P][n][n], one plane per polarisation; the normaliser one value
+ * per polarisation.
  * Reading for the flip: the measurement equation gives V_pq(-u) = conj V_qp(u) for a
  * polarised record, so with P = 4 a flipped record puts conj of its YX value (with YX's
  * weight and flag) into the XY slot and conj of XY into the YX slot; the parallel hands are
@@ -235,12 +236,12 @@ void or_index(int32_t n, int32_t beta, int32_t n_w, double uv_scale,
             }
 }
 
-/* eq. gridding: G[row0+i][a+j][p] += gamma[p] * K_plane[slice][i][j] for every run and
+/* eq. gridding: G[p][row0+i][a+j] += gamma[p] * K_plane[slice][i][j] for every run and
  * polarisation, FP64.
  * table: interleaved complex FP64, plane k starting at offset[k] complex elements; each
  * plane holds beta^2 slices of S_k x S_k row-major matrices, slice index
  * (o_v + beta/2 - 1)*beta + (o_u + beta/2 - 1). gamma: [nruns][npol] complex;
- * grid: [n][n][npol] complex, accumulated. */
+ * grid: [npol][n][n] complex, accumulated. */
 void or_grid(int32_t n, int32_t beta, int32_t npol, const int32_t *support, const int64_t *offset,
              const double *table, int64_t nruns, const int32_t *X, const int32_t *Y,
              const int32_t *plane, const int32_t *ou, const int32_t *ov,
@@ -256,7 +257,7 @@ void or_grid(int32_t n, int32_t beta, int32_t npol, const int32_t *support, cons
             for (int64_t i = 0; i < S; ++i)
                 for (int64_t j = 0; j < S; ++j) {
                     double kr = K[2 * (i * S + j)], ki = K[2 * (i * S + j) + 1];
-                    double *G = grid + 2 * (((row0 + i) * n + a + j) * npol + p);
+                    double *G = grid + 2 * ((int64_t)p * n * n + (row0 + i) * n + a + j);
                     G[0] += gr * kr - gi * ki;
                     G[1] += gr * ki + gi * kr;
                 }
@@ -265,7 +266,7 @@ void or_grid(int32_t n, int32_t beta, int32_t npol, const int32_t *support, cons
 }
 
 /* Adjoint of or_grid followed by the adjoint of the visibility weighting:
- * per run and polarisation d[p] = sum_ij conj(K[i][j]) * G[row0+i][a+j][p]; polarisation p
+ * per run and polarisation d[p] = sum_ij conj(K[i][j]) * G[p][row0+i][a+j]; polarisation p
  * of every member record x of the run gets weight_{x,p} (1 - f_{x,p}) times d[p], or, when
  * x is flipped, conj d[s] with s the slot its value went to (the cross hands exchange with
  * P = 4). Records in no run get 0. vis_out: [N_rec][npol] complex; weight, flag
@@ -289,7 +290,7 @@ void or_degrid(int32_t n, int32_t beta, int32_t npol, const int32_t *support, co
             for (int64_t i = 0; i < S; ++i)
                 for (int64_t j = 0; j < S; ++j) {
                     double kr = K[2 * (i * S + j)], ki = K[2 * (i * S + j) + 1];
-                    const double *G = grid + 2 * (((row0 + i) * n + a + j) * npol + p);
+                    const double *G = grid + 2 * ((int64_t)p * n * n + (row0 + i) * n + a + j);
                     dr[p] += kr * G[0] + ki * G[1];
                     di[p] += kr * G[1] - ki * G[0];
                 }

@@ -502,7 +502,7 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
     if (npol > 1 && !runs->norm) return WG_EINVAL;
     if (per_channel) {
         if (!runs->grid || !runs->norm) return WG_EINVAL;
-        if (nc > 32767 || (int64_t)nc * g->n * g->n >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
+        if (nc > 32767 || (int64_t)nc * npol * g->n * g->n >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
     }
     if (stack) {
         if (!runs->grid) return WG_EINVAL;

@@ -24,7 +24,8 @@ struct GArgs {
     const float2 *gamma;
     const int32_t *plan, *items;
     const int16_t *grid_id;  // the grid of each run (its channel or its w-plane), else NULL
-    int64_t cells;           // cells of one grid (n*n)
+    int64_t cells;           // cells of one polarisation's grid (n*n); polarisation p of a
+                             // cell is cells*p values further on
     int32_t *queue;  // work-list counter and exit count of this kernel (two plan words)
     const int64_t *offset;
     const void *data;
@@ -144,7 +145,7 @@ __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool val
         if (ax >= 0 && ax + S <= a.n && row0 >= 0 && row0 + S <= a.n && kbase >= 0 &&
             kbase + (int64_t)S * S <= a.data_cap) {
             b.ok = 1;
-            b.cell0 = row0 * a.n + ax + (a.grid_id ? (int)(a.grid_id[j] * a.cells) : 0);
+            b.cell0 = row0 * a.n + ax + (a.grid_id ? (int)(a.grid_id[j] * a.cells * NP) : 0);
             b.ph = (row0 % S) << 16 | (ax % S);
             b.kb = (int)kbase;
 #pragma unroll
@@ -282,11 +283,12 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
     // starts from acc = cmp, i.e. from the value zero, with the compensation term left as it
     // is (Kahan's recurrence holds from any starting pair).
     auto commit = [&](int m) {
-        float *cell = a.grid + 2 * (int64_t)(unsigned)cur[m] * NP;
+        float *cell = a.grid + 2 * (int64_t)(unsigned)cur[m];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            unsafeAtomicAdd(cell + 2 * p, acc_r[m][p] - cmp_r[m][p]);
-            unsafeAtomicAdd(cell + 2 * p + 1, acc_i[m][p] - cmp_i[m][p]);
+            // polarisation planes: neighbouring lanes' cells stay neighbours in memory
+            unsafeAtomicAdd(cell + 2 * p * a.cells, acc_r[m][p] - cmp_r[m][p]);
+            unsafeAtomicAdd(cell + 2 * p * a.cells + 1, acc_i[m][p] - cmp_i[m][p]);
             acc_r[m][p] = cmp_r[m][p];
             acc_i[m][p] = cmp_i[m][p];
         }
@@ -458,20 +460,11 @@ struct DStage {
     bool moved;            // wave-uniform: the run's footprint origin differs from the previous run's
 };
 
-// The NP complex values of one cell ([n][n][NP] grid), as one or two 16-byte loads.
+// The NP complex values of one cell, one from each polarisation plane ([NP][n][n] grid).
 template <int NP>
-__device__ inline void load_cell(const float2 *grid, unsigned cell, float2 *v) {
-    if constexpr (NP == 1) {
-        v[0] = grid[cell];
-    } else {
-        const float4 *g4 = (const float4 *)grid + (size_t)cell * (NP / 2);
+__device__ inline void load_cell(const float2 *grid, unsigned cell, int64_t cells, float2 *v) {
 #pragma unroll
-        for (int h = 0; h < NP / 2; ++h) {
-            const float4 q = g4[h];
-            v[2 * h] = make_float2(q.x, q.y);
-            v[2 * h + 1] = make_float2(q.z, q.w);
-        }
-    }
+    for (int p = 0; p < NP; ++p) v[p] = grid[cell + p * cells];
 }
 
 // A wave-uniform value held in a VGPR, so that an instruction taking it together with a
@@ -518,7 +511,7 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
 #pragma unroll
                 for (int m = 0; m < NS; ++m) {
                     wpos[m] = footprint_pos(cls[m], ph, ss);
-                    load_cell<NP>(grid, dot2(wpos[m], mul_c, cell0), st.g[m]);
+                    load_cell<NP>(grid, dot2(wpos[m], mul_c, cell0), a.cells, st.g[m]);
                 }
             }
 #pragma unroll

@@ -10,7 +10,7 @@
 // Pixels where the taper is zero (the first row and column, l or m = -FOV/2) are 0, and the
 // whole image is 0 when the normaliser is 0 (nothing was gridded).
 //
-// Polarised grids ([n][n][P], P = 2 or 4): each polarisation is transformed on its own and
+// Polarised grids ([P][n][n], P = 2 or 4): each polarisation is transformed on its own and
 // divided by its normaliser, and the Stokes images are the real parts of the linear
 // combinations given by the feed relations (XX = I + Q, XY = U + iV, YX = U - iV, YY = I - Q;
 // RR = I + V, RL = Q + iU, LR = Q - iU, LL = I - V), accumulated pixel by pixel in FP32 as
@@ -355,8 +355,8 @@ int finalise(const wg_geom *g, const float *grid, const double *normaliser, floa
     if (npol > 1) {
         StokesCoef c = stokes_coef(npol, (g->flags & WG_POL_CIRCULAR) != 0);
         for (int p = 0; p < npol; ++p) {
-            hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, (const float2 *)grid + p, A, n, lg, tw,
-                               npol);
+            hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, (const float2 *)grid + p * nn, A, n, lg,
+                               tw, 1);
             hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
             hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw, 1);
             hipLaunchKernelGGL(k_stokes_acc, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, acc, nn,

@@ -14,9 +14,9 @@ constexpr int kSlots = 8;          // most cell classes per lane in the gridder 
 constexpr int kSlotsNarrow = 6;    // the same with BF16/FP16 tables (measured faster there)
 constexpr int kDegridSlots = 5;    // the same for the degridder
 constexpr int kSlotsPol2 = 5;      // gridder with two polarisations (any table type)
-constexpr int kSlotsPol4 = 3;      // gridder with four polarisations
-constexpr int kDegridSlotsPol2 = 4;
-constexpr int kDegridSlotsPol4 = 2;
+constexpr int kSlotsPol4 = 3;      // gridder with four polarisations (2 to 5 measured alike)
+constexpr int kDegridSlotsPol2 = 5;  // degridder with two polarisations (4.33 vs 4.61 ms with 4)
+constexpr int kDegridSlotsPol4 = 3;  // with four (9.55 vs 11.65 ms with 2, 20.8 with 1)
 
 // ---------------------------------------------------------------------------------------
 // Plan layout (int32 words). Items are local chunks (first run, one past last run) of

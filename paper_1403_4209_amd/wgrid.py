@@ -182,7 +182,7 @@ def wg_finalise_stacked(geom: WgGeom, grids: torch.Tensor, normaliser: torch.Ten
 
 def finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, out=None, ws=None, stream=None) -> torch.Tensor:
     """Dirty image float32 [n][n] from a complex64 [n][n] grid; with P = geom.n_pol > 1
-    polarisations, the Stokes images float32 [P][n][n] from a [n][n][P] grid. `normaliser`
+    polarisations, the Stokes images float32 [P][n][n] from a [P][n][n] grid. `normaliser`
     holds P float64 values on the device (a view of the statistics or of the normalisers in
     the runs)."""
     n = geom.n
@@ -333,8 +333,9 @@ class Gridder:
 
     def grid_shape(self):
         n = self.geom.n
-        shape = (self.n_grids, n, n) if (self.per_channel or self.w_stacking) else (n, n)
-        return shape if self.n_pol == 1 else shape + (self.n_pol,)
+        if self.n_pol == 1:
+            return (self.n_grids, n, n) if (self.per_channel or self.w_stacking) else (n, n)
+        return (self.n_grids, self.n_pol, n, n) if self.per_channel else (self.n_pol, n, n)
 
     def vis_shape(self):
         shape = (self.nb, self.nc, self.nt)
@@ -348,7 +349,7 @@ class Gridder:
 
     def grid(self, out=None, stream=None):
         """Accumulate the batch into a complex64 grid ([n][n], or [nc][n][n] per channel, or
-        [n_w][n][n] with w-stacking; [..., P] with P polarisations)."""
+        [n_w][n][n] with w-stacking; [P][n][n] or [nc][P][n][n] with P polarisations)."""
         if out is None:
             out = torch.zeros(self.grid_shape(), dtype=torch.complex64, device=self.uvw.device)
         elif tuple(out.shape) != self.grid_shape():

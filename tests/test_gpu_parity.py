@@ -755,7 +755,7 @@ def _pol_case(case, npol, circular):
 def test_polarised_records(case, npol, circular, per_channel):
     """Records of 2 or 4 polarisation products with per-product weights and flags: runs
     bit-exact (a record is griddable with one unflagged product), gamma per product and the
-    per-product normalisers against the oracle; the [n][n][P] grid within relative L2 1e-5;
+    per-product normalisers against the oracle; the [P][n][n] grid within relative L2 1e-5;
     the adjoint (flagged products get 0) within 1e-5; every Stokes image within 1e-5 before
     the taper division. Per-channel grids: the same per channel."""
     from oracle import image as oimg
@@ -775,7 +775,7 @@ def test_polarised_records(case, npol, circular, per_channel):
         orc = oracle.compress(geom, otable(geom, "f32"), data["uvw"], data["il"], data["vis"], data["wt"],
                               data["flag"])
         compare_runs(gr, orc)
-        assert tuple(G.shape) == (geom["n"], geom["n"], npol)
+        assert tuple(G.shape) == (npol, geom["n"], geom["n"])
         o64 = oracle.compress(geom, t64, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"])
         Go = oracle.grid(geom, t64, o64)
         Gh = G.cpu().numpy().astype(np.complex128)
@@ -798,7 +798,7 @@ def test_polarised_records(case, npol, circular, per_channel):
             assert e < 1e-5
         return
     # per-channel grids: each channel against the oracle imaging that channel alone
-    assert tuple(G.shape) == (nc, geom["n"], geom["n"], npol)
+    assert tuple(G.shape) == (nc, npol, geom["n"], geom["n"])
     Gh = G.cpu().numpy().astype(np.complex128)
     norms = h["norm"].reshape(nc, npol)
     imgs = gr.finalise(G).cpu().numpy().astype(np.float64)

@@ -676,7 +676,7 @@ def test_polarised_slots_without_flips_are_single_polarisation_gridding(oracle_m
     flag[0, 0, :6, :] = 1                                   # some records flagged in every polarisation
     runs = oracle_mod.compress(geom, table, uvw, il, vis, wt, flag)
     G = oracle_mod.grid(geom, table, runs)
-    assert G.shape == (96, 96, npol)
+    assert G.shape == (npol, 96, 96)
     all_fl = flag.all(axis=3).astype(np.uint8)
     for p in range(npol):
         w1 = (wt[..., p] * (1 - flag[..., p])).astype(np.float32)
@@ -685,7 +685,7 @@ def test_polarised_slots_without_flips_are_single_polarisation_gridding(oracle_m
             assert np.array_equal(runs[k], r1[k]), k
         assert np.array_equal(runs["gamma"][:, p], r1["gamma"])
         assert runs["normaliser"][p] == r1["normaliser"]
-        assert np.array_equal(G[:, :, p], oracle_mod.grid(geom, table, r1))
+        assert np.array_equal(G[p], oracle_mod.grid(geom, table, r1))
 
 
 def test_flip_is_the_explicit_hermitian_partner(oracle_mod):
