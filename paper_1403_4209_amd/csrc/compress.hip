@@ -93,7 +93,8 @@ __device__ inline Key index_record(double um, double vm, double wm, double il, b
 
 __global__ void k_init(CArgs a, int64_t n_records) {
     if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i < kPlanHdr; i += blockDim.x) a.plan[i] = 0;
+        for (int i = threadIdx.x; i < kPlanHdr; i += blockDim.x)
+            a.plan[i] = i == kPlanGrids ? (a.grid_id ? (a.stack ? a.n_w : a.nc) : 1) : 0;
         if (a.norm)
             for (int c = threadIdx.x; c < (a.norm_per_ch ? a.nc : 1) * a.npol; c += blockDim.x) a.norm[c] = 0.0;
         if (threadIdx.x == 0) {

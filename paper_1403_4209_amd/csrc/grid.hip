@@ -137,15 +137,16 @@ __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool val
     if (valid) {
         const int H = (S - 1) >> 1, half = a.n >> 1, hb = a.beta >> 1;
         const int X = a.x[j], Y = a.y[j], k = a.plane[j];
+        const int gid = a.grid_id ? a.grid_id[j] : 0;
         const int sigma = (a.ov[j] + hb - 1) * a.beta + (a.ou[j] + hb - 1);
         const int ax = X + half - H, row0 = Y + half - H;
         const int64_t kbase = koff[k] + (int64_t)sigma * S * S;
         // runs from wg_compress with the same geometry and table always pass; anything else
         // is skipped rather than read or written out of bounds
         if (ax >= 0 && ax + S <= a.n && row0 >= 0 && row0 + S <= a.n && kbase >= 0 &&
-            kbase + (int64_t)S * S <= a.data_cap) {
+            kbase + (int64_t)S * S <= a.data_cap && gid >= 0 && gid < a.plan[kPlanGrids]) {
             b.ok = 1;
-            b.cell0 = row0 * a.n + ax + (a.grid_id ? (int)(a.grid_id[j] * a.cells * NP) : 0);
+            b.cell0 = row0 * a.n + ax + (int)(gid * a.cells * NP);
             b.ph = (row0 % S) << 16 | (ax % S);
             b.kb = (int)kbase;
 #pragma unroll

@@ -176,6 +176,8 @@ def wg_finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, imag
 
 def wg_finalise_stacked(geom: WgGeom, grids: torch.Tensor, normaliser: torch.Tensor, image: torch.Tensor,
                         ws: torch.Tensor, stream=None):
+    if grids.numel() != 2 * geom.n_w * geom.n * geom.n or image.numel() != geom.n * geom.n:
+        raise ValueError("wg_finalise_stacked: grids must hold n_w x n x n complex values, image n x n")
     _check(lib().wg_finalise_stacked(ctypes.byref(geom), _p(grids), _p(normaliser), _p(image), _p(ws),
                                      ws.numel() * ws.element_size(), _stream(stream)), "wg_finalise_stacked")
 
@@ -189,6 +191,9 @@ def finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, out=Non
     npol = max(1, geom.n_pol)
     if out is None:
         out = torch.empty((n, n) if npol == 1 else (npol, n, n), dtype=torch.float32, device=grid.device)
+    if grid.numel() != npol * n * n or out.numel() != npol * n * n or normaliser.numel() < npol:
+        raise ValueError(f"finalise: grid {tuple(grid.shape)}, image {tuple(out.shape)} and {normaliser.numel()} "
+                         f"normalisers do not fit {npol} polarisation(s) of {n} x {n}")
     if ws is None:
         ws = torch.empty(wg_finalise_ws_bytes(geom), dtype=torch.uint8, device=grid.device)
     wg_finalise(geom, torch.view_as_real(grid.contiguous()), normaliser, out, ws, stream)

@@ -830,3 +830,22 @@ def test_polarised_records(case, npol, circular, per_channel, dtype):
         ref = oimg.finalise_stokes(geom, Gh[c], norms[c], circular)
         for k, (name, r) in enumerate(ref.items()):
             assert _fin_err(imgs[c, k], r, geom) < 1e-5, (c, name)
+
+
+def test_runs_with_grid_ids_beyond_the_grids_are_skipped():
+    """Runs are checked before any grid access: with every run's grid id moved past the last
+    channel (or negative), wg_grid leaves the grids untouched and wg_degrid returns zeros."""
+    geom, data = cfg1()
+    g = wg.geom_from_dict(geom, per_channel=True)
+    table = wg.KernelTable(g, "f32", device=DEV)
+    uvw, il, vis, wt, fl = to_dev(data)
+    gr = wg.Gridder(g, table, uvw, il, wt, fl)
+    gr.compress(vis)
+    n_runs = gr.runs.stats().n_runs
+    assert n_runs > 0
+    for bad in (gr.nc, -1):
+        gr.runs.grid[:n_runs] = bad
+        G = gr.grid()
+        out = gr.degrid(torch.ones(gr.grid_shape(), dtype=torch.complex64, device=DEV))
+        torch.cuda.synchronize()
+        assert not torch.any(G != 0) and not torch.any(out != 0)
