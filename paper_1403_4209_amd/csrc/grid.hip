@@ -623,20 +623,35 @@ __global__ void k_zero_work(GArgs a) {
 }
 
 // Hands each run's dot products to its records: polarisation p gets weight * (1 - flag) *
-// (d[p], or conj d[s] when w < 0, s the slot its value went to).
+// (d[p], or conj d[s] when w < 0, s the slot its value went to). A wave takes 64 runs (in
+// record order) and its lanes walk their records in order, so that neighbouring lanes write
+// neighbouring records; each lane finds its record's run among the 64 by a shuffle search.
+// Records between runs (not griddable) keep the zero written before.
 template <int NP>
 __global__ void k_degrid_finish(GArgs a) {
     const int64_t n = a.stats->n_runs;
     const int64_t seglen = (int64_t)a.nt * a.nc;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        float2 d[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) d[p] = a.work[j * NP + p];
-        const int64_t r0 = a.start[j];
-        const int cnt = a.len[j];
-        for (int m = 0; m < cnt; ++m) {
-            const int64_t r = r0 + m;
-            if (r < 0 || r >= a.n_rec) break;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t j0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave; j0 < n;
+         j0 += nwaves * kWave) {
+        const int nv = (int)min((int64_t)kWave, n - j0);
+        const bool v = lane < nv;
+        const int st = v ? a.start[j0 + lane] : 0x7FFFFFFF;  // runs are in record order
+        const int ln = v ? a.len[j0 + lane] : 0;
+        const int64_t r_begin = __shfl(st, 0, kWave);
+        const int64_t r_end = min((int64_t)__shfl(st, nv - 1, kWave) + __shfl(ln, nv - 1, kWave), a.n_rec);
+        for (int64_t base = r_begin; base < r_end; base += kWave) {  // wave-uniform trip count
+            const int64_t r = base + lane;
+            int l = 0;  // the last of the 64 runs that starts at or before r
+            for (int step = kWave / 2; step >= 1; step >>= 1) {
+                const int c = l + step;
+                const int sc = __shfl(st, c < kWave ? c : kWave - 1, kWave);
+                if (c < nv && sc <= r) l = c;
+            }
+            const int sl = __shfl(st, l, kWave), ll = __shfl(ln, l, kWave);
+            if (r >= r_end || r < sl || r >= (int64_t)sl + ll) continue;
+            const int64_t j = j0 + l;
             const int64_t bb = r / seglen, tt = r - (r / a.nt) * a.nt;
             const double wm = a.uvw[(bb * a.nt + tt) * 3 + 2];
             const int psi = (wm >= 0.0) ? 1 : -1;
@@ -645,8 +660,8 @@ __global__ void k_degrid_finish(GArgs a) {
                 const int64_t e = r * NP + p;
                 float w = a.wt ? a.wt[e] : 1.0f;
                 if (NP > 1 && a.flag && a.flag[e]) w = 0.0f;
-                const float2 v = d[pol_source<NP>(p, psi)];
-                a.vis_out[e] = make_float2(w * v.x, w * (psi > 0 ? v.y : -v.y));
+                const float2 d = a.work[j * NP + pol_source<NP>(p, psi)];
+                a.vis_out[e] = make_float2(w * d.x, w * (psi > 0 ? d.y : -d.y));
             }
         }
     }
