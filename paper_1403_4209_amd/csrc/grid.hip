@@ -117,9 +117,19 @@ __device__ void build_units(const int32_t *plan, int slots, UnitTable *t) {
 
 // Run records of up to 64 consecutive runs, one per lane, with everything the per-run loop
 // needs precomputed in parallel; the loop then broadcasts run t with v_readlane.
+// FP32 tables are read only at non-negative oversample offsets. The kernel is even in u and
+// in v (eq. C_W: the taper and the w-screen are even in l and in m), so the matrix of offset
+// -o along an axis is the matrix of +o reversed along that axis (position j <-> S-1-j). Reading
+// the 25 of 64 slices with o >= 0 per axis, mirrored where the run's offset is negative, cuts
+// the samples a plane keeps in the caches by 2.5 (about 6 % off grid and degrid on a 32-plane
+// 2048^2 workload; with 16-bit tables the extra index arithmetic costs more than it saves).
+template <int DT>
+constexpr bool mirror_reads() { return DT == WG_KF32; }
+
 template <int NP>
 struct RunBatch {
     int cell0, ph, kb, ok;  // ph: footprint origin phases, (row0 mod S) << 16 | (ax mod S)
+    int mir;                // mirrored reads: 0xFFFF in each half whose offset is negative
     float gr[NP], gi[NP];   // the run's weighted visibility sum per polarisation
 };
 
@@ -127,18 +137,20 @@ __device__ inline int rl(int v, int t) { return __builtin_amdgcn_readlane(v, t);
 __device__ inline float rlf(float v, int t) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t)); }
 __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-template <int NP>
+template <int DT, int NP>
 __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool valid, const int64_t *koff) {
     RunBatch<NP> b;
     b.ok = 0;
-    b.cell0 = b.ph = b.kb = 0;
+    b.cell0 = b.ph = b.kb = b.mir = 0;
 #pragma unroll
     for (int p = 0; p < NP; ++p) b.gr[p] = b.gi[p] = 0.f;
     if (valid) {
         const int H = (S - 1) >> 1, half = a.n >> 1, hb = a.beta >> 1;
         const int X = a.x[j], Y = a.y[j], k = a.plane[j];
         const int gid = a.grid_id ? a.grid_id[j] : 0;
-        const int sigma = (a.ov[j] + hb - 1) * a.beta + (a.ou[j] + hb - 1);
+        const int ou = a.ou[j], ov = a.ov[j];
+        const int su = mirror_reads<DT>() ? abs(ou) : ou, sv = mirror_reads<DT>() ? abs(ov) : ov;
+        const int sigma = (sv + hb - 1) * a.beta + (su + hb - 1);
         const int ax = X + half - H, row0 = Y + half - H;
         const int64_t kbase = koff[k] + (int64_t)sigma * S * S;
         // runs from wg_compress with the same geometry and table always pass; anything else
@@ -149,6 +161,7 @@ __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool val
             b.cell0 = row0 * a.n + ax + (int)(gid * a.cells * NP);
             b.ph = (row0 % S) << 16 | (ax % S);
             b.kb = (int)kbase;
+            if (mirror_reads<DT>()) b.mir = (ou < 0 ? 0xFFFF : 0) | (ov < 0 ? (int)0xFFFF0000u : 0);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const float2 g = a.gamma[(int64_t)j * NP + p];
@@ -298,8 +311,20 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
-        const RunBatch<NP> b = load_batch<NP>(a, S, base + lane, lane < n, koff);
+        const RunBatch<NP> b = load_batch<DT, NP>(a, S, base + lane, lane < n, koff);
 
+        // the lane's samples of run t (mirrored positions where the run's offsets are negative)
+        auto load_samples = [&](int t, unsigned kbB, typename KRaw<DT>::type *k) {
+            const unsigned mir = mirror_reads<DT>() ? (unsigned)rl(b.mir, t) : 0u;
+            const u16x2 sm1 = {(unsigned short)(S - 1), (unsigned short)(S - 1)};
+#pragma unroll
+            for (int m = 0; m < NS; ++m) {
+                unsigned pos = __builtin_bit_cast(unsigned, wpos[m]);
+                if (mirror_reads<DT>())
+                    pos = (mir & __builtin_bit_cast(unsigned, (u16x2)(sm1 - wpos[m]))) | (~mir & pos);
+                k[m] = buf_load<DT>(rs, (int)dot2(as_u16x2(pos), mul_k, kbB));
+            }
+        };
         // cells (when the footprint moved) and samples of the lane's classes for run t
         auto fetch = [&](int t, Stage<DT> &st) {
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
@@ -315,8 +340,7 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
                     st.yc[m] = (int)dot2(wpos[m], mul_c, cell0);
                 }
             }
-#pragma unroll
-            for (int m = 0; m < NS; ++m) st.k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
+            load_samples(t, kbB, st.k);
         };
         auto accumulate = [&](int t, const Stage<DT> &st) {
             if (!rl(b.ok, t)) return;
@@ -499,8 +523,19 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
-        const RunBatch<NP> b = load_batch<NP>(a, S, base + lane, lane < n, koff);
+        const RunBatch<NP> b = load_batch<DT, NP>(a, S, base + lane, lane < n, koff);
 
+        auto load_samples = [&](int t, unsigned kbB, typename KRaw<DT>::type *k) {
+            const unsigned mir = mirror_reads<DT>() ? (unsigned)rl(b.mir, t) : 0u;
+            const u16x2 sm1 = {(unsigned short)(S - 1), (unsigned short)(S - 1)};
+#pragma unroll
+            for (int m = 0; m < NS; ++m) {
+                unsigned pos = __builtin_bit_cast(unsigned, wpos[m]);
+                if (mirror_reads<DT>())
+                    pos = (mir & __builtin_bit_cast(unsigned, (u16x2)(sm1 - wpos[m]))) | (~mir & pos);
+                k[m] = buf_load<DT>(rs, (int)dot2(as_u16x2(pos), mul_k, kbB));
+            }
+        };
         auto fetch = [&](int t, DStage<DT, NP> &st) {
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
@@ -515,8 +550,7 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
                     load_cell<NP>(grid, dot2(wpos[m], mul_c, cell0), a.cells, st.g[m]);
                 }
             }
-#pragma unroll
-            for (int m = 0; m < NS; ++m) st.k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
+            load_samples(t, kbB, st.k);
         };
         float sum_r[NP], sum_i[NP];  // lane t: this wave's sums for run base + t
 #pragma unroll

@@ -849,3 +849,33 @@ def test_runs_with_grid_ids_beyond_the_grids_are_skipped():
         out = gr.degrid(torch.ones(gr.grid_shape(), dtype=torch.complex64, device=DEV))
         torch.cuda.synchronize()
         assert not torch.any(G != 0) and not torch.any(out != 0)
+
+
+@pytest.mark.parametrize("case", ["cfg1", "cfg4"])
+def test_fp32_table_is_even_in_each_offset(case):
+    """The FP32 gridder and degridder read only slices of non-negative oversample offsets,
+    mirrored where a run's offset is negative. That rests on the kernel being even in u and
+    in v (eq. C_W with an even taper and w-screen): on the built table, the matrix of offset
+    -o along an axis equals the matrix of +o reversed along that axis, to FP32 rounding of
+    the two transform outputs (1e-6 of the plane's largest sample)."""
+    geom = cfg1()[0] if case == "cfg1" else cfg4_small()[0]
+    g = wg.geom_from_dict(geom)
+    tb = wg.KernelTable(g, "f32", device=DEV)
+    data = tb.data_complex().cpu().numpy()
+    beta, hb = geom["beta"], geom["beta"] // 2
+    worst = 0.0
+    for k in range(geom["n_w"]):
+        S = tb.support[k]
+        plane = data[tb.offset[k]:tb.offset[k + 1]].reshape(beta, beta, S, S)   # [ov][ou][i][j]
+        peak = np.max(np.abs(plane))
+        for ov in range(-hb + 1, hb + 1):
+            for ou in range(-hb + 1, hb + 1):
+                m = plane[ov + hb - 1, ou + hb - 1]
+                src = plane[abs(ov) + hb - 1, abs(ou) + hb - 1]
+                if ou < 0:
+                    src = src[:, ::-1]
+                if ov < 0:
+                    src = src[::-1, :]
+                worst = max(worst, float(np.max(np.abs(m - src))) / peak)
+    say(f"  {case}: largest mirror difference {worst:.2e} of the plane peak")
+    assert worst < 1e-6
