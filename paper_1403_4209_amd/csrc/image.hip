@@ -133,27 +133,45 @@ __device__ inline void ifft_pass(float2 *buf, const float2 *in, float2 *out, int
     __syncthreads();
 }
 
+// The passes of an N = 2^LG point transform with their radices fixed at compile time (the
+// first pass takes the LG mod 4 leftover bits, the others radix 16), so that every array
+// index and stride is a constant and the lane's 16 values stay in registers.
+template <int LG, int PASS, int NS_LOG>
+__device__ inline void ifft_passes(float2 *buf, const float2 *in, float2 *out, bool active, const float2 *tw,
+                                   int stride) {
+    constexpr int kBits = PASS == 0 && (LG & 3) ? (LG & 3) : 4;
+    constexpr int kDone = NS_LOG + kBits;
+    ifft_pass<1 << kBits>(buf, in, out, 1 << LG, 1 << NS_LOG, PASS == 0, kDone == LG, active, tw, stride);
+    if constexpr (kDone < LG) ifft_passes<LG, PASS + 1, kDone>(buf, in, out, active, tw, stride);
+}
+
 // Rows of src (N x N complex values, `stride` apart: one polarisation of a polarised grid)
 // -> inverse transforms in dst; ifftshift on input and fftshift on output. blockDim >= N/16.
+template <int LG>
 __global__ __launch_bounds__(512) void k_ifft_rows(const float2 *__restrict__ src, float2 *__restrict__ dst,
-                                                   int n, int lg, const float2 *__restrict__ tw, int stride) {
+                                                   const float2 *__restrict__ tw, int stride) {
     extern __shared__ float2 buf[];
+    constexpr int n = 1 << LG;
     const float2 *in = src + (size_t)blockIdx.x * n * stride;
     float2 *out = dst + (size_t)blockIdx.x * n;
     const bool active = (int)threadIdx.x < (n >> 4);
-    const int P = (lg + 3) >> 2;
-    int ns = 1, rem = lg;
-    for (int p = 0; p < P; ++p) {
-        const int bits = (p == 0 && (lg & 3)) ? (lg & 3) : 4;
-        rem -= bits;
-        const bool first = p == 0, last = rem == 0;
-        switch (bits) {
-        case 1: ifft_pass<2>(buf, in, out, n, ns, first, last, active, tw, stride); break;
-        case 2: ifft_pass<4>(buf, in, out, n, ns, first, last, active, tw, stride); break;
-        case 3: ifft_pass<8>(buf, in, out, n, ns, first, last, active, tw, stride); break;
-        default: ifft_pass<16>(buf, in, out, n, ns, first, last, active, tw, stride); break;
-        }
-        ns <<= bits;
+    ifft_passes<LG, 0, 0>(buf, in, out, active, tw, stride);
+}
+
+using RowFft = void (*)(const float2 *, float2 *, const float2 *, int);
+
+RowFft row_fft(int lg) {
+    switch (lg) {
+    case 4: return k_ifft_rows<4>;
+    case 5: return k_ifft_rows<5>;
+    case 6: return k_ifft_rows<6>;
+    case 7: return k_ifft_rows<7>;
+    case 8: return k_ifft_rows<8>;
+    case 9: return k_ifft_rows<9>;
+    case 10: return k_ifft_rows<10>;
+    case 11: return k_ifft_rows<11>;
+    case 12: return k_ifft_rows<12>;
+    default: return k_ifft_rows<13>;
     }
 }
 
@@ -347,6 +365,7 @@ int finalise(const wg_geom *g, const float *grid, const double *normaliser, floa
     TaperCoef tc;
     prolate_coefficients(kTaperC, &tc);
     const int threads = n / 16 > 64 ? n / 16 : 64;
+    const RowFft rows = row_fft(lg);
     const size_t lds = sizeof(float2) * (size_t)n;
     const dim3 tiles((n + 31) / 32, (n + 31) / 32), tb(32, 8);
     hipLaunchKernelGGL(k_fin_setup, dim3((n + 255) / 256), dim3(256), 0, s, tw, corr, n, g->beta, tc);
@@ -355,10 +374,9 @@ int finalise(const wg_geom *g, const float *grid, const double *normaliser, floa
     if (npol > 1) {
         StokesCoef c = stokes_coef(npol, (g->flags & WG_POL_CIRCULAR) != 0);
         for (int p = 0; p < npol; ++p) {
-            hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, (const float2 *)grid + p * nn, A, n, lg,
-                               tw, 1);
+            hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, (const float2 *)grid + p * nn, A, tw, 1);
             hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
-            hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw, 1);
+            hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, B, A, tw, 1);
             hipLaunchKernelGGL(k_stokes_acc, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, acc, nn,
                                normaliser, p, c);
         }
@@ -370,9 +388,9 @@ int finalise(const wg_geom *g, const float *grid, const double *normaliser, floa
     const int planes = stacked ? g->n_w : 1;
     for (int k = 0; k < planes; ++k) {
         const float2 *G = (const float2 *)grid + (size_t)k * nn;
-        hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, G, A, n, lg, tw, 1);
+        hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, G, A, tw, 1);
         hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
-        hipLaunchKernelGGL(k_ifft_rows, dim3(n), dim3(threads), lds, s, B, A, n, lg, tw, 1);
+        hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, B, A, tw, 1);
         if (stacked) {
             // the plane's w, computed as the table generator places its planes
             const double q = g->n_w > 1 ? (double)k / (double)(g->n_w - 1) : 0.0;
