@@ -128,16 +128,6 @@ __device__ inline void stockham_pass(int M, int nsub, int ns, int L, const doubl
     }
 }
 
-template <class Ld, class St>
-__device__ inline void stockham_any(int R, int M, int nsub, int ns, int L, const double2 *tw, Ld ld, St st) {
-    switch (R) {
-    case 2: stockham_pass<2>(M, nsub, ns, L, tw, ld, st); break;
-    case 4: stockham_pass<4>(M, nsub, ns, L, tw, ld, st); break;
-    case 8: stockham_pass<8>(M, nsub, ns, L, tw, ld, st); break;
-    default: stockham_pass<16>(M, nsub, ns, L, tw, ld, st); break;
-    }
-}
-
 // Passes of an M-point transform (M = 2^lgM): radix 2^(lgM mod 4) first when lgM is not a
 // multiple of 4, radix 16 after that.
 __host__ __device__ inline int n_passes(int lgM) { return (lgM + 3) / 4; }
@@ -146,37 +136,40 @@ __host__ __device__ inline int n_passes(int lgM) { return (lgM + 3) / 4; }
 // LDS or global memory, x[n + M/2] = sample n): first(b, e) = x[n] w_L^(n b) feeds the first
 // pass, out(b, k1, v) receives X[beta*k1 + b]. buf0 and buf1 hold beta*M values each in LDS
 // (buf1 only with three or more passes; it may alias x, which the first pass alone reads).
-template <class Out>
+// Pass PASS of the M = 2^LGM point transforms, its radix fixed at compile time (the first
+// pass takes the LGM mod 4 leftover bits, the others radix 16), then the passes after it.
+template <int LGM, int PASS, int NS_LOG, class First, class Out>
+__device__ inline void dft_passes(const BuildArgs &a, const double2 *src, double2 *dst, double2 *buf0, double2 *buf1,
+                                  First first, Out out) {
+    constexpr int kBits = PASS == 0 && (LGM & 3) ? (LGM & 3) : 4;
+    constexpr int kDone = NS_LOG + kBits;
+    constexpr bool kLast = kDone == LGM;
+    constexpr int M = 1 << LGM, R = 1 << kBits, ns = 1 << NS_LOG;
+    auto lds_ld = [&](int b, int e) { return src[b * M + e]; };
+    auto lds_st = [&](int b, int e, double2 v) { dst[b * M + e] = v; };
+    if constexpr (PASS == 0 && kLast)
+        stockham_pass<R>(M, a.beta, ns, a.L, a.tw, first, out);
+    else if constexpr (PASS == 0)
+        stockham_pass<R>(M, a.beta, ns, a.L, a.tw, first, lds_st);
+    else if constexpr (kLast)
+        stockham_pass<R>(M, a.beta, ns, a.L, a.tw, lds_ld, out);
+    else
+        stockham_pass<R>(M, a.beta, ns, a.L, a.tw, lds_ld, lds_st);
+    __syncthreads();
+    if constexpr (!kLast)
+        dft_passes<LGM, PASS + 1, kDone>(a, dst, dst == buf0 ? buf1 : buf0, buf0, buf1, first, out);
+}
+
+template <int LGM, class Out>
 __device__ void oversampled_dft(const BuildArgs &a, const double2 *x, double2 *buf0, double2 *buf1, Out out) {
-    const int M = a.M, L = a.L, nsub = a.beta;
+    constexpr int M = 1 << LGM;
+    const int L = a.L;
     const double2 *tw = a.tw;
     auto first = [&](int b, int e) {
         const int n = e - ((e >= M / 2) ? M : 0);
         return cmul(x[(e + M / 2) & (M - 1)], tw[(n * b) & (L - 1)]);
     };
-    const int P = n_passes(a.lgM);
-    int ns = 1, rem = a.lgM;
-    double2 *src = nullptr, *dst = buf0;
-    for (int p = 0; p < P; ++p) {
-        const int bits = (p == 0 && (a.lgM & 3)) ? (a.lgM & 3) : 4;
-        const int R = 1 << bits;
-        rem -= bits;
-        const bool last = rem == 0;
-        auto lds_ld = [&](int b, int e) { return src[b * M + e]; };
-        auto lds_st = [&](int b, int e, double2 v) { dst[b * M + e] = v; };
-        if (p == 0 && last)
-            stockham_any(R, M, nsub, ns, L, tw, first, out);
-        else if (p == 0)
-            stockham_any(R, M, nsub, ns, L, tw, first, lds_st);
-        else if (last)
-            stockham_any(R, M, nsub, ns, L, tw, lds_ld, out);
-        else
-            stockham_any(R, M, nsub, ns, L, tw, lds_ld, lds_st);
-        __syncthreads();
-        ns <<= bits;
-        src = dst;
-        dst = (dst == buf0) ? buf1 : buf0;
-    }
+    dft_passes<LGM, 0, 0>(a, nullptr, buf0, buf0, buf1, first, out);
 }
 
 __global__ void k_twiddle(double2 *tw, int L) {
@@ -208,6 +201,7 @@ inline size_t dft_lds_bytes(int M, int L, int lgM) {
 // unpaired sample (x = -1) has taper 0. So row M - q equals row q, row 0 is zero, and each row
 // transform is even in u. Only rows q >= M/2 are transformed (each stored also as row M - q)
 // and only the columns the column pass reads (u >= 0 and the Nyquist column -L/2) are stored.
+template <int LGM>
 __global__ __launch_bounds__(128) void k_rows(BuildArgs a) {
     extern __shared__ double2 lds[];
     double2 *buf0 = lds, *xin = lds + a.L;
@@ -235,7 +229,7 @@ __global__ __launch_bounds__(128) void k_rows(BuildArgs a) {
     __syncthreads();
     double2 *plane = a.A + (size_t)k * a.L * a.M;
     const int L = a.L, M = a.M, beta = a.beta;
-    oversampled_dft(a, xin, buf0, xin, [&](int b, int k1, double2 v) {
+    oversampled_dft<LGM>(a, xin, buf0, xin, [&](int b, int k1, double2 v) {
         const int cu = (k1 * beta + b + L / 2) & (L - 1);
         if (cu != 0 && cu < L / 2) return;  // u < 0: the column pass uses the mirror column
         double2 *col = plane + (size_t)cu * M;
@@ -279,6 +273,7 @@ __global__ void k_c00_and_reset(BuildArgs a, double *wbound) {
 // The support test |C/c00| > 1e-3 is decided on |C|^2 against (1e-3 c00)^2 wherever the two
 // differ by more than a relative 1e-9 (far beyond the rounding of either side); only values
 // closer than that take the exact quotient and hypot, so every decision equals the exact one.
+template <int LGM>
 __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     extern __shared__ double2 lds[];
     __shared__ int red[128];
@@ -297,7 +292,7 @@ __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     double2 *win = a.win + (size_t)k * W * W + (fu + Wf);
     const int mirror = -2 * fu;  // column -fu relative to column fu
     int dmax = 0;
-    oversampled_dft(a, xin, buf0, xin, [&](int b, int k1, double2 s) {
+    oversampled_dft<LGM>(a, xin, buf0, xin, [&](int b, int k1, double2 s) {
         const int fv = ((k1 * beta + b + L / 2) & (L - 1)) - L / 2;
         const double r2 = s.x * s.x + s.y * s.y;
         bool above = r2 > t2_hi;
@@ -434,6 +429,26 @@ WsLayout ws_layout(const wg_geom *g) {
 }  // namespace
 }  // namespace wg
 
+namespace wg {
+namespace {
+
+// The row (ROWS) or column kernel for M = 2^lgM image samples (16..1024).
+template <bool ROWS>
+void (*line_kernel(int lgM))(BuildArgs) {
+    switch (lgM) {
+    case 4: return ROWS ? k_rows<4> : k_cols<4>;
+    case 5: return ROWS ? k_rows<5> : k_cols<5>;
+    case 6: return ROWS ? k_rows<6> : k_cols<6>;
+    case 7: return ROWS ? k_rows<7> : k_cols<7>;
+    case 8: return ROWS ? k_rows<8> : k_cols<8>;
+    case 9: return ROWS ? k_rows<9> : k_cols<9>;
+    default: return ROWS ? k_rows<10> : k_cols<10>;
+    }
+}
+
+}  // namespace
+}  // namespace wg
+
 extern "C" int wg_ktable_sizes(const wg_geom *g, int64_t *data_elems_max, size_t *ws_bytes) {
     int st = wg::check_geom(g);
     if (st != WG_OK) return st;
@@ -481,9 +496,9 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
     const size_t lds = dft_lds_bytes(a.M, a.L, a.lgM);
     hipLaunchKernelGGL(k_twiddle, dim3((a.L + 255) / 256), dim3(256), 0, s, (double2 *)a.tw, a.L);
     hipLaunchKernelGGL(k_taper, dim3((a.M + 255) / 256), dim3(256), 0, s, a, tc);
-    hipLaunchKernelGGL(k_rows, dim3(a.M / 2, a.n_w), dim3(128), lds, s, a);
+    hipLaunchKernelGGL(line_kernel<true>(a.lgM), dim3(a.M / 2, a.n_w), dim3(128), lds, s, a);
     hipLaunchKernelGGL(k_c00_and_reset, dim3(1), dim3(256), 0, s, a, kt->wbound);
-    hipLaunchKernelGGL(k_cols, dim3(a.L / 2 + 1, a.n_w), dim3(128), lds, s, a);
+    hipLaunchKernelGGL(line_kernel<false>(a.lgM), dim3(a.L / 2 + 1, a.n_w), dim3(128), lds, s, a);
     hipLaunchKernelGGL(k_supports, dim3(1), dim3(64), 0, s, a, g->s_lo, g->s_hi, kt->support, kt->offset);
     if (hipGetLastError() != hipSuccess) return WG_EHIP;
 
