@@ -226,21 +226,35 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
 #pragma unroll
     for (int q = 0; q < NP; ++q) my_norm[q] = 0.0;
 
+    // uvw of the lane's record one step ahead: each step's loads are in flight while the
+    // previous step is indexed
+    const double *uvw_b = a.uvw + b * a.nt * 3;
+    double nu = 0.0, nv = 0.0, nw = 0.0;
+    if (lane < a.nt) {
+        nu = uvw_b[lane * 3];
+        nv = uvw_b[lane * 3 + 1];
+        nw = uvw_b[lane * 3 + 2];
+    }
     for (int t0 = 0; t0 < a.nt; t0 += kWave) {
         const int t = t0 + lane;
         const bool valid = t < a.nt;
         const int64_t r = seg * a.nt + t;
+        const double cu = nu, cv = nv, cw = nw;
+        if (t + kWave < a.nt) {
+            nu = uvw_b[(t + kWave) * 3];
+            nv = uvw_b[(t + kWave) * 3 + 1];
+            nw = uvw_b[(t + kWave) * 3 + 2];
+        }
         Key key;
         key.ok = 0;
         key.X = key.Y = key.k = key.ou = key.ov = 0;
         key.psi = 1;
         if (valid) {
-            const double *p = a.uvw + (b * a.nt + t) * 3;
             bool fl = a.flag != nullptr;  // dropped only when every polarisation is flagged
 #pragma unroll
             for (int q = 0; q < NP; ++q)
                 if (a.flag && a.flag[r * NP + q] == 0) fl = false;
-            key = index_record(p[0], p[1], p[2], il, fl, a, s_wb, s_sup);
+            key = index_record(cu, cv, cw, il, fl, a, s_wb, s_sup);
         }
         int pX = __shfl_up(key.X, 1, kWave), pY = __shfl_up(key.Y, 1, kWave);
         int pK = __shfl_up(key.k, 1, kWave), pOu = __shfl_up(key.ou, 1, kWave);
