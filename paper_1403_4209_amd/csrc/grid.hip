@@ -619,21 +619,23 @@ __device__ inline void degrid_dispatch(int ns, const GArgs &a, int S, int c0, in
     }
 }
 
-template <int NP>
-constexpr int degrid_slots() { return NP == 4 ? kDegridSlotsPol4 : NP == 2 ? kDegridSlotsPol2 : kDegridSlots; }
+template <int DT, int NP>
+constexpr int degrid_slots() {
+    return NP == 4 ? kDegridSlotsPol4 : NP == 2 ? kDegridSlotsPol2 : DT == WG_KF32 ? kDegridSlots : kDegridSlotsNarrow;
+}
 
 template <int DT, int NP>
 __device__ void degrid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
     int c0, c1, ns;
-    chunk_classes(S, chunk, degrid_slots<NP>(), c0, c1, ns);
-    degrid_dispatch<DT, NP, 1, degrid_slots<NP>()>(ns, a, S, c0, c1, rb, re, lane, koff);
+    chunk_classes(S, chunk, degrid_slots<DT, NP>(), c0, c1, ns);
+    degrid_dispatch<DT, NP, 1, degrid_slots<DT, NP>()>(ns, a, S, c0, c1, rb, re, lane, koff);
 }
 
 template <int DT, int NP>
 __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, degrid_slots<NP>(), &ut);
+    if (threadIdx.x == 0) build_units(a.plan, degrid_slots<DT, NP>(), &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -641,7 +643,7 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     for_each_unit(nunits, a.queue, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_of(S, degrid_slots<NP>());
+        const int S = uni(ut.S[m]), nch = nchunk_of(S, degrid_slots<DT, NP>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;

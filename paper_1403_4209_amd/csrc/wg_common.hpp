@@ -12,7 +12,8 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxS = WG_MAX_SUPPORT;
 constexpr int kSlots = 8;          // most cell classes per lane in the gridder (register budget)
 constexpr int kSlotsNarrow = 6;    // the same with BF16/FP16 tables (measured faster there)
-constexpr int kDegridSlots = 5;    // the same for the degridder
+constexpr int kDegridSlots = 7;    // the same for the degridder (FP32 tables: 3.06 ms, 3.14 with 5)
+constexpr int kDegridSlotsNarrow = 6;  // with BF16/FP16 tables (2.51 ms, 2.57 with 5)
 constexpr int kSlotsPol2 = 5;      // gridder with two polarisations (any table type)
 constexpr int kSlotsPol4 = 3;      // gridder with four polarisations (2 to 5 measured alike)
 constexpr int kDegridSlotsPol2 = 5;  // degridder with two polarisations (4.33 vs 4.61 ms with 4)
