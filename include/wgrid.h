@@ -97,7 +97,7 @@ typedef enum wg_kdtype {
  *           WG_W_STACKING; or 0 (unknown bits or both grid modes: WG_EINVAL).
  *   n_pol   polarisations per record P: 1 (0 is read as 1), 2 (the parallel hands XX, YY or
  *           RR, LL) or 4 (XX, XY, YX, YY or RR, RL, LR, LL), in that order; others are
- *           WG_EINVAL. WG_W_STACKING needs P = 1 (else WG_EUNSUPPORTED).
+ *           WG_EINVAL.
  *           The flip of a record with w < 0 (eq. conj) conjugates each value; with P = 4 it
  *           also exchanges the cross hands with their weights and flags (the partner of a
  *           polarised record: V_pq(-u) = conj V_qp(u)).
@@ -256,8 +256,8 @@ int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const 
  * Gridding phase (eq. gridding): for every run and polarisation p, grid[p][row0+i][a+j] +=
  * gamma[p] * K[i][j] with
  * a = x + n/2 - H, row0 = y + n/2 - H, K the run's matrix. ACCUMULATES into `grid`
- * (complex64 [P][n][n], or [nc][P][n][n] with WG_GRID_PER_CHANNEL or [n_w][n][n] with
- * WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first. Accumulation is FP32 with Kahan
+ * (complex64 [P][n][n], or [nc][P][n][n] with WG_GRID_PER_CHANNEL or [n_w][P][n][n]
+ * with WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first. Accumulation is FP32 with Kahan
  * compensation per owned cell between commits; commits use FP32 atomic adds, so the last
  * bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
  * Errors: WG_EINVAL, WG_EHIP.
@@ -268,7 +268,7 @@ int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg
 /*
  * Adjoint of wg_compress + wg_grid with respect to the visibilities: per run
  * d[p] = sum_ij conj(K[i][j]) * grid[p][row0+i][a+j] (grid complex64 [P][n][n], or
- * [nc][P][n][n] / [n_w][n][n] read at grid runs->grid[q] with WG_GRID_PER_CHANNEL /
+ * [nc][P][n][n] / [n_w][P][n][n] read at grid runs->grid[q] with WG_GRID_PER_CHANNEL /
  * WG_W_STACKING; FP32, pairwise/tree summation; partial sums of the waves sharing a run
  * are combined with FP32 atomic adds into runs->work, so the last
  * bits depend on scheduling); polarisation p of record r of the run gets weight_{r,p} *
@@ -315,7 +315,9 @@ int wg_finalise(const wg_geom *g, const float *grid, const double *normaliser, f
  * divided by the taper and sinc corrections. The correction is the image-plane factor that
  * the w-projection kernel of plane k carries (eq. C_W), so the stacked image equals the
  * w-projection image up to the truncation of the kernels to their supports.
- *   grids  complex64 [n_w][n][n] (device, read only), grid k holding w-plane k's records
+ *   grids  complex64 [n_w][P][n][n] (device, read only), grid k holding w-plane k's records;
+ *          with P > 1 each product is stacked and the Stokes images are formed as in
+ *          wg_finalise (image [P][n][n], normaliser P doubles)
  *   normaliser, image, ws as for wg_finalise (ws of wg_finalise_ws_bytes bytes). The
  *   accumulation over planes is FP32, plane by plane in order.
  * Errors: as wg_finalise; WG_EINVAL also when g->flags lacks WG_W_STACKING.

@@ -197,9 +197,13 @@ def w_stacking(geom, table, uvw, inv_lambda, vis, weight=None, flag=None, compre
     give it (nearest plane in sqrt(w), after the flip of eq. conj); the records of plane j are
     compressed and gridded with the w = 0 kernel (plane 0 of `table`: its support, slices and
     zeta) on grid j. Returns the per-plane run lists (on the one-plane table), the grids
-    complex128 [n_w][n][n] and the normaliser (eq. normalizer with the w = 0 zeta)."""
+    complex128 [n_w][n][n] ([n_w][P][n][n] with P polarisations) and the normaliser (eq.
+    normalizer with the w = 0 zeta; one per polarisation)."""
     vis = np.asarray(vis)
-    k = index(geom, table, uvw, inv_lambda, flag)[:, 2].reshape(vis.shape)
+    rec_shape = vis.shape[:3]
+    k = index(geom, table, uvw, inv_lambda, flag)[:, 2].reshape(rec_shape)
+    if vis.ndim == 4:
+        k = k[..., None]
     g0, t0 = dict(geom, n_w=1), plane0_table(geom, table)
     base = np.zeros(vis.shape, dtype=bool) if flag is None else (np.asarray(flag).reshape(vis.shape) != 0)
     runs, grids, norm = [], [], 0.0
@@ -212,11 +216,11 @@ def w_stacking(geom, table, uvw, inv_lambda, vis, weight=None, flag=None, compre
     return runs, np.stack(grids), norm
 
 
-def w_stacking_degrid(geom, table, runs, grids, uvw, weight, shape):
+def w_stacking_degrid(geom, table, runs, grids, uvw, weight, shape, flag=None):
     """Adjoint of `w_stacking`'s gridding: every record is read back from the grid of its
     plane with the w = 0 kernel (each record is in one plane's runs at most)."""
     g0, t0 = dict(geom, n_w=1), plane0_table(geom, table)
     out = np.zeros(shape, dtype=np.complex128)
     for j, r in enumerate(runs):
-        out += degrid(g0, t0, r, grids[j], uvw, weight, shape)
+        out += degrid(g0, t0, r, grids[j], uvw, weight, shape, flag)
     return out

@@ -120,11 +120,22 @@ def finalise_stokes(geom: dict, grid: np.ndarray, normalisers, circular: bool = 
     g = np.asarray(grid, dtype=np.complex128)
     if g.ndim == 2:
         g = g[None]
-    npol = g.shape[0]
+    return _stokes(geom, [transform(geom, g[p]) for p in range(g.shape[0])], normalisers, circular)
+
+
+def finalise_stokes_stacked(geom: dict, grids: np.ndarray, normalisers, circular: bool = False) -> dict:
+    """Stokes images of w-stacking with P polarisations: each product's plane grids
+    ([n_w][P][N][N]) stacked as in `stacked_transform`, then the Stokes steps."""
+    g = np.asarray(grids, dtype=np.complex128)
+    return _stokes(geom, [stacked_transform(geom, g[:, p]) for p in range(g.shape[1])], normalisers, circular)
+
+
+def _stokes(geom: dict, transforms, normalisers, circular: bool) -> dict:
+    npol = len(transforms)
     norms = np.atleast_1d(np.asarray(normalisers, dtype=np.float64))
     pol_img = []
     for p in range(npol):
-        pol_img.append(transform(geom, g[p]) / norms[p] if norms[p] != 0.0 else None)
+        pol_img.append(transforms[p] / norms[p] if norms[p] != 0.0 else None)
     c = axis_correction(geom)
     corr = np.outer(c, c)
     nz = corr != 0.0

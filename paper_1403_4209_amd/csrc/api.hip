@@ -14,7 +14,6 @@ int check_geom(const wg_geom *g) {
     if ((g->flags & ~(WG_COMPRESS | WG_GRID_PER_CHANNEL | WG_W_STACKING | WG_POL_CIRCULAR)) != 0) return WG_EINVAL;
     if ((g->flags & WG_GRID_PER_CHANNEL) && (g->flags & WG_W_STACKING)) return WG_EINVAL;
     if (g->n_pol != 0 && g->n_pol != 1 && g->n_pol != 2 && g->n_pol != 4) return WG_EINVAL;
-    if ((g->flags & WG_W_STACKING) && g->n_pol > 1) return WG_EUNSUPPORTED;
     if (g->n > 32768 || g->beta > 32 || g->n_w > WG_MAX_PLANES || g->s_hi > WG_MAX_SUPPORT)
         return WG_EUNSUPPORTED;
     const int64_t L = (int64_t)g->beta * g->m_img;

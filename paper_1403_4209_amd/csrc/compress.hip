@@ -521,7 +521,7 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
     }
     if (stack) {
         if (!runs->grid) return WG_EINVAL;
-        if ((int64_t)g->n_w * g->n * g->n >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
+        if ((int64_t)g->n_w * npol * g->n * g->n >= ((int64_t)1 << 31)) return WG_EUNSUPPORTED;
     }
     if (runs->capacity < n_rec) return WG_ECAPACITY;
     if (runs->plan_elems < wg_plan_elems(runs->capacity, n_seg)) return WG_ECAPACITY;

@@ -210,20 +210,33 @@ struct StokesCoef {
     int ns;
 };
 
-// acc[s][p][q] (+)= Re(c[s][pol] * T[p][q]) / normaliser[pol] for the Stokes images s, T the
-// transformed, transposed grid of polarisation `pol`; the first polarisation writes. A zero
-// normaliser adds 0.
-__global__ void k_stokes_acc(const float2 *__restrict__ T, float *__restrict__ acc, int64_t nn,
-                             const double *__restrict__ normaliser, int pol, StokesCoef c) {
+// acc[s][p][q] (+)= Re(c[s][pol] * T[p][q] * W) / normaliser[pol] for the Stokes images s, T
+// the transformed, transposed grid of polarisation `pol`, W = exp(+2 pi i w (n - 1)) with
+// w-stacking (0 where l^2 + m^2 > 1) and 1 otherwise; `first` writes. A zero normaliser
+// adds 0.
+__global__ void k_stokes_acc(const float2 *__restrict__ T, float *__restrict__ acc, int n,
+                             const double *__restrict__ normaliser, int pol, StokesCoef c, int stacked, double du,
+                             double w, int first) {
+    const int64_t nn = (int64_t)n * n;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nn) return;
     const double np = normaliser[pol];
     const double inv = np != 0.0 ? 1.0 / np : 0.0;
-    const float2 t = T[e];
+    double tx = T[e].x, ty = T[e].y;
+    if (stacked) {
+        const int p = (int)(e / n), q = (int)(e - (int64_t)p * n);
+        const double l = (double)(p - n / 2) / ((double)n * du), m = (double)(q - n / 2) / ((double)n * du);
+        const double rr = 1.0 - l * l - m * m;
+        double sn = 0.0, cs = 0.0;
+        if (rr >= 0.0) sincospi(2.0 * w * (sqrt(rr) - 1.0), &sn, &cs);
+        const double ux = tx * cs - ty * sn, uy = tx * sn + ty * cs;
+        tx = ux;
+        ty = uy;
+    }
     for (int s = 0; s < c.ns; ++s) {
-        const float v = (float)(((double)c.re[s][pol] * t.x - (double)c.im[s][pol] * t.y) * inv);
+        const float v = (float)(((double)c.re[s][pol] * tx - (double)c.im[s][pol] * ty) * inv);
         float *a = acc + (size_t)s * nn + e;
-        *a = pol == 0 ? v : *a + v;
+        *a = first ? v : *a + v;
     }
 }
 
@@ -372,13 +385,21 @@ int finalise(const wg_geom *g, const float *grid, const double *normaliser, floa
     const int64_t nn = (int64_t)n * n;
     float *acc = (float *)(base + lay.acc);
     if (npol > 1) {
+        // polarised grids ([P][n][n], or [n_w][P][n][n] stacked): every (plane, product)
+        // transform adds its share to the Stokes accumulators
         StokesCoef c = stokes_coef(npol, (g->flags & WG_POL_CIRCULAR) != 0);
-        for (int p = 0; p < npol; ++p) {
-            hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, (const float2 *)grid + p * nn, A, tw, 1);
-            hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
-            hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, B, A, tw, 1);
-            hipLaunchKernelGGL(k_stokes_acc, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, acc, nn,
-                               normaliser, p, c);
+        const int planes = stacked ? g->n_w : 1;
+        for (int k = 0; k < planes; ++k) {
+            const double q = g->n_w > 1 ? (double)k / (double)(g->n_w - 1) : 0.0;
+            const double w = stacked ? g->w_max * (q * q) : 0.0;
+            for (int p = 0; p < npol; ++p) {
+                const float2 *G = (const float2 *)grid + ((size_t)k * npol + p) * nn;
+                hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, G, A, tw, 1);
+                hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
+                hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, B, A, tw, 1);
+                hipLaunchKernelGGL(k_stokes_acc, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, acc, n,
+                                   normaliser, p, c, stacked ? 1 : 0, g->du, w, (k == 0 && p == 0) ? 1 : 0);
+            }
         }
         for (int k = 0; k < c.ns; ++k)
             hipLaunchKernelGGL(k_fin_out<float>, tiles, tb, 0, s, (const float *)(acc + (size_t)k * nn), corr,

@@ -176,8 +176,11 @@ def wg_finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, imag
 
 def wg_finalise_stacked(geom: WgGeom, grids: torch.Tensor, normaliser: torch.Tensor, image: torch.Tensor,
                         ws: torch.Tensor, stream=None):
-    if grids.numel() != 2 * geom.n_w * geom.n * geom.n or image.numel() != geom.n * geom.n:
-        raise ValueError("wg_finalise_stacked: grids must hold n_w x n x n complex values, image n x n")
+    npol = max(1, geom.n_pol)
+    if grids.numel() != 2 * geom.n_w * npol * geom.n * geom.n or image.numel() != npol * geom.n * geom.n \
+            or normaliser.numel() < npol:
+        raise ValueError("wg_finalise_stacked: grids must hold n_w x P x n x n complex values, image P x n x n, "
+                         "and P normalisers")
     _check(lib().wg_finalise_stacked(ctypes.byref(geom), _p(grids), _p(normaliser), _p(image), _p(ws),
                                      ws.numel() * ws.element_size(), _stream(stream)), "wg_finalise_stacked")
 
@@ -340,7 +343,7 @@ class Gridder:
         n = self.geom.n
         if self.n_pol == 1:
             return (self.n_grids, n, n) if (self.per_channel or self.w_stacking) else (n, n)
-        return (self.n_grids, self.n_pol, n, n) if self.per_channel else (self.n_pol, n, n)
+        return (self.n_grids, self.n_pol, n, n) if (self.per_channel or self.w_stacking) else (self.n_pol, n, n)
 
     def vis_shape(self):
         shape = (self.nb, self.nc, self.nt)
@@ -381,7 +384,8 @@ class Gridder:
         if self.w_stacking:
             n = self.geom.n
             if out is None:
-                out = torch.empty((n, n), dtype=torch.float32, device=grid.device)
+                out = torch.empty((n, n) if self.n_pol == 1 else (self.n_pol, n, n), dtype=torch.float32,
+                                  device=grid.device)
             ws = torch.empty(wg_finalise_ws_bytes(self.geom), dtype=torch.uint8, device=grid.device)
             wg_finalise_stacked(self.geom, torch.view_as_real(grid.contiguous()), self.runs.normaliser(), out, ws,
                                 stream)

@@ -163,8 +163,8 @@ def test_w_stacking_needs_grid_ids_and_excludes_per_channel(wg):
 
 
 def test_polarisation_count_and_normalisers(wg):
-    """n_pol is 1 (or 0), 2 or 4; w-stacking takes one polarisation; several polarisations
-    need the per-polarisation normalisers in wg_runs."""
+    """n_pol is 1 (or 0), 2 or 4 (also with w-stacking); several polarisations need the
+    per-polarisation normalisers in wg_runs."""
     L = wg.lib()
     by = ctypes.byref
     size = ctypes.c_int64(0), ctypes.c_size_t(0)
@@ -173,7 +173,12 @@ def test_polarisation_count_and_normalisers(wg):
         g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, n_pol=npol)
         assert L.wg_ktable_sizes(by(g), by(size[0]), by(size[1])) == want, npol
     g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, w_stacking=True, n_pol=2)
-    assert L.wg_ktable_sizes(by(g), by(size[0]), by(size[1])) == wg.WG_EUNSUPPORTED
+    assert L.wg_ktable_sizes(by(g), by(size[0]), by(size[1])) == wg.WG_OK
+    # 64 w-planes x 4 products x 4096^2 cells exceed the 31-bit cell index
+    g5 = wg.make_geom(4096, 8, 64, 7, 7, 256, 15.0, 100.0, w_stacking=True, n_pol=4)
+    kt5 = wg.WgKtable(0, 64, 8, 7, 1, 1, 1, 1, 1, 10)
+    big = wg.WgRuns(1 << 20, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 24, 1, 1, 1)
+    assert L.wg_compress(by(g5), by(kt5), 1, 1, 1, None, None, 1, 1, 1, by(big), 1, None) == wg.WG_EUNSUPPORTED
     g4 = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, n_pol=4, circular=True)
     kt = wg.WgKtable(0, 8, 8, 7, 1, 1, 1, 1, 1, 10)
     runs = wg.WgRuns(10, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10_000, 1, None, None)
