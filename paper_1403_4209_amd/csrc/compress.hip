@@ -116,6 +116,7 @@ __global__ void k_init(CArgs a, int64_t n_records) {
 // emit pass the chunk records are staged in LDS and given slots per support at the end; a
 // chunk that does not fit the stage takes its slot directly.
 constexpr int kStage = 1024;
+constexpr int kSegWaves = 16;  // segments (one per wave) per k_segments workgroup
 
 struct BlockAgg {
     int cnt[64];       // chunks per support
@@ -150,7 +151,7 @@ template <bool EMIT, int NP>
 __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, const int *s_sup, BlockAgg &agg);
 
 template <bool EMIT, int NP>
-__global__ __launch_bounds__(256) void k_segments(CArgs a) {
+__global__ __launch_bounds__(1024) void k_segments(CArgs a) {
     __shared__ double s_wb[WG_MAX_PLANES];
     __shared__ int s_sup[WG_MAX_PLANES];
     __shared__ BlockAgg agg;
@@ -566,13 +567,16 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
 
     hipStream_t s = (hipStream_t)stream;
     const int64_t n_tiles = n_scan_tiles(n_seg);
-    const int64_t seg_blocks = (n_seg + 3) / 4;
+    // 16 segments (waves) per workgroup: the per-support chunk counters and the statistics
+    // take one global atomic per workgroup each, and these few addresses serialise them
+    // (4 waves per workgroup: 0.31 ms for the compress step of a 15,136-segment batch; 16: 0.19)
+    const int64_t seg_blocks = (n_seg + kSegWaves - 1) / kSegWaves;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, a, n_rec);
     auto segments = [&](bool emit) {
         void (*k)(CArgs) = npol == 4   ? (emit ? k_segments<true, 4> : k_segments<false, 4>)
                            : npol == 2 ? (emit ? k_segments<true, 2> : k_segments<false, 2>)
                                        : (emit ? k_segments<true, 1> : k_segments<false, 1>);
-        hipLaunchKernelGGL(k, dim3((unsigned)seg_blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k, dim3((unsigned)seg_blocks), dim3(kSegWaves * kWave), 0, s, a);
     };
     segments(false);
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(1024), 0, s, a);
