@@ -86,13 +86,6 @@ __device__ inline typename KRaw<DT>::type raw_zero() {
         return 0u;
 }
 
-__device__ inline void kahan_add(float &s, float &c, float v) {
-    const float y = v - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
-
 // Supports present in the plan, largest first, with their first work unit.
 struct UnitTable {
     int n;

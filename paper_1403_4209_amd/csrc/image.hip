@@ -97,7 +97,7 @@ __device__ inline void idft_reg(float2 *v) {
 // and writes to `out` (global, shifted) when last, else back to LDS.
 template <int R>
 __device__ inline void ifft_pass(float2 *buf, const float2 *in, float2 *out, int n, int ns, bool first,
-                                 bool last, bool active, const float2 *tw, int stride) {
+                                 bool last, bool active, const float2 *tw) {
     const int T = n >> 4, t = threadIdx.x, nb = n / R, half = n >> 1;
     float2 v[16];
     if (active) {
@@ -107,7 +107,7 @@ __device__ inline void ifft_pass(float2 *buf, const float2 *in, float2 *out, int
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int e = j + r * nb;
-                float2 x = first ? in[(size_t)(e ^ half) * stride] : buf[e];
+                float2 x = first ? in[e ^ half] : buf[e];
                 if (r > 0 && ns > 1) x = fmulc(x, tw[jm * r * (n / (ns * R))]);
                 v[b * R + r] = x;
             }
@@ -137,28 +137,27 @@ __device__ inline void ifft_pass(float2 *buf, const float2 *in, float2 *out, int
 // first pass takes the LG mod 4 leftover bits, the others radix 16), so that every array
 // index and stride is a constant and the lane's 16 values stay in registers.
 template <int LG, int PASS, int NS_LOG>
-__device__ inline void ifft_passes(float2 *buf, const float2 *in, float2 *out, bool active, const float2 *tw,
-                                   int stride) {
+__device__ inline void ifft_passes(float2 *buf, const float2 *in, float2 *out, bool active, const float2 *tw) {
     constexpr int kBits = PASS == 0 && (LG & 3) ? (LG & 3) : 4;
     constexpr int kDone = NS_LOG + kBits;
-    ifft_pass<1 << kBits>(buf, in, out, 1 << LG, 1 << NS_LOG, PASS == 0, kDone == LG, active, tw, stride);
-    if constexpr (kDone < LG) ifft_passes<LG, PASS + 1, kDone>(buf, in, out, active, tw, stride);
+    ifft_pass<1 << kBits>(buf, in, out, 1 << LG, 1 << NS_LOG, PASS == 0, kDone == LG, active, tw);
+    if constexpr (kDone < LG) ifft_passes<LG, PASS + 1, kDone>(buf, in, out, active, tw);
 }
 
-// Rows of src (N x N complex values, `stride` apart: one polarisation of a polarised grid)
-// -> inverse transforms in dst; ifftshift on input and fftshift on output. blockDim >= N/16.
+// Rows of src (N x N complex, one grid plane) -> inverse transforms in dst; ifftshift on input
+// and fftshift on output. blockDim >= N/16.
 template <int LG>
 __global__ __launch_bounds__(512) void k_ifft_rows(const float2 *__restrict__ src, float2 *__restrict__ dst,
-                                                   const float2 *__restrict__ tw, int stride) {
+                                                   const float2 *__restrict__ tw) {
     extern __shared__ float2 buf[];
     constexpr int n = 1 << LG;
-    const float2 *in = src + (size_t)blockIdx.x * n * stride;
+    const float2 *in = src + (size_t)blockIdx.x * n;
     float2 *out = dst + (size_t)blockIdx.x * n;
     const bool active = (int)threadIdx.x < (n >> 4);
-    ifft_passes<LG, 0, 0>(buf, in, out, active, tw, stride);
+    ifft_passes<LG, 0, 0>(buf, in, out, active, tw);
 }
 
-using RowFft = void (*)(const float2 *, float2 *, const float2 *, int);
+using RowFft = void (*)(const float2 *, float2 *, const float2 *);
 
 RowFft row_fft(int lg) {
     switch (lg) {
@@ -394,9 +393,9 @@ int finalise(const wg_geom *g, const float *grid, const double *normaliser, floa
             const double w = stacked ? g->w_max * (q * q) : 0.0;
             for (int p = 0; p < npol; ++p) {
                 const float2 *G = (const float2 *)grid + ((size_t)k * npol + p) * nn;
-                hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, G, A, tw, 1);
+                hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, G, A, tw);
                 hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
-                hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, B, A, tw, 1);
+                hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, B, A, tw);
                 hipLaunchKernelGGL(k_stokes_acc, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, A, acc, n,
                                    normaliser, p, c, stacked ? 1 : 0, g->du, w, (k == 0 && p == 0) ? 1 : 0);
             }
@@ -409,9 +408,9 @@ int finalise(const wg_geom *g, const float *grid, const double *normaliser, floa
     const int planes = stacked ? g->n_w : 1;
     for (int k = 0; k < planes; ++k) {
         const float2 *G = (const float2 *)grid + (size_t)k * nn;
-        hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, G, A, tw, 1);
+        hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, G, A, tw);
         hipLaunchKernelGGL(k_transpose, tiles, tb, 0, s, A, B, n);
-        hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, B, A, tw, 1);
+        hipLaunchKernelGGL(rows, dim3(n), dim3(threads), lds, s, B, A, tw);
         if (stacked) {
             // the plane's w, computed as the table generator places its planes
             const double q = g->n_w > 1 ? (double)k / (double)(g->n_w - 1) : 0.0;
