@@ -449,27 +449,33 @@ __global__ __launch_bounds__(256) void k_grid(GArgs a) {
     });
 }
 
-// Sum over the 64 lanes with DPP moves (quad permutes, row mirrors, row broadcasts);
-// the total is left in lane 63 and returned to every lane through v_readlane.
-template <int CTRL, int ROW_MASK>
+// Wave totals of a complex value (re, im), one per lane: lanes 0-31 receive the total of
+// re, lanes 32-63 the total of im. v_permlane32_swap trades the upper half of re for the
+// lower half of im, so the two swapped registers add to re[l] + re[l + 32] in the lower half
+// and im[l - 32] + im[l] in the upper half; v_permlane16_swap of a register with itself then
+// pairs rows 0 and 1, and rows 2 and 3; DPP moves inside each row (quad permutes, row
+// mirrors) finish the sums. One tree serves both components.
+template <int CTRL>
 __device__ inline float dpp_f(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
-__device__ inline float wave_total(float v) {
-    v += dpp_f<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f<0x141, 0xF>(v);  // row_half_mirror
-    v += dpp_f<0x140, 0xF>(v);  // row_mirror
-    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+__device__ inline float wave_total_pair(float re, float im) {
+    const auto h = __builtin_amdgcn_permlane32_swap(__float_as_int(re), __float_as_int(im), false, false);
+    float v = __int_as_float(h[0]) + __int_as_float(h[1]);
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+    v = __int_as_float(r[0]) + __int_as_float(r[1]);
+    v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x141>(v);  // row_half_mirror
+    v += dpp_f<0x140>(v);  // row_mirror
+    return v;
 }
 
 // Adjoint, with the gridder's decomposition: a wave owns the same cell classes of a local
 // chunk, keeps the grid value of each owned cell in a register and reloads the values only
 // when the footprint moves (about one run in seven), and forms per run the partial dot
-// product of conj(K) with those values (a short FMA chain per lane, then a DPP tree over the
-// wave). The waves sharing a
+// product of conj(K) with those values (a short FMA chain per lane, then one lane-swap and
+// DPP tree over the wave for the real and imaginary parts together). The waves sharing a
 // chunk add their partial sums into work[run]; k_degrid_finish hands d to the run's records.
 template <int DT, int NP>
 struct DStage {
@@ -545,9 +551,11 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
             }
             load_samples(t, kbB, st.k);
         };
-        float sum_r[NP], sum_i[NP];  // lane t: this wave's sums for run base + t
+        // this wave's sums: lane l holds component l >> 5 (0 real, 1 imaginary) of run
+        // base + (l & 31) in lo and of run base + 32 + (l & 31) in hi
+        float lo[NP], hi[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) sum_r[p] = sum_i[p] = 0.f;
+        for (int p = 0; p < NP; ++p) lo[p] = hi[p] = 0.f;
         auto consume = [&](int t, const DStage<DT, NP> &st) {
             float pr[NP], pim[NP];
 #pragma unroll
@@ -568,12 +576,14 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
                     }
                 }
             }
-            // the wave's sums for run t wait in lane t; one atomic per batch adds them all
+            // the wave's sums for run t wait in lanes (t & 31) and 32 + (t & 31); two atomics
+            // per polarisation and batch add them all
+            const bool mine = (lane & 31) == (t & 31);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const float dr = wave_total(pr[p]), di = wave_total(pim[p]);
-                sum_r[p] = lane == t ? dr : sum_r[p];
-                sum_i[p] = lane == t ? di : sum_i[p];
+                const float d = wave_total_pair(pr[p], pim[p]);
+                lo[p] = (mine && t < 32) ? d : lo[p];
+                hi[p] = (mine && t >= 32) ? d : hi[p];
             }
         };
 
@@ -587,14 +597,15 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
                 consume(t + 1, sb);
             }
         }
-        if (lane < n && b.ok) {
-            float *w = (float *)(a.work + (int64_t)(base + lane) * NP);
+        const int r = lane & 31, comp = lane >> 5;
+        const int ok_lo = __shfl(b.ok, r), ok_hi = __shfl(b.ok, r + 32);
+        float *w = (float *)(a.work + (int64_t)(base + r) * NP) + comp;
+        if (r < n && ok_lo)
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                unsafeAtomicAdd(w + 2 * p, sum_r[p]);
-                unsafeAtomicAdd(w + 2 * p + 1, sum_i[p]);
-            }
-        }
+            for (int p = 0; p < NP; ++p) unsafeAtomicAdd(w + 2 * p, lo[p]);
+        if (r + 32 < n && ok_hi)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) unsafeAtomicAdd(w + 64 * NP + 2 * p, hi[p]);
     }
 }
 
