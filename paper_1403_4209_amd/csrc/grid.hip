@@ -375,11 +375,15 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
             for (int m = 0; m < NS; ++m) cur[m] = sa.yc[m];
             first = false;
         }
+        // The next run's fetch is issued on every path (past the batch's end it repeats the
+        // last run, whose footprint has not moved), so the waits before each accumulation
+        // leave that prefetch in flight; a fetch skipped on some path would make them wait
+        // for every outstanding load.
         for (int t = 0; t < n; t += 2) {
-            if (t + 1 < n) fetch(t + 1, sb);
+            fetch(min(t + 1, n - 1), sb);
             accumulate(t, sa);
             if (t + 1 < n) {
-                if (t + 2 < n) fetch(t + 2, sa);
+                fetch(min(t + 2, n - 1), sa);
                 accumulate(t + 1, sb);
             }
         }
@@ -430,7 +434,7 @@ __device__ void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int
 }
 
 template <int DT, int NP>
-__global__ __launch_bounds__(256) void k_grid(GArgs a) {
+__global__ __launch_bounds__(256, 4) void k_grid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
     if (threadIdx.x == 0) build_units(a.plan, grid_slots<DT, NP>(), &ut);
@@ -589,11 +593,12 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
 
         DStage<DT, NP> sa, sb;
         fetch(0, sa);
+        // the next run's fetch is issued on every path, as in the gridder
         for (int t = 0; t < n; t += 2) {
-            if (t + 1 < n) fetch(t + 1, sb);
+            fetch(min(t + 1, n - 1), sb);
             consume(t, sa);
             if (t + 1 < n) {
-                if (t + 2 < n) fetch(t + 2, sa);
+                fetch(min(t + 2, n - 1), sa);
                 consume(t + 1, sb);
             }
         }
