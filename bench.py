@@ -70,9 +70,14 @@ def gpu_step(wg, geom, kt, ws, gridder, vis, grid, vis_out, ev):
 
 
 def grid_source_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the gridder's sources (grid.hip, then
+    wg_common.hpp, whose constants set its slot counts)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1403_4209_amd", "csrc", "grid.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("grid.hip", "wg_common.hpp"):
+        with open(os.path.join(ROOT, "paper_1403_4209_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_counters(kernel):
@@ -81,7 +86,7 @@ def read_counters(kernel):
     try:
         with open(PROFILE_COUNTERS) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line)
-        if kv["grid_hip_sha256_16"].strip() != grid_source_hash():
+        if kv["grid_sources_sha256_16"].split()[0] != grid_source_hash():
             return None
         return float(kv[f"traffic_{kernel}"].strip())
     except Exception:

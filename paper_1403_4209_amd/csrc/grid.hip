@@ -481,6 +481,10 @@ __device__ inline float wave_total_pair(float re, float im) {
 // product of conj(K) with those values (a short FMA chain per lane, then one lane-swap and
 // DPP tree over the wave for the real and imaginary parts together). The waves sharing a
 // chunk add their partial sums into work[run]; k_degrid_finish hands d to the run's records.
+static_assert(kDegridSlots <= kSlots && kDegridSlotsNarrow <= kSlots && kDegridSlotsPol2 <= kSlots &&
+                  kDegridSlotsPol4 <= kSlots && kSlotsNarrow <= kSlots && kSlotsPol2 <= kSlots &&
+                  kSlotsPol4 <= kSlots,
+              "per-lane stage arrays hold kSlots classes");
 template <int DT, int NP>
 struct DStage {
     typename KRaw<DT>::type k[kSlots];

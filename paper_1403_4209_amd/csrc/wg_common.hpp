@@ -10,7 +10,7 @@ namespace wg {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxS = WG_MAX_SUPPORT;
-constexpr int kSlots = 8;          // most cell classes per lane in the gridder (register budget)
+constexpr int kSlots = 7;          // most cell classes per lane in the gridder (120 VGPRs; 8 measure alike with 5 spilled)
 constexpr int kSlotsNarrow = 6;    // the same with BF16/FP16 tables (measured faster there)
 constexpr int kDegridSlots = 7;    // the same for the degridder (FP32 tables: 3.06 ms, 3.14 with 5)
 constexpr int kDegridSlotsNarrow = 6;  // with BF16/FP16 tables (2.51 ms, 2.57 with 5)
