@@ -335,8 +335,11 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
             }
             load_samples(t, kbB, st.k);
         };
+        // A run that failed load_batch's checks (and lane n, past a batch of odd length n)
+        // carries gamma = 0: its step adds zero, so the loop needs no branch on it. Such a
+        // failed run counts as moved, with cells inside the first grid's corner, so the next
+        // good run commits what was held there (zero) and moves on.
         auto accumulate = [&](int t, const Stage<DT> &st) {
-            if (!rl(b.ok, t)) return;
             float gr[NP], gi[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
@@ -378,14 +381,13 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
         // The next run's fetch is issued on every path (past the batch's end it repeats the
         // last run, whose footprint has not moved), so the waits before each accumulation
         // leave that prefetch in flight; a fetch skipped on some path would make them wait
-        // for every outstanding load.
+        // for every outstanding load. With n odd, step t + 1 = n repeats run n - 1's
+        // footprint with lane n's zero gamma.
         for (int t = 0; t < n; t += 2) {
             fetch(min(t + 1, n - 1), sb);
             accumulate(t, sa);
-            if (t + 1 < n) {
-                fetch(min(t + 2, n - 1), sa);
-                accumulate(t + 1, sb);
-            }
+            fetch(min(t + 2, n - 1), sa);
+            accumulate(t + 1, sb);
         }
     }
 #pragma unroll
