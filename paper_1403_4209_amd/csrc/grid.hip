@@ -122,7 +122,8 @@ constexpr bool mirror_reads() { return DT == WG_KF32; }
 template <int NP>
 struct RunBatch {
     int cell0, ph, kb, ok;  // ph: footprint origin phases, (row0 mod S) << 16 | (ax mod S)
-    int mir;                // mirrored reads: 0xFFFF in each half whose offset is negative
+    int mul;                // mirrored reads: signed byte strides (row << 16 | column) of the
+                            // footprint position; kb then starts at the mirrored origin
     float gr[NP], gi[NP];   // the run's weighted visibility sum per polarisation
 };
 
@@ -134,7 +135,7 @@ template <int DT, int NP>
 __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool valid, const int64_t *koff) {
     RunBatch<NP> b;
     b.ok = 0;
-    b.cell0 = b.ph = b.kb = b.mir = 0;
+    b.cell0 = b.ph = b.kb = b.mul = 0;
 #pragma unroll
     for (int p = 0; p < NP; ++p) b.gr[p] = b.gi[p] = 0.f;
     if (valid) {
@@ -154,7 +155,14 @@ __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool val
             b.cell0 = row0 * a.n + ax + (int)(gid * a.cells * NP);
             b.ph = (row0 % S) << 16 | (ax % S);
             b.kb = (int)kbase;
-            if (mirror_reads<DT>()) b.mir = (ou < 0 ? 0xFFFF : 0) | (ov < 0 ? (int)0xFFFF0000u : 0);
+            if (mirror_reads<DT>()) {
+                // a negative offset reads position S - 1 - j along its axis: the stride turns
+                // negative and the origin moves to S - 1
+                constexpr int esz = (DT == WG_KF32) ? 8 : 4;
+                const int mu = ou < 0 ? -esz : esz, mv = ov < 0 ? -S * esz : S * esz;
+                b.mul = (int)((unsigned)(unsigned short)mu | (unsigned)(unsigned short)mv << 16);
+                b.kb += (ou < 0 ? S - 1 : 0) + (ov < 0 ? (S - 1) * S : 0);
+            }
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const float2 g = a.gamma[(int64_t)j * NP + p];
@@ -197,6 +205,21 @@ __device__ inline u16x2 footprint_pos(u16x2 cls, u16x2 ph, u16x2 ss) {
 
 // w.x * m.x + w.y * m.y + c (v_dot2_u32_u16)
 __device__ inline unsigned dot2(u16x2 w, u16x2 m, unsigned c) { return __builtin_amdgcn_udot2(w, m, c, false); }
+
+// A wave-uniform value held in a VGPR, so that an instruction taking it together with a
+// per-run scalar needs only one scalar operand.
+__device__ inline unsigned in_vgpr(unsigned x) {
+    unsigned r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+// The same with signed multipliers (v_dot2_i32_i16); positions are below 2^15.
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ inline i16x2 as_i16x2(unsigned v) { return __builtin_bit_cast(i16x2, v); }
+__device__ inline int sdot2(u16x2 w, i16x2 m, int c) {
+    return __builtin_amdgcn_sdot2(__builtin_bit_cast(i16x2, w), m, c, false);
+}
 
 // The lane's classes of a chunk: slot m holds class min(c0 + 64 m + lane, c1 - 1) as (q, p).
 template <int NS>
@@ -308,14 +331,13 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
 
         // the lane's samples of run t (mirrored positions where the run's offsets are negative)
         auto load_samples = [&](int t, unsigned kbB, typename KRaw<DT>::type *k) {
-            const unsigned mir = mirror_reads<DT>() ? (unsigned)rl(b.mir, t) : 0u;
-            const u16x2 sm1 = {(unsigned short)(S - 1), (unsigned short)(S - 1)};
+            if constexpr (mirror_reads<DT>()) {
+                const i16x2 mul = as_i16x2(in_vgpr((unsigned)rl(b.mul, t)));
 #pragma unroll
-            for (int m = 0; m < NS; ++m) {
-                unsigned pos = __builtin_bit_cast(unsigned, wpos[m]);
-                if (mirror_reads<DT>())
-                    pos = (mir & __builtin_bit_cast(unsigned, (u16x2)(sm1 - wpos[m]))) | (~mir & pos);
-                k[m] = buf_load<DT>(rs, (int)dot2(as_u16x2(pos), mul_k, kbB));
+                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, sdot2(wpos[m], mul, (int)kbB));
+            } else {
+#pragma unroll
+                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
             }
         };
         // cells (when the footprint moved) and samples of the lane's classes for run t
@@ -501,14 +523,6 @@ __device__ inline void load_cell(const float2 *grid, unsigned cell, int64_t cell
     for (int p = 0; p < NP; ++p) v[p] = grid[cell + p * cells];
 }
 
-// A wave-uniform value held in a VGPR, so that an instruction taking it together with a
-// per-run scalar needs only one scalar operand.
-__device__ inline unsigned in_vgpr(unsigned x) {
-    unsigned r;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
-    return r;
-}
-
 template <int DT, int NP, int NS>
 __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
                                 const int64_t *koff) {
@@ -535,14 +549,13 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
         const RunBatch<NP> b = load_batch<DT, NP>(a, S, base + lane, lane < n, koff);
 
         auto load_samples = [&](int t, unsigned kbB, typename KRaw<DT>::type *k) {
-            const unsigned mir = mirror_reads<DT>() ? (unsigned)rl(b.mir, t) : 0u;
-            const u16x2 sm1 = {(unsigned short)(S - 1), (unsigned short)(S - 1)};
+            if constexpr (mirror_reads<DT>()) {
+                const i16x2 mul = as_i16x2(in_vgpr((unsigned)rl(b.mul, t)));
 #pragma unroll
-            for (int m = 0; m < NS; ++m) {
-                unsigned pos = __builtin_bit_cast(unsigned, wpos[m]);
-                if (mirror_reads<DT>())
-                    pos = (mir & __builtin_bit_cast(unsigned, (u16x2)(sm1 - wpos[m]))) | (~mir & pos);
-                k[m] = buf_load<DT>(rs, (int)dot2(as_u16x2(pos), mul_k, kbB));
+                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, sdot2(wpos[m], mul, (int)kbB));
+            } else {
+#pragma unroll
+                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
             }
         };
         auto fetch = [&](int t, DStage<DT, NP> &st) {
