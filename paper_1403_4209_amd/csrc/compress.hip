@@ -48,6 +48,35 @@ struct Key {
 };
 
 // t with t - 1/2 < x <= t + 1/2 (eq. sat at the fine interval), exact for |x| < 2^30.
+// Cross-lane moves on the DPP path (no LDS): the previous lane's value (wave_shr:1; lane 0
+// gets `old`), and lane 63's value in every lane.
+__device__ inline int from_prev_lane(int v, int old) { return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xF, 0xF, false); }
+__device__ inline int lane63(int v) { return __builtin_amdgcn_readlane(v, 63); }
+__device__ inline float lane63f(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+
+// Segmented inclusive sum over the wave: lane l receives the sum of v over lanes
+// [max(seg, 0), l], where seg = seg_start(l) is the last segment head at or below l (-1:
+// none). Shifts by 1, 2, 4, 8 within each row of 16 lanes, then the row broadcasts carry
+// lane 15 into rows 1 and 3 and lane 31 into rows 2 and 3; each step is taken only where
+// its source lane lies in the receiving lane's segment.
+template <int CTRL, int ROWS, bool BC>
+__device__ inline float dpp_mv(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, BC));
+}
+__device__ inline float seg_scan(float v, int seg, int lane) {
+    const int r = lane & 15;
+    float u;
+    u = dpp_mv<0x111, 0xF, true>(v); v += (r >= 1 && lane - 1 >= seg) ? u : 0.f;  // row_shr:1
+    u = dpp_mv<0x112, 0xF, true>(v); v += (r >= 2 && lane - 2 >= seg) ? u : 0.f;  // row_shr:2
+    u = dpp_mv<0x114, 0xF, true>(v); v += (r >= 4 && lane - 4 >= seg) ? u : 0.f;  // row_shr:4
+    u = dpp_mv<0x118, 0xF, true>(v); v += (r >= 8 && lane - 8 >= seg) ? u : 0.f;  // row_shr:8
+    u = dpp_mv<0x142, 0xA, false>(v);                                              // row_bcast:15
+    v += ((lane & 16) && ((lane | 15) - 16) >= seg) ? u : 0.f;
+    u = dpp_mv<0x143, 0xC, false>(v);                                              // row_bcast:31
+    v += (lane >= 32 && 31 >= seg) ? u : 0.f;
+    return v;
+}
+
 __device__ inline int fine_index(double x) {
     double t = ceil(x - 0.5);
     if (!(t - 0.5 < x))
@@ -257,12 +286,10 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
                 if (a.flag && a.flag[r * NP + q] == 0) fl = false;
             key = index_record(cu, cv, cw, il, fl, a, s_wb, s_sup);
         }
-        int pX = __shfl_up(key.X, 1, kWave), pY = __shfl_up(key.Y, 1, kWave);
-        int pK = __shfl_up(key.k, 1, kWave), pOu = __shfl_up(key.ou, 1, kWave);
-        int pOv = __shfl_up(key.ov, 1, kWave), pOk = __shfl_up(key.ok, 1, kWave);
-        if (lane == 0) {
-            pX = cX; pY = cY; pK = cK; pOu = cOu; pOv = cOv; pOk = cOk;
-        }
+        // the previous record's key; lane 0 takes the carried one
+        const int pX = from_prev_lane(key.X, cX), pY = from_prev_lane(key.Y, cY);
+        const int pK = from_prev_lane(key.k, cK), pOu = from_prev_lane(key.ou, cOu);
+        const int pOv = from_prev_lane(key.ov, cOv), pOk = from_prev_lane(key.ok, cOk);
         const bool same = key.X == pX && key.Y == pY && key.k == pK && key.ou == pOu && key.ov == pOv;
         const bool c = a.compress && t > 0 && key.ok && pOk && same;
         const bool g = key.ok && !c;
@@ -320,16 +347,10 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
             }
             const uint64_t gle = gm & (lt | (1ull << lane));
             const int seg_start = gle ? 63 - __clzll(gle) : -1;
-            for (int d = 1; d < kWave; d <<= 1) {
-                const bool take = lane >= d && lane - d >= seg_start;
 #pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    const float ur = __shfl_up(sr[q], d, kWave), ui = __shfl_up(si[q], d, kWave);
-                    if (take) {
-                        sr[q] += ur;
-                        si[q] += ui;
-                    }
-                }
+            for (int q = 0; q < NP; ++q) {
+                sr[q] = seg_scan(sr[q], seg_start, lane);
+                si[q] = seg_scan(si[q], seg_start, lane);
             }
             if (seg_start < 0 && open) {
 #pragma unroll
@@ -364,13 +385,13 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
 #pragma unroll
                 for (int q = 0; q < NP; ++q) a.gamma[(int64_t)j * NP + q] = make_float2(sr[q], si[q]);
             }
-            const int carry = __shfl((int)(key.ok && !is_end), kWave - 1, kWave);
-            const int ss63 = __shfl(seg_start, kWave - 1, kWave);
+            const int carry = lane63((int)(key.ok && !is_end));
+            const int ss63 = lane63(seg_start);
             float cr[NP], ci[NP];
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
-                cr[q] = __shfl(sr[q], kWave - 1, kWave);
-                ci[q] = __shfl(si[q], kWave - 1, kWave);
+                cr[q] = lane63f(sr[q]);
+                ci[q] = lane63f(si[q]);
             }
             if (carry) {
                 if (ss63 >= 0) {
@@ -389,12 +410,12 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
                 open = false;
             }
         }
-        cX = __shfl(key.X, kWave - 1, kWave);
-        cY = __shfl(key.Y, kWave - 1, kWave);
-        cK = __shfl(key.k, kWave - 1, kWave);
-        cOu = __shfl(key.ou, kWave - 1, kWave);
-        cOv = __shfl(key.ov, kWave - 1, kWave);
-        cOk = __shfl(key.ok, kWave - 1, kWave);
+        cX = lane63(key.X);
+        cY = lane63(key.Y);
+        cK = lane63(key.k);
+        cOu = lane63(key.ou);
+        cOv = lane63(key.ov);
+        cOk = lane63(key.ok);
         if (gm) lastS = __shfl(S, 63 - __clzll(gm), kWave);
         runs_before += __popcll(gm);
     }
