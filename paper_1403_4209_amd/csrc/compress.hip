@@ -41,13 +41,14 @@ struct CArgs {
     int16_t *grid_id;  // the grid of each run (its channel, or its w-plane when stacking), else NULL
     double *norm;      // normalisers [grid][npol] (per-channel grids or npol > 1), else NULL
     int norm_per_ch;   // norm has one row per channel (per-channel grids), else one row
+    int vec;           // npol > 1 with vis, wt and flag aligned to a record's values: each
+                       // record's products are read with vector loads
 };
 
 struct Key {
     int X, Y, k, ou, ov, psi, ok;
 };
 
-// t with t - 1/2 < x <= t + 1/2 (eq. sat at the fine interval), exact for |x| < 2^30.
 // Cross-lane moves on the DPP path (no LDS): the previous lane's value (wave_shr:1; lane 0
 // gets `old`), and lane 63's value in every lane.
 __device__ inline int from_prev_lane(int v, int old) { return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xF, 0xF, false); }
@@ -77,6 +78,48 @@ __device__ inline float seg_scan(float v, int seg, int lane) {
     return v;
 }
 
+// A record's NP flag bytes, byte q in bits 8q..8q+7 (0 without flags).
+template <int NP>
+__device__ inline unsigned load_flags(const CArgs &a, int64_t r) {
+    if (!a.flag) return 0u;
+    if constexpr (NP == 4)
+        if (a.vec) return *(const unsigned *)(a.flag + 4 * r);
+    if constexpr (NP == 2)
+        if (a.vec) return *(const unsigned short *)(a.flag + 2 * r);
+    unsigned f = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) f |= (unsigned)a.flag[r * NP + q] << (8 * q);
+    return f;
+}
+
+// A record's NP visibilities and weights (weights 1 without them).
+template <int NP>
+__device__ inline void load_values(const CArgs &a, int64_t r, float2 *v, float *w) {
+    if (NP > 1 && a.vec) {
+        const float4 *vp = (const float4 *)(a.vis + r * NP);
+#pragma unroll
+        for (int h = 0; h < NP / 2; ++h) {
+            const float4 x = vp[h];
+            v[2 * h] = make_float2(x.x, x.y);
+            v[2 * h + 1] = make_float2(x.z, x.w);
+        }
+        if constexpr (NP == 4) {
+            const float4 x = a.wt ? *(const float4 *)(a.wt + 4 * r) : make_float4(1.f, 1.f, 1.f, 1.f);
+            w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+        } else {
+            const float2 x = a.wt ? *(const float2 *)(a.wt + 2 * r) : make_float2(1.f, 1.f);
+            w[0] = x.x; w[1] = x.y;
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        v[q] = a.vis[r * NP + q];
+        w[q] = a.wt ? a.wt[r * NP + q] : 1.0f;
+    }
+}
+
+// t with t - 1/2 < x <= t + 1/2 (eq. sat at the fine interval), exact for |x| < 2^30.
 __device__ inline int fine_index(double x) {
     double t = ceil(x - 0.5);
     if (!(t - 0.5 < x))
@@ -279,11 +322,13 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
         key.ok = 0;
         key.X = key.Y = key.k = key.ou = key.ov = 0;
         key.psi = 1;
+        unsigned fw = 0;  // the record's flag bytes
         if (valid) {
+            fw = load_flags<NP>(a, r);
             bool fl = a.flag != nullptr;  // dropped only when every polarisation is flagged
 #pragma unroll
             for (int q = 0; q < NP; ++q)
-                if (a.flag && a.flag[r * NP + q] == 0) fl = false;
+                if (((fw >> (8 * q)) & 0xFFu) == 0) fl = false;
             key = index_record(cu, cv, cw, il, fl, a, s_wb, s_sup);
         }
         // the previous record's key; lane 0 takes the carried one
@@ -334,12 +379,21 @@ __device__ void walk_segment(const CArgs &a, int64_t seg, const double *s_wb, co
             if (key.ok) {
                 const int sigma = (key.ov + (a.beta >> 1) - 1) * a.beta + (key.ou + (a.beta >> 1) - 1);
                 const double z = a.zeta[(int64_t)(a.stack ? 0 : key.k) * nbeta2 + sigma];
+                float2 vv[NP];
+                float ww[NP];
+                load_values<NP>(a, r, vv, ww);
 #pragma unroll
                 for (int q = 0; q < NP; ++q) {
-                    const int64_t e = r * NP + pol_source<NP>(q, key.psi);
-                    float w = a.wt ? a.wt[e] : 1.0f;
-                    if (NP > 1 && a.flag && a.flag[e]) w = 0.0f;
-                    const float2 v = a.vis[e];
+                    const int src = pol_source<NP>(q, key.psi);
+                    // q is a compile-time index after unrolling: src is q or, four products
+                    // with a flipped record, 3 - q
+                    float w = ww[q];
+                    float2 v = vv[q];
+                    if constexpr (NP == 4) {
+                        w = src != q ? ww[3 - q] : w;
+                        v = src != q ? vv[3 - q] : v;
+                    }
+                    if (NP > 1 && ((fw >> (8 * src)) & 0xFFu)) w = 0.0f;
                     sr[q] = w * v.x;
                     si[q] = w * ((float)key.psi * v.y);
                     my_norm[q] += (double)w * z;
@@ -566,6 +620,8 @@ extern "C" int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *
     a.vis = (const float2 *)vis;
     a.wt = weight;
     a.flag = flag;
+    a.vec = npol > 1 && (uintptr_t)vis % 16 == 0 && (uintptr_t)weight % (4 * npol) == 0 &&
+            (uintptr_t)flag % npol == 0;
     a.wbound = kt->wbound;
     a.support = kt->support;
     a.zeta = kt->zeta;
