@@ -851,6 +851,30 @@ def test_runs_with_grid_ids_beyond_the_grids_are_skipped():
         assert not torch.any(G != 0) and not torch.any(out != 0)
 
 
+def test_failed_runs_interleaved_with_good_ones():
+    """Every third run's grid id moved past the last channel: those runs are skipped (they add
+    zero) and the others, in the same chunks and batches, still grid as the oracle's runs
+    with the skipped runs' gammas set to zero (the channel grids summed)."""
+    geom, data = cfg1()
+    g = wg.geom_from_dict(geom, per_channel=True)
+    table = wg.KernelTable(g, "f32", device=DEV)
+    uvw, il, vis, wt, fl = to_dev(data)
+    gr = wg.Gridder(g, table, uvw, il, wt, fl)
+    gr.compress(vis)
+    n_runs = gr.runs.stats().n_runs
+    gr.runs.grid[0:n_runs:3] = gr.nc
+    G = gr.grid().sum(0).cpu().numpy().astype(np.complex128)
+    t64 = otable(geom, "f64")
+    orc = oracle.compress(geom, t64, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"])
+    assert orc["n_runs"] == n_runs
+    orc["gamma"] = np.array(orc["gamma"], copy=True)
+    orc["gamma"][0::3] = 0
+    Go = oracle.grid(geom, t64, orc)
+    err = rel_l2(G, Go)
+    say("failed runs interleaved: grid rel L2", err)
+    assert err < 1e-5
+
+
 @pytest.mark.parametrize("case", ["cfg1", "cfg4"])
 def test_fp32_table_is_even_in_each_offset(case):
     """The FP32 gridder and degridder read only slices of non-negative oversample offsets,
