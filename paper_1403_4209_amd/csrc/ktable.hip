@@ -193,6 +193,13 @@ inline size_t dft_lds_bytes(int M, int L, int lgM) {
     return sizeof(double2) * (size_t)(L + (n_passes(lgM) >= 3 ? L : M));
 }
 
+// LDS of the column kernel: with two passes it reads its column from global memory and
+// needs buf0 alone (beta*M values: 32 KB at M = 256, five blocks per CU); with three or
+// more, as the row kernel.
+inline size_t col_lds_bytes(int M, int L, int lgM) {
+    return n_passes(lgM) >= 3 ? dft_lds_bytes(M, L, lgM) : sizeof(double2) * (size_t)L;
+}
+
 // Row pass: image row q of plane k -> L-point transform along u; stores the centred
 // spectrum column-major so the column pass reads contiguous values.
 //
@@ -276,13 +283,15 @@ __global__ void k_c00_and_reset(BuildArgs a, double *wbound) {
 template <int LGM>
 __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     extern __shared__ double2 lds[];
-    __shared__ int red[128];
+    constexpr bool kStage = (LGM + 3) / 4 >= 3;  // three or more passes: the column goes to LDS
     double2 *buf0 = lds, *xin = lds + a.L;
     const int fu_b = (int)blockIdx.x == a.L / 2 ? -a.L / 2 : (int)blockIdx.x;
     const int cu = fu_b + a.L / 2, k = blockIdx.y;
     const double2 *in = a.A + ((size_t)k * a.L + cu) * a.M;
-    for (int q = threadIdx.x; q < a.M; q += blockDim.x) xin[q] = in[q];
-    __syncthreads();
+    if constexpr (kStage) {
+        for (int q = threadIdx.x; q < a.M; q += blockDim.x) xin[q] = in[q];
+        __syncthreads();
+    }
     const double c00 = *a.c00;
     const double t2 = (kThreshold * c00) * (kThreshold * c00);
     const double t2_hi = t2 * (1.0 + 1e-9), t2_lo = t2 * (1.0 - 1e-9);
@@ -292,7 +301,7 @@ __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     double2 *win = a.win + (size_t)k * W * W + (fu + Wf);
     const int mirror = -2 * fu;  // column -fu relative to column fu
     int dmax = 0;
-    oversampled_dft<LGM>(a, xin, buf0, xin, [&](int b, int k1, double2 s) {
+    oversampled_dft<LGM>(a, kStage ? xin : in, buf0, xin, [&](int b, int k1, double2 s) {
         const int fv = ((k1 * beta + b + L / 2) & (L - 1)) - L / 2;
         const double r2 = s.x * s.x + s.y * s.y;
         bool above = r2 > t2_hi;
@@ -304,6 +313,8 @@ __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
             if (fu > 0) win[(size_t)(fv + Wf) * W + mirror] = v;
         }
     });
+    // the transform ended with a barrier: its LDS now holds the block's maxima
+    int *red = (int *)lds;
     red[threadIdx.x] = dmax;
     __syncthreads();
     for (int d = blockDim.x / 2; d > 0; d >>= 1) {
@@ -498,7 +509,8 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
     hipLaunchKernelGGL(k_taper, dim3((a.M + 255) / 256), dim3(256), 0, s, a, tc);
     hipLaunchKernelGGL(line_kernel<true>(a.lgM), dim3(a.M / 2, a.n_w), dim3(128), lds, s, a);
     hipLaunchKernelGGL(k_c00_and_reset, dim3(1), dim3(256), 0, s, a, kt->wbound);
-    hipLaunchKernelGGL(line_kernel<false>(a.lgM), dim3(a.L / 2 + 1, a.n_w), dim3(128), lds, s, a);
+    hipLaunchKernelGGL(line_kernel<false>(a.lgM), dim3(a.L / 2 + 1, a.n_w), dim3(128), col_lds_bytes(a.M, a.L, a.lgM),
+                       s, a);
     hipLaunchKernelGGL(k_supports, dim3(1), dim3(64), 0, s, a, g->s_lo, g->s_hi, kt->support, kt->offset);
     if (hipGetLastError() != hipSuccess) return WG_EHIP;
 
