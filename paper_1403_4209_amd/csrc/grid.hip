@@ -778,7 +778,11 @@ int check_runs(const wg_geom *g, const wg_runs *runs) {
     return WG_OK;
 }
 
-constexpr int kPersistentBlocks = 4096;
+// Workgroups of four waves per launch. The gridder's static walk gains from more waves than
+// fit at once (later ones start as early ones finish); the degridder's work counter is best
+// served by one resident round (four waves per SIMD).
+constexpr int kGridBlocks = 8192;
+constexpr int kDegridBlocks = 1024;
 
 // The gridder (GRID) or degridder kernel for a table type and polarisation count.
 template <bool GRID>
@@ -808,7 +812,7 @@ extern "C" int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *run
     GArgs a = make_args(g, kt, runs);
     a.grid = grid;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(pick_kernel<true>(kt->dtype, a.npol), dim3(kPersistentBlocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pick_kernel<true>(kt->dtype, a.npol), dim3(kGridBlocks), dim3(256), 0, s, a);
     return launch_status();
 }
 
@@ -839,7 +843,7 @@ extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *r
     // records in no run get 0: clear the output and the per-run accumulators first
     hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, s, (float2 *)vis_out, n_rec * a.npol);
     hipLaunchKernelGGL(k_zero_work, dim3(2048), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(pick_kernel<false>(kt->dtype, a.npol), dim3(kPersistentBlocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pick_kernel<false>(kt->dtype, a.npol), dim3(kDegridBlocks), dim3(256), 0, s, a);
     hipLaunchKernelGGL(a.npol == 4 ? k_degrid_finish<4> : a.npol == 2 ? k_degrid_finish<2> : k_degrid_finish<1>,
                        dim3(2048), dim3(256), 0, s, a);
     return launch_status();
