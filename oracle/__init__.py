@@ -16,8 +16,26 @@ shares no code with it.
 * `image.finalise_stacked`  -- the w-plane grids transformed, corrected for their w-term in
                                the image plane and added, then finalised.
 
-Parity unpinned: none of the functions here; every one is pinned by the tests listed in
-the design notes (closed forms, invariants, brute force on tiny inputs).
+Pins (tests/test_oracle_pins.py), one or more per function:
+  ktable.build / taper     -- Nystrom eigen-equation of the prolate spheroidal, the w = 0
+                              kernel as the spheroidal itself, a direct DFT of the padded
+                              samples, symmetries, the support law
+  ktable.round_to / requantize -- nearest-even rounding cases; zeta as an exactly rounded
+                              sum of the stored values, equal to a table built in that type
+  index                    -- hand-derived tie rows (tests/golden), nearest plane in sqrt(w)
+  compress                 -- brute-force run scan in exact rational arithmetic, adversarial
+                              runs, the unit-visibility normaliser, compressed = uncompressed
+  grid                     -- delta-kernel histogram, sum invariant, Hermitian flip, one-cell
+                              translation, gridding + inverse DFT = image-plane sum
+  degrid                   -- the adjoint identity
+  per_channel              -- channel grids = shared grid with the other channels' weights
+                              zeroed; they and the normalisers add up to the shared ones; the
+                              runs are the shared runs of that channel
+  w_stacking (+ _degrid)   -- image-plane sum, w = 0 reduces to w-projection, unit source,
+                              adjoint
+  image.finalise (+ stacked, Stokes) -- unit and off-centre sources, edge zeros, polarised
+                              sources at and off the centre
+Parity unpinned: none.
 """
 from __future__ import annotations
 

@@ -830,3 +830,96 @@ def test_polarised_w_stacking_source_at_centre_and_adjoint(oracle_mod, circular)
     rhs = np.vdot(vis2.astype(np.complex128), back).real
     assert abs(lhs - rhs) < 1e-13 * np.linalg.norm(G2) * np.linalg.norm(g)
     assert not np.any(back[flag != 0])
+
+
+# ------------------------------------------------------- per-channel grids (NEXT-3)
+def _channel_records(seed=41):
+    geom = small_geom(n=96, beta=8, m_img=64, n_w=3, w_max=300.0, s_lo=7, s_hi=11, du=6.0)
+    uvw, il, vis, wt = random_records(5, 4, 40, geom, seed=seed, spread=0.3)
+    rng = np.random.default_rng(seed + 1)
+    fl = (rng.uniform(size=vis.shape) < 0.15).astype(np.uint8)
+    # consecutive equal records so that compression merges within each channel
+    uvw[:, 1::2] = uvw[:, 0:-1:2]
+    return geom, uvw, il, vis, wt, fl
+
+
+def test_per_channel_grids_are_the_shared_grid_split_by_channel(oracle_mod):
+    """WImager component, one instance per channel; eqs. gridding and normalizer. Gridding
+    is linear in the records, so the grid of channel c must equal the shared-grid result of
+    every channel's records with the weights of all other channels set to zero, and the
+    per-channel grids and normalisers must add up to the shared ones. Weights differ per
+    record and 15 % are flagged, so taking the weights or flags of another channel (a slicing
+    mistake) breaks the first identity by O(1)."""
+    from oracle import ktable as kt
+    geom, uvw, il, vis, wt, fl = _channel_records()
+    table = kt.build(geom, "f64")
+    runs_c, grids, norms = oracle_mod.per_channel(geom, table, uvw, il, vis, wt, fl)
+    shared = oracle_mod.compress(geom, table, uvw, il, vis, wt, fl)
+    G = oracle_mod.grid(geom, table, shared)
+    assert shared["stats"][3] > 0 and all(r["n_runs"] > 0 for r in runs_c)
+    scale = np.linalg.norm(G)
+    assert np.linalg.norm(grids.sum(axis=0) - G) <= 1e-12 * scale
+    assert abs(norms.sum() - shared["normaliser"]) <= 1e-12 * abs(shared["normaliser"])
+    assert sum(int(r["stats"][1]) for r in runs_c) == int(shared["stats"][1])
+    for c in range(len(il)):
+        wc = wt.copy()
+        wc[:, np.arange(len(il)) != c, :] = 0.0
+        masked = oracle_mod.compress(geom, table, uvw, il, vis, wc, fl)
+        Gc = oracle_mod.grid(geom, table, masked)
+        assert np.linalg.norm(grids[c] - Gc) <= 1e-12 * np.linalg.norm(Gc)
+        assert abs(norms[c] - masked["normaliser"]) <= 1e-12 * abs(masked["normaliser"])
+
+
+def test_per_channel_runs_are_the_shared_runs_of_that_channel(oracle_mod):
+    """Runs never cross a (baseline, channel) segment, so the runs of channel c alone are
+    exactly the shared runs whose records lie in channel c, with record index (b*C + c)*T + t
+    mapped to b*T + t; and with one channel the per-channel path is the shared path, bit for
+    bit."""
+    from oracle import ktable as kt
+    geom, uvw, il, vis, wt, fl = _channel_records(seed=43)
+    table = kt.build(geom, "f64")
+    nb, nc, nt = vis.shape
+    runs_c, grids, norms = oracle_mod.per_channel(geom, table, uvw, il, vis, wt, fl)
+    shared = oracle_mod.compress(geom, table, uvw, il, vis, wt, fl)
+    seg = shared["start"] // nt
+    ch = seg % nc
+    for c in range(nc):
+        sel = ch == c
+        b, t = seg[sel] // nc, shared["start"][sel] % nt
+        r = runs_c[c]
+        assert r["n_runs"] == int(sel.sum())
+        assert np.array_equal(r["start"], b * nt + t)
+        for k in ("len", "x", "y", "plane", "ou", "ov"):
+            assert np.array_equal(r[k], shared[k][sel]), k
+        assert np.array_equal(r["gamma"], shared["gamma"][sel])
+    one = slice(2, 3)
+    r1, g1, n1 = oracle_mod.per_channel(geom, table, uvw, il[one], vis[:, one], wt[:, one], fl[:, one])
+    s1 = oracle_mod.compress(geom, table, uvw, il[one], vis[:, one], wt[:, one], fl[:, one])
+    assert np.array_equal(g1[0], oracle_mod.grid(geom, table, s1))
+    assert n1[0] == s1["normaliser"]
+
+
+# ------------------------------------------------------ quantised tables (eq. sum)
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "f32"])
+def test_requantized_zeta_is_the_sum_of_the_stored_values(dtype):
+    """eq. sum: zeta of a matrix is the sum of the real parts of the values the gridder uses,
+    i.e. of the rounded samples. requantize must give the samples of a table built directly
+    in that type, bit for bit, and zetas equal to that table's and to an exactly rounded
+    sum (math.fsum) over each S x S matrix taken by explicit plane/matrix/element indices."""
+    from oracle import ktable as kt
+    geom = small_geom(n=64, beta=4, m_img=64, n_w=3, w_max=200.0, s_lo=5, s_hi=9, du=8.0)
+    t64 = kt.build(geom, "f64")
+    tq = kt.requantize(t64, dtype)
+    td = kt.build(geom, dtype)
+    assert np.array_equal(tq["data"], td["data"])
+    assert np.array_equal(tq["zeta"], td["zeta"])
+    beta = geom["beta"]
+    assert len(set(int(s) for s in t64["support"])) > 1
+    for k, S in enumerate(int(s) for s in t64["support"]):
+        for s in range(beta * beta):
+            base = int(t64["offset"][k]) + s * S * S
+            vals = [kt.round_to(np.array([t64["data"][base + e].real]), dtype)[0] for e in range(S * S)]
+            ref = math.fsum(vals)
+            assert abs(tq["zeta"][k, s] - ref) <= 1e-13 * max(1.0, sum(abs(v) for v in vals)), (k, s)
+    if dtype != "f32":
+        assert not np.array_equal(tq["zeta"], t64["zeta"])
