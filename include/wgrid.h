@@ -10,6 +10,7 @@
  *     compressindex, eqs. compress1 and conjugatetake, statistics logic, eq. normalizer)
  *     -> wg_compress
  *   - WImager gridding phase (eq. gridding) -> wg_grid
+ *   - the whole WImager component, records to grid and normaliser -> wg_grid_records
  *   - the exact adjoint of eq. gridding (not in the thesis) -> wg_degrid
  *
  * Conventions shared by every call
@@ -264,6 +265,44 @@ int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const 
  */
 int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg_stats *stats,
             float *grid, wg_stream_t stream);
+
+/*
+ * Workspace of wg_grid_records for nb x nc x nt records (WImager inputs I-1..I-5): the run
+ * arrays of wg_runs with capacity nb*nc*nt (so the run list cannot overflow), the per-run
+ * grid ids (per-channel grids or w-stacking), the normalisers ([nc][P] with per-channel
+ * grids, else [P]) and the plan, each on a 256-byte boundary.
+ *   ws == NULL: [host] *ws_bytes receives the size in bytes.
+ *   ws != NULL: a device workspace of *ws_bytes bytes, 256-byte aligned; [host] *runs
+ *           (when non-NULL) receives the wg_runs view of it that wg_grid_records uses, so the
+ *           runs it leaves there can be passed to wg_degrid, wg_grid or wg_finalise
+ *           (runs->norm). No device work is done.
+ * Errors: WG_EINVAL (NULL ws_bytes, invalid geometry, sizes < 1, ws misaligned),
+ * WG_ECAPACITY (*ws_bytes too small), WG_EUNSUPPORTED (nb*nc*nt >= 2^31).
+ */
+int wg_grid_records_ws(const wg_geom *g, int64_t nb, int32_t nc, int32_t nt, void *ws, size_t *ws_bytes,
+                       wg_runs *runs);
+
+/*
+ * Records to grid in one call: the WImager component with the generator's table (inputs
+ * I-1..I-5 and C-1..C-3; outputs O-1, the grid, and O-2, the normaliser of eq. normalizer).
+ * The preparation phase of wg_compress (keys, compression of eqs. compression and ci with
+ * g->flags & WG_COMPRESS, weighting of eqs. compress1 and conjugatetake; without
+ * WG_COMPRESS every griddable record is its own run) followed by the gridding phase of
+ * wg_grid (eq. gridding), with the same arguments, layouts and accumulation:
+ *   grid   complex64 [P][n][n] (or [nc][P][n][n] / [n_w][P][n][n]), ACCUMULATES
+ *   stats  device wg_stats of the batch (normaliser N of the first polarisation)
+ *   ws     device workspace of at least wg_grid_records_ws's size, 256-byte aligned; the
+ *          run list, plan and per-grid normalisers are left there (OVERWRITTEN each call)
+ *   runs_out [host] optional: receives the wg_runs view of ws (as wg_grid_records_ws gives)
+ * Enqueues on `stream` and returns without waiting. Two calls sharing a workspace must not
+ * overlap in time.
+ * Errors: those of wg_compress and wg_grid, all checked before any work is enqueued;
+ * WG_ECAPACITY (ws_bytes too small), WG_EINVAL (ws NULL or misaligned).
+ */
+int wg_grid_records(const wg_geom *g, const wg_ktable *kt, const double *uvw, const double *inv_lambda,
+                    const float *vis, const float *weight, const uint8_t *flag, int64_t nb, int32_t nc,
+                    int32_t nt, float *grid, wg_stats *stats, void *ws, size_t ws_bytes, wg_runs *runs_out,
+                    wg_stream_t stream);
 
 /*
  * Adjoint of wg_compress + wg_grid with respect to the visibilities: per run

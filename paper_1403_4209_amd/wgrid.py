@@ -82,6 +82,10 @@ def lib():
         L.wg_compress.argtypes = [P, P, P, P, P, P, P, I64, I32, I32, P, P, P]
         L.wg_grid.restype = ctypes.c_int
         L.wg_grid.argtypes = [P, P, P, P, P, P]
+        L.wg_grid_records_ws.restype = ctypes.c_int
+        L.wg_grid_records_ws.argtypes = [P, I64, I32, I32, P, P, P]
+        L.wg_grid_records.restype = ctypes.c_int
+        L.wg_grid_records.argtypes = [P, P, P, P, P, P, P, I64, I32, I32, P, P, P, ctypes.c_size_t, P, P]
         L.wg_degrid.restype = ctypes.c_int
         L.wg_degrid.argtypes = [P, P, P, P, P, P, P, P, I64, I32, I32, P, P]
         L.wg_finalise_ws_bytes.restype = ctypes.c_int
@@ -154,6 +158,30 @@ def wg_compress(geom, kt, uvw, inv_lambda, vis, weight, flag, nb, nc, nt, runs: 
 def wg_grid(geom, kt, runs: WgRuns, stats: torch.Tensor, grid: torch.Tensor, stream=None):
     _check(lib().wg_grid(ctypes.byref(geom), ctypes.byref(kt), ctypes.byref(runs), _p(stats), _p(grid),
                          _stream(stream)), "wg_grid")
+
+
+def wg_grid_records_ws(geom: WgGeom, nb: int, nc: int, nt: int, ws: torch.Tensor | None = None):
+    """Without `ws`: the workspace size in bytes. With `ws` (a device byte tensor): the
+    WgRuns view of it that wg_grid_records fills."""
+    size = ctypes.c_size_t(0 if ws is None else ws.numel() * ws.element_size())
+    if ws is None:
+        _check(lib().wg_grid_records_ws(ctypes.byref(geom), int(nb), int(nc), int(nt), None, ctypes.byref(size),
+                                        None), "wg_grid_records_ws")
+        return int(size.value)
+    runs = WgRuns()
+    _check(lib().wg_grid_records_ws(ctypes.byref(geom), int(nb), int(nc), int(nt), _p(ws), ctypes.byref(size),
+                                    ctypes.byref(runs)), "wg_grid_records_ws")
+    return runs
+
+
+def wg_grid_records(geom, kt, uvw, inv_lambda, vis, weight, flag, nb, nc, nt, grid, stats, ws: torch.Tensor,
+                    stream=None):
+    runs = WgRuns()
+    _check(lib().wg_grid_records(ctypes.byref(geom), ctypes.byref(kt), _p(uvw), _p(inv_lambda), _p(vis), _p(weight),
+                                 _p(flag), int(nb), int(nc), int(nt), _p(grid), _p(stats), _p(ws),
+                                 ws.numel() * ws.element_size(), ctypes.byref(runs), _stream(stream)),
+           "wg_grid_records")
+    return runs
 
 
 def wg_degrid(geom, kt, runs: WgRuns, stats, grid, uvw, weight, flag, nb, nc, nt, vis_out, stream=None):
@@ -258,32 +286,43 @@ class Stats:
 
 
 class Runs:
-    """Run list + plan + device statistics for one record batch."""
+    """Run list + plan + normalisers of one record batch, all views of one device workspace
+    laid out by wg_grid_records_ws (the workspace wg_grid_records fills), plus the device
+    statistics."""
 
-    def __init__(self, capacity: int, n_segments: int, device="cuda", grid_ids: bool = False, n_norms: int = 0,
-                 n_pol: int = 1):
+    def __init__(self, geom: WgGeom, nb: int, nc: int, nt: int, device="cuda"):
         dev = torch.device(device)
-        cap = max(1, int(capacity))
-        self.capacity = cap
-        self.n_pol = max(1, int(n_pol))
-        self.start = torch.empty(cap, dtype=torch.int32, device=dev)
-        self.len = torch.empty(cap, dtype=torch.int32, device=dev)
-        self.x = torch.empty(cap, dtype=torch.int32, device=dev)
-        self.y = torch.empty(cap, dtype=torch.int32, device=dev)
-        self.plane = torch.empty(cap, dtype=torch.int16, device=dev)
-        self.ou = torch.empty(cap, dtype=torch.int8, device=dev)
-        self.ov = torch.empty(cap, dtype=torch.int8, device=dev)
-        self.gamma = torch.empty(2 * cap * self.n_pol, dtype=torch.float32, device=dev)
-        pe = wg_plan_elems(cap, n_segments)
-        self.plan = torch.empty(pe, dtype=torch.int32, device=dev)
-        self.work = torch.empty(2 * cap * self.n_pol, dtype=torch.float32, device=dev)
+        self.n_pol = max(1, geom.n_pol)
+        self.ws = torch.empty(wg_grid_records_ws(geom, nb, nc, nt), dtype=torch.uint8, device=dev)
+        self.c = wg_grid_records_ws(geom, nb, nc, nt, self.ws)
+        self.capacity = int(self.c.capacity)
         self.stats_d = torch.zeros(8, dtype=torch.int64, device=dev)
+        base = self.ws.data_ptr()
+        cap = self.capacity
+
+        def view(ptr, n, dt):
+            if ptr is None:
+                return None
+            off = int(ptr) - base
+            nbytes = n * torch.empty((), dtype=dt).element_size()
+            return self.ws[off:off + nbytes].view(dt)
+
+        self.start = view(self.c.start, cap, torch.int32)
+        self.len = view(self.c.len, cap, torch.int32)
+        self.x = view(self.c.x, cap, torch.int32)
+        self.y = view(self.c.y, cap, torch.int32)
+        self.plane = view(self.c.plane, cap, torch.int16)
+        self.ou = view(self.c.ou, cap, torch.int8)
+        self.ov = view(self.c.ov, cap, torch.int8)
+        self.gamma = view(self.c.gamma, 2 * cap * self.n_pol, torch.float32)
+        self.work = view(self.c.work, 2 * cap * self.n_pol, torch.float32)
+        self.plan = view(self.c.plan, int(self.c.plan_elems), torch.int32)
         # per-channel grids and w-stacking: the grid of each run; per-channel grids or several
         # polarisations: the normalisers [grid][polarisation]
-        self.grid = torch.empty(cap, dtype=torch.int16, device=dev) if grid_ids else None
-        self.norm = torch.zeros(n_norms, dtype=torch.float64, device=dev) if n_norms > 0 else None
-        self.c = WgRuns(cap, _p(self.start), _p(self.len), _p(self.x), _p(self.y), _p(self.plane), _p(self.ou),
-                        _p(self.ov), _p(self.gamma), _p(self.plan), pe, _p(self.work), _p(self.grid), _p(self.norm))
+        per_channel = bool(geom.flags & WG_GRID_PER_CHANNEL)
+        self.grid = view(self.c.grid, cap, torch.int16) if per_channel or geom.flags & WG_W_STACKING else None
+        n_norms = nc * self.n_pol if per_channel else self.n_pol if self.n_pol > 1 else 0
+        self.norm = view(self.c.norm, n_norms, torch.float64) if n_norms else None
 
     def normaliser(self, g: int | None = None) -> torch.Tensor:
         """float64 device view of the normaliser(s): P values (of grid g with per-channel
@@ -335,9 +374,7 @@ class Gridder:
         for name, arr in (("weight", self.weight), ("flag", self.flag)):
             if arr is not None and arr.numel() != self.n_rec * self.n_pol:
                 raise ValueError(f"{name} has {arr.numel()} values, expected {self.n_rec} records x {self.n_pol}")
-        n_norms = self.nc * self.n_pol if self.per_channel else self.n_pol if self.n_pol > 1 else 0
-        self.runs = Runs(self.n_rec, self.nb * self.nc, device=uvw.device,
-                         grid_ids=self.per_channel or self.w_stacking, n_norms=n_norms, n_pol=self.n_pol)
+        self.runs = Runs(geom, self.nb, self.nc, self.nt, device=uvw.device)
 
     def grid_shape(self):
         n = self.geom.n
@@ -354,6 +391,20 @@ class Gridder:
             raise ValueError(f"vis has shape {tuple(vis.shape)}, expected {self.vis_shape()} complex values")
         wg_compress(self.geom, self.table.kt, self.uvw, self.inv_lambda, _f32_view(vis.contiguous()), self.weight,
                     self.flag, self.nb, self.nc, self.nt, self.runs.c, self.runs.stats_d, stream)
+
+    def grid_records(self, vis, out=None, stream=None):
+        """compress + grid in one call (wg_grid_records): the batch's runs are left in the
+        workspace for degrid. Accumulates into `out` (zeros when not given)."""
+        if vis.numel() != self.n_rec * self.n_pol * (1 if vis.is_complex() else 2):
+            raise ValueError(f"vis has shape {tuple(vis.shape)}, expected {self.vis_shape()} complex values")
+        if out is None:
+            out = torch.zeros(self.grid_shape(), dtype=torch.complex64, device=self.uvw.device)
+        elif tuple(out.shape) != self.grid_shape():
+            raise ValueError(f"grid shape {tuple(out.shape)} != {self.grid_shape()}")
+        wg_grid_records(self.geom, self.table.kt, self.uvw, self.inv_lambda, _f32_view(vis.contiguous()), self.weight,
+                        self.flag, self.nb, self.nc, self.nt, torch.view_as_real(out), self.runs.stats_d, self.runs.ws,
+                        stream)
+        return out
 
     def grid(self, out=None, stream=None):
         """Accumulate the batch into a complex64 grid ([n][n], or [nc][n][n] per channel, or
@@ -403,13 +454,12 @@ class Gridder:
 
 
 class GridFn(torch.autograd.Function):
-    """grid = G(vis) with compression; backward returns G^H(grad_grid) via wg_degrid, the
+    """grid = G(vis) with compression (forward: wg_grid_records); backward returns G^H(grad_grid) via wg_degrid, the
     adjoint for the real inner product Re<a, b> (PyTorch's complex-gradient convention)."""
 
     @staticmethod
     def forward(ctx, vis, gridder: Gridder):
-        gridder.compress(vis)
-        out = gridder.grid()
+        out = gridder.grid_records(vis)
         ctx.gridder = gridder
         return out
 

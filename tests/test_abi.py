@@ -27,7 +27,7 @@ def test_header_declares_entry_points():
     names = declared_functions()
     for n in ["wg_status_str", "wg_version", "wg_ktable_sizes", "wg_ktable_build", "wg_plan_elems",
               "wg_compress", "wg_grid", "wg_degrid", "wg_finalise_ws_bytes", "wg_finalise",
-              "wg_finalise_stacked"]:
+              "wg_finalise_stacked", "wg_grid_records_ws", "wg_grid_records"]:
         assert n in names
 
 
@@ -187,3 +187,68 @@ def test_polarisation_count_and_normalisers(wg):
     assert L.wg_finalise_ws_bytes(by(wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)), by(ws1)) == wg.WG_OK
     assert L.wg_finalise_ws_bytes(by(g4), by(ws4)) == wg.WG_OK
     assert ws4.value >= ws1.value + 3 * 256 * 256 * 4
+
+
+def test_grid_records_workspace_layout_and_rejections(wg):
+    """wg_grid_records_ws sizes the one-call workspace and carves it into the run arrays,
+    grid ids, normalisers and plan (256-byte aligned, disjoint, inside the workspace) without
+    touching the device; wg_grid_records rejects bad arguments before any work."""
+    L = wg.lib()
+    by = ctypes.byref
+    nb, nc, nt = 28, 4, 64
+    cap = nb * nc * nt
+    for kw, npol, ids, n_norm in [(dict(), 1, False, 1), (dict(n_pol=4), 4, False, 4),
+                                  (dict(per_channel=True, n_pol=2), 2, True, nc * 2),
+                                  (dict(w_stacking=True), 1, True, 1)]:
+        g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0, **kw)
+        size = ctypes.c_size_t(0)
+        assert L.wg_grid_records_ws(by(g), nb, nc, nt, None, by(size), None) == wg.WG_OK
+        base = 1 << 40                      # a host-side stand-in address; nothing is dereferenced
+        runs = wg.WgRuns()
+        assert L.wg_grid_records_ws(by(g), nb, nc, nt, base, by(size), by(runs)) == wg.WG_OK
+        assert runs.capacity == cap and runs.plan_elems == wg.wg_plan_elems(cap, nb * nc)
+        spans = [(runs.start, 4 * cap), (runs.len, 4 * cap), (runs.x, 4 * cap), (runs.y, 4 * cap),
+                 (runs.plane, 2 * cap), (runs.ou, cap), (runs.ov, cap), (runs.gamma, 8 * cap * npol),
+                 (runs.work, 8 * cap * npol), (runs.norm, 8 * n_norm), (runs.plan, 4 * runs.plan_elems)]
+        if ids:
+            spans.append((runs.grid, 2 * cap))
+        else:
+            assert runs.grid is None
+        spans.sort()
+        for (a, na), (b, _) in zip(spans, spans[1:]):
+            assert a % 256 == 0 and a + na <= b
+        assert spans[0][0] >= base and spans[-1][0] + spans[-1][1] <= base + size.value
+        small = ctypes.c_size_t(size.value - 1)
+        assert L.wg_grid_records_ws(by(g), nb, nc, nt, base, by(small), by(runs)) == wg.WG_ECAPACITY
+        assert L.wg_grid_records_ws(by(g), nb, nc, nt, base + 8, by(size), by(runs)) == wg.WG_EINVAL
+    g = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)
+    size = ctypes.c_size_t(0)
+    assert L.wg_grid_records_ws(by(g), 0, nc, nt, None, by(size), None) == wg.WG_EINVAL
+    assert L.wg_grid_records_ws(by(g), nb, nc, nt, None, None, None) == wg.WG_EINVAL
+    assert L.wg_grid_records_ws(by(g), 1 << 20, 64, 64, None, by(size), None) == wg.WG_EUNSUPPORTED
+    assert L.wg_grid_records_ws(by(g), nb, nc, nt, None, by(size), None) == wg.WG_OK
+    ws = size.value
+    kt = wg.WgKtable(0, 8, 8, 7, 1, 1, 1, 1, 1, 10)
+    A = 1 << 40
+    # (uvw, inv_lambda, vis, weight, flag, nb, nc, nt, grid, stats, ws, ws_bytes)
+    ok = [1, 1, 1, None, None, nb, nc, nt, 1, 1, A, ws]
+
+    def call(geom=g, table=kt, **change):
+        args = list(ok)
+        names = ["uvw", "il", "vis", "wt", "flag", "nb", "nc", "nt", "grid", "stats", "ws", "ws_bytes"]
+        for k, v in change.items():
+            args[names.index(k)] = v
+        return L.wg_grid_records(by(geom), by(table) if table is not None else None, *args, None, None)
+
+    assert call(grid=None) == wg.WG_EINVAL
+    assert call(stats=None) == wg.WG_EINVAL
+    assert call(ws=None) == wg.WG_EINVAL
+    assert call(ws=A + 64) == wg.WG_EINVAL
+    assert call(ws_bytes=ws - 1) == wg.WG_ECAPACITY
+    assert call(uvw=None) == wg.WG_EINVAL
+    assert call(vis=None) == wg.WG_EINVAL
+    assert call(nt=0) == wg.WG_EINVAL
+    assert call(table=None) == wg.WG_EINVAL
+    assert call(table=wg.WgKtable(0, 4, 8, 7, 1, 1, 1, 1, 1, 10)) == wg.WG_EINVAL
+    assert call(table=wg.WgKtable(0, 8, 8, 7, 1, 1, 1, 1, 1, 1 << 28)) == wg.WG_EUNSUPPORTED
+    assert call(nb=1 << 20, nc=64, nt=64) == wg.WG_EUNSUPPORTED
