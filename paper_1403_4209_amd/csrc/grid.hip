@@ -221,6 +221,18 @@ __device__ inline int sdot2(u16x2 w, i16x2 m, int c) {
     return __builtin_amdgcn_sdot2(__builtin_bit_cast(i16x2, w), m, c, false);
 }
 
+// The same with a wave-uniform addend in a scalar register, as one three-operand
+// v_dot2_i32_i16. (From the builtin the compiler selects the two-operand v_dot2c_i32_i16,
+// whose addend is its destination, and copies the scalar into it first: two operations per
+// slot and run instead of one.)
+__device__ inline int sdot2_s(u16x2 w, i16x2 m, int c) {
+    int r;
+    asm("v_dot2_i32_i16 %0, %1, %2, %3"
+        : "=v"(r)
+        : "v"(__builtin_bit_cast(unsigned, w)), "v"(__builtin_bit_cast(unsigned, m)), "s"(c));
+    return r;
+}
+
 // The lane's classes of a chunk: slot m holds class min(c0 + 64 m + lane, c1 - 1) as (q, p).
 template <int NS>
 __device__ inline void lane_classes(int S, int c0, int c1, int lane, u16x2 *cls) {
@@ -334,7 +346,7 @@ __device__ void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int
             if constexpr (mirror_reads<DT>()) {
                 const i16x2 mul = as_i16x2(in_vgpr((unsigned)rl(b.mul, t)));
 #pragma unroll
-                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, sdot2(wpos[m], mul, (int)kbB));
+                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, sdot2_s(wpos[m], mul, (int)kbB));
             } else {
 #pragma unroll
                 for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
@@ -552,7 +564,7 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
             if constexpr (mirror_reads<DT>()) {
                 const i16x2 mul = as_i16x2(in_vgpr((unsigned)rl(b.mul, t)));
 #pragma unroll
-                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, sdot2(wpos[m], mul, (int)kbB));
+                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, sdot2_s(wpos[m], mul, (int)kbB));
             } else {
 #pragma unroll
                 for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
