@@ -305,6 +305,26 @@ int wg_grid_records(const wg_geom *g, const wg_ktable *kt, const double *uvw, co
                     wg_stream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops or harnesses that forbid hipMalloc): wg_grid_records with its workspace in a fixed
+ * array of WG_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on until the
+ * process ends, instead of a workspace argument. Arguments, layouts, accumulation and
+ * errors are those of wg_grid_records without ws and ws_bytes; it allocates nothing.
+ *   runs_out [host] optional: the wg_runs view of the array on the current device, valid
+ *            until the next call on that device (wg_degrid may use it in between).
+ * The current device must be the one `stream` and the pointers belong to. Every call on a
+ * GPU shares that GPU's array and leaves its contents there: calls that overlap in time on
+ * one GPU (other streams or threads) race and give wrong results.
+ * Errors: WG_ECAPACITY when the batch's workspace (wg_grid_records_ws) exceeds
+ * WG_STATIC_SCRATCH_BYTES (about 1.4 million single-polarisation records); WG_EHIP when the
+ * array's device address cannot be had; otherwise those of wg_grid_records.
+ */
+#define WG_STATIC_SCRATCH_BYTES (64u << 20)
+int wg_grid_records_static(const wg_geom *g, const wg_ktable *kt, const double *uvw, const double *inv_lambda,
+                           const float *vis, const float *weight, const uint8_t *flag, int64_t nb, int32_t nc,
+                           int32_t nt, float *grid, wg_stats *stats, wg_runs *runs_out, wg_stream_t stream);
+
+/*
  * Adjoint of wg_compress + wg_grid with respect to the visibilities: per run
  * d[p] = sum_ij conj(K[i][j]) * grid[p][row0+i][a+j] (grid complex64 [P][n][n], or
  * [nc][P][n][n] / [n_w][P][n][n] read at grid runs->grid[q] with WG_GRID_PER_CHANNEL /

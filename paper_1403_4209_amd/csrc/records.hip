@@ -2,6 +2,8 @@
 // generator's outputs C-1..C-3 in; the grid O-1 and the normaliser O-2 out), i.e. the
 // preparation phase (wg_compress) followed by the gridding phase (wg_grid), with the run
 // list and plan carved out of one caller-owned workspace.
+#include <mutex>
+
 #include "wg_common.hpp"
 
 namespace wg {
@@ -99,6 +101,60 @@ extern "C" int wg_grid_records(const wg_geom *g, const wg_ktable *kt, const doub
     if (ws_bytes < carve(g, nb, nc, nt, nullptr, nullptr)) return WG_ECAPACITY;
     wg_runs r;
     carve(g, nb, nc, nt, (char *)ws, &r);
+    if (runs_out) *runs_out = r;
+    return grid_records_into(g, kt, uvw, inv_lambda, vis, weight, flag, nb, nc, nt, grid, stats, &r, stream);
+}
+
+// ---------------------------------------------------------------------------------------
+// Workspace-free variant: the run list, plan and normalisers live in `scratch`, a fixed
+// array of this library on each GPU (held until the process ends). In host code the
+// array's name stands for no device address: its address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current, and only that
+// address is handed to the kernels.
+namespace wg {
+namespace {
+
+constexpr size_t kScratchBytes = WG_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex scratch_mu;
+void *scratch_at[kMaxDevices];
+
+// The device address of `scratch` on the current device, or NULL on a HIP error.
+void *scratch_address(int dev) {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_at[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        scratch_at[dev] = p;
+    }
+    return scratch_at[dev];
+}
+
+}  // namespace
+}  // namespace wg
+
+extern "C" int wg_grid_records_static(const wg_geom *g, const wg_ktable *kt, const double *uvw,
+                                      const double *inv_lambda, const float *vis, const float *weight,
+                                      const uint8_t *flag, int64_t nb, int32_t nc, int32_t nt, float *grid,
+                                      wg_stats *stats, wg_runs *runs_out, wg_stream_t stream) {
+    using namespace wg;
+    int st = check_geom(g);
+    if (st != WG_OK) return st;
+    if ((st = check_table(g, kt)) != WG_OK) return st;
+    if ((st = check_sizes(nb, nc, nt)) != WG_OK) return st;
+    if (!grid || !stats) return WG_EINVAL;
+    if (kt->data_cap >= ((int64_t)1 << 28)) return WG_EUNSUPPORTED;
+    if (carve(g, nb, nc, nt, nullptr, nullptr) > kScratchBytes) return WG_ECAPACITY;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return WG_EHIP;
+    if (dev >= kMaxDevices) return WG_EUNSUPPORTED;
+    void *base = scratch_address(dev);
+    if (!base) return WG_EHIP;
+    wg_runs r;
+    carve(g, nb, nc, nt, (char *)base, &r);
     if (runs_out) *runs_out = r;
     return grid_records_into(g, kt, uvw, inv_lambda, vis, weight, flag, nb, nc, nt, grid, stats, &r, stream);
 }

@@ -86,6 +86,8 @@ def lib():
         L.wg_grid_records_ws.argtypes = [P, I64, I32, I32, P, P, P]
         L.wg_grid_records.restype = ctypes.c_int
         L.wg_grid_records.argtypes = [P, P, P, P, P, P, P, I64, I32, I32, P, P, P, ctypes.c_size_t, P, P]
+        L.wg_grid_records_static.restype = ctypes.c_int
+        L.wg_grid_records_static.argtypes = [P, P, P, P, P, P, P, I64, I32, I32, P, P, P, P]
         L.wg_degrid.restype = ctypes.c_int
         L.wg_degrid.argtypes = [P, P, P, P, P, P, P, P, I64, I32, I32, P, P]
         L.wg_finalise_ws_bytes.restype = ctypes.c_int
@@ -181,6 +183,16 @@ def wg_grid_records(geom, kt, uvw, inv_lambda, vis, weight, flag, nb, nc, nt, gr
                                  _p(flag), int(nb), int(nc), int(nt), _p(grid), _p(stats), _p(ws),
                                  ws.numel() * ws.element_size(), ctypes.byref(runs), _stream(stream)),
            "wg_grid_records")
+    return runs
+
+
+def wg_grid_records_static(geom, kt, uvw, inv_lambda, vis, weight, flag, nb, nc, nt, grid, stats, stream=None):
+    """wg_grid_records with the library's own fixed device array as workspace (allocates
+    nothing); returns the WgRuns view of that array on the current device."""
+    runs = WgRuns()
+    _check(lib().wg_grid_records_static(ctypes.byref(geom), ctypes.byref(kt), _p(uvw), _p(inv_lambda), _p(vis),
+                                        _p(weight), _p(flag), int(nb), int(nc), int(nt), _p(grid), _p(stats),
+                                        ctypes.byref(runs), _stream(stream)), "wg_grid_records_static")
     return runs
 
 
