@@ -316,8 +316,9 @@ int wg_grid_records(const wg_geom *g, const wg_ktable *kt, const double *uvw, co
  * GPU shares that GPU's array and leaves its contents there: calls that overlap in time on
  * one GPU (other streams or threads) race and give wrong results.
  * Errors: WG_ECAPACITY when the batch's workspace (wg_grid_records_ws) exceeds
- * WG_STATIC_SCRATCH_BYTES (about 1.4 million single-polarisation records); WG_EHIP when the
- * array's device address cannot be had; otherwise those of wg_grid_records.
+ * WG_STATIC_SCRATCH_BYTES (about 1.5 million records with one polarisation, 0.7 million
+ * with four); WG_EHIP when the array's device address cannot be had; otherwise those of
+ * wg_grid_records.
  */
 #define WG_STATIC_SCRATCH_BYTES (64u << 20)
 int wg_grid_records_static(const wg_geom *g, const wg_ktable *kt, const double *uvw, const double *inv_lambda,
