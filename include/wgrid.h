@@ -154,8 +154,9 @@ typedef struct wg_ktable {
  * the sum over its records of weight * (1 - flag) * (vis, conjugated when w < 0), as float32
  * (re, im) (eqs. compress1, conjugatetake). Runs are in record order.
  * `plan` is a device work list the gridder reads (local chunks of equal support, grouped by
- * support); size it with wg_plan_elems. It also holds wg_degrid's work counter, so two
- * wg_degrid calls on the same runs must not overlap in time.
+ * support); size it with wg_plan_elems. It also holds the work counters of wg_degrid and
+ * (on grids of side 4096 and more) wg_grid, so two wg_degrid calls, or two wg_grid calls, on
+ * the same runs must not overlap in time.
  * With WG_GRID_PER_CHANNEL, `grid` (one int16 per run: the channel of its records, i.e. the
  * grid it goes to) and `norm` (one double per channel: that channel's normaliser N of eq.
  * normalizer) are required and written by wg_compress. With WG_W_STACKING, `grid` is

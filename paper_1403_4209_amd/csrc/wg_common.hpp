@@ -27,6 +27,7 @@ constexpr int kDegridSlotsPol4 = 3;  // with four (9.55 vs 11.65 ms with 2, 20.8
 //   [kPlanOff + S]     first item slot of support S       (kPlanOff + 64 = total)
 //   [kPlanCur + S]     append cursor of support S
 //   [kPlanQueueDegrid] degridder work-list counter and exit count (2 words), zero between launches
+//   [kPlanQueueGrid]   the same for the gridder's counter walk (large grids)
 //   [kPlanGrids]       number of grids the runs address (channels, w-planes or 1)
 //   [kPlanHdr ...]     items: 2 * capacity words
 //   then               runs per segment, scanned in place: n_seg + 1 words
@@ -36,6 +37,7 @@ constexpr int kPlanCount = 0;
 constexpr int kPlanOff = 64;
 constexpr int kPlanCur = 129;
 constexpr int kPlanQueueDegrid = 200;
+constexpr int kPlanQueueGrid = 208;
 constexpr int kPlanGrids = 240;  // read by every batch: kept off the work counter's cache line
 constexpr int kPlanHdr = 256;
 constexpr int kScanTile = 4096;
