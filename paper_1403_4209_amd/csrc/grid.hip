@@ -540,11 +540,10 @@ static_assert(kDegridSlots <= kSlots && kDegridSlotsNarrow <= kSlots && kDegridS
                   kDegridSlotsPol4 <= kSlots && kSlotsNarrow <= kSlots && kSlotsPol2 <= kSlots &&
                   kSlotsPol4 <= kSlots,
               "per-lane stage arrays hold kSlots classes");
-template <int DT, int NP>
+template <int DT>
 struct DStage {
     typename KRaw<DT>::type k[kSlots];
-    float2 g[kSlots][NP];  // grid values of the run's cells (loaded when the footprint moved)
-    bool moved;            // wave-uniform: the run's footprint origin differs from the previous run's
+    bool moved;  // wave-uniform: the run's footprint origin differs from the previous run's
 };
 
 // The NP complex values of one cell, one from each polarisation plane ([NP][n][n] grid).
@@ -554,21 +553,28 @@ __device__ inline void load_cell(const float2 *grid, unsigned cell, int64_t cell
     for (int p = 0; p < NP; ++p) v[p] = grid[cell + p * cells];
 }
 
+// Order of the loads per run t: the samples of run t + 1 are issued before run t's sums, and
+// when run t + 1 moves the footprint its grid values are loaded into the owned-cell registers
+// right after run t's last use of them. The wait before run t + 1's sums then covers those
+// grid values and run t + 1's samples while run t + 2's samples stay in flight, whichever path
+// was taken.
 template <int DT, int NP, int NS>
-__device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
-                                const int64_t *koff) {
+__device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb,
+                                                               int re, int lane, const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
-    constexpr int nslots = NS;
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
     const float2 *grid = (const float2 *)a.grid;
     u16x2 cls[kSlots];
     lane_classes<NS>(S, c0, c1, lane, cls);
-    const bool last_ok = c0 + (nslots - 1) * kWave + lane < c1;
+    const bool last_ok = c0 + (NS - 1) * kWave + lane < c1;
+    // lanes without a class in the last slot read their samples past the table's end (zeros)
+    const unsigned idle_off = last_ok ? 0u : 0x80000000u;
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
     const u16x2 mul_k = as_u16x2(in_vgpr((unsigned)(S * esz) << 16 | (unsigned)esz));
     const u16x2 mul_c = as_u16x2(in_vgpr((unsigned)a.n << 16 | 1u));
-    float2 gv[NS][NP];    // grid values of the owned cells
-    u16x2 wpos[kSlots];   // footprint positions, recomputed only when the footprint moves
+    float2 gv[NS][NP];       // grid values of the owned cells
+    u16x2 wpos[kSlots];      // footprint positions, recomputed only when the footprint moves
+    unsigned gcell[kSlots];  // owned cells of the last run that moved the footprint
     unsigned last_cell0 = kNoCell;
 #pragma unroll
     for (int m = 0; m < NS; ++m)
@@ -583,13 +589,20 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
             if constexpr (mirror_reads<DT>()) {
                 const i16x2 mul = as_i16x2(in_vgpr((unsigned)rl(b.mul, t)));
 #pragma unroll
-                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, sdot2_s(wpos[m], mul, (int)kbB));
+                for (int m = 0; m < NS; ++m) {
+                    const unsigned off = (unsigned)sdot2_s(wpos[m], mul, (int)kbB);
+                    k[m] = buf_load<DT>(rs, (int)(m == NS - 1 ? off | idle_off : off));
+                }
             } else {
 #pragma unroll
-                for (int m = 0; m < NS; ++m) k[m] = buf_load<DT>(rs, (int)dot2(wpos[m], mul_k, kbB));
+                for (int m = 0; m < NS; ++m) {
+                    const unsigned off = dot2(wpos[m], mul_k, kbB);
+                    k[m] = buf_load<DT>(rs, (int)(m == NS - 1 ? off | idle_off : off));
+                }
             }
         };
-        auto fetch = [&](int t, DStage<DT, NP> &st) {
+        // footprint positions and cells (when the footprint moved) and samples of run t
+        auto fetch = [&](int t, DStage<DT> &st) {
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
             const bool ok = rl(b.ok, t) != 0;
@@ -600,34 +613,31 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
 #pragma unroll
                 for (int m = 0; m < NS; ++m) {
                     wpos[m] = footprint_pos(cls[m], ph, ss);
-                    load_cell<NP>(grid, dot2(wpos[m], mul_c, cell0), a.cells, st.g[m]);
+                    gcell[m] = dot2(wpos[m], mul_c, cell0);
                 }
             }
             load_samples(t, kbB, st.k);
+        };
+        auto load_values = [&]() {
+#pragma unroll
+            for (int m = 0; m < NS; ++m) load_cell<NP>(grid, gcell[m], a.cells, gv[m]);
         };
         // this wave's sums: lane l holds component l >> 5 (0 real, 1 imaginary) of run
         // base + (l & 31) in lo and of run base + 32 + (l & 31) in hi
         float lo[NP], hi[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) lo[p] = hi[p] = 0.f;
-        auto consume = [&](int t, const DStage<DT, NP> &st) {
+        auto consume = [&](int t, const DStage<DT> &st) {
             float pr[NP], pim[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) pr[p] = pim[p] = 0.f;
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
-                if (m < nslots) {
-                    if (st.moved)
+                const float2 kv = to_float2<DT>(st.k[m]);
 #pragma unroll
-                        for (int p = 0; p < NP; ++p) gv[m][p] = st.g[m][p];
-                    if (m < nslots - 1 || last_ok) {
-                        const float2 kv = to_float2<DT>(st.k[m]);
-#pragma unroll
-                        for (int p = 0; p < NP; ++p) {
-                            pr[p] = fmaf(kv.x, gv[m][p].x, fmaf(kv.y, gv[m][p].y, pr[p]));
-                            pim[p] = fmaf(kv.x, gv[m][p].y, fmaf(-kv.y, gv[m][p].x, pim[p]));
-                        }
-                    }
+                for (int p = 0; p < NP; ++p) {
+                    pr[p] = fmaf(kv.x, gv[m][p].x, fmaf(kv.y, gv[m][p].y, pr[p]));
+                    pim[p] = fmaf(kv.x, gv[m][p].y, fmaf(-kv.y, gv[m][p].x, pim[p]));
                 }
             }
             // the wave's sums for run t wait in lanes (t & 31) and 32 + (t & 31); two atomics
@@ -641,15 +651,18 @@ __device__ void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, i
             }
         };
 
-        DStage<DT, NP> sa, sb;
+        DStage<DT> sa, sb;
         fetch(0, sa);
+        if (sa.moved) load_values();
         // the next run's fetch is issued on every path, as in the gridder
         for (int t = 0; t < n; t += 2) {
             fetch(min(t + 1, n - 1), sb);
             consume(t, sa);
+            if (sb.moved) load_values();
             if (t + 1 < n) {
                 fetch(min(t + 2, n - 1), sa);
                 consume(t + 1, sb);
+                if (sa.moved) load_values();
             }
         }
         const int r = lane & 31, comp = lane >> 5;
