@@ -1,12 +1,21 @@
 // Gridding phase (eq. gridding) and its adjoint on gfx950.
 //
 // Work unit = one local chunk (consecutive runs of one baseline/channel trajectory with a
-// common support S) x one share of its S*S cell classes. A class (p, q) stands for the grid
+// common support S) x one share of its cell classes. A class (p, q) stands for the grid
 // cells with y = p mod S and x = q mod S; every footprint position holds exactly one cell of
 // each class. Lane l owns a few classes: as the footprint slides along the trajectory the
 // lane keeps updating the same cell, accumulating gamma*K in registers with Kahan
 // compensation, and commits (one FP32 atomic add per component) only when the cell leaves
 // the footprint -- the ownership idea of Romein's gridder, applied per wavefront.
+//
+// Classes are owned in pairs (q, q + 1) of one footprint row: the two samples sit next to
+// each other in a table row (padded with the last column before it and the first column
+// after it, so that the pair that wraps from column S - 1 to column 0 is adjacent too, read
+// forwards or, for a mirrored matrix, backwards) and one 16-byte load (8 bytes with 16-bit
+// tables) fetches both. A vector load instruction costs about the same whatever its width,
+// and the instruction rate of the vector memory path is what bounds these kernels.
+#include <type_traits>
+
 #include "wg_common.hpp"
 
 #pragma clang fp contract(off)
@@ -50,24 +59,15 @@ __device__ inline float2 load_k(const void *data, int64_t idx) {
     return make_float2((float)lo, (float)hi);
 }
 
-// Raw table sample as fetched (converted to float only when used, so that a wave can keep
-// several loads in flight).
-template <int DT> struct KRaw { using type = uint32_t; };
-template <> struct KRaw<WG_KF32> { using type = float2; };
+// The two samples of a class pair as fetched (converted to float only when used, so that a
+// wave can keep several loads in flight): four floats with FP32 tables, two packed complex
+// 16-bit values otherwise.
+template <int DT> struct PairRaw { using type = uint2; };
+template <> struct PairRaw<WG_KF32> { using type = float4; };
 
 template <int DT>
-__device__ inline typename KRaw<DT>::type load_raw(const void *data, int64_t idx) {
-    if constexpr (DT == WG_KF32)
-        return ((const float2 *)data)[idx];
-    else
-        return ((const uint32_t *)data)[idx];
-}
-
-template <int DT>
-__device__ inline float2 to_float2(typename KRaw<DT>::type u) {
-    if constexpr (DT == WG_KF32) {
-        return u;
-    } else if constexpr (DT == WG_KBF16) {
+__device__ inline float2 to_float2(uint32_t u) {
+    if constexpr (DT == WG_KBF16) {
         return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xFFFF0000u));
     } else {
         _Float16 lo, hi;
@@ -78,12 +78,13 @@ __device__ inline float2 to_float2(typename KRaw<DT>::type u) {
     }
 }
 
+// Sample h (0: first class of the pair, 1: second) as a complex float.
 template <int DT>
-__device__ inline typename KRaw<DT>::type raw_zero() {
+__device__ inline float2 pair_sample(const typename PairRaw<DT>::type &v, int h) {
     if constexpr (DT == WG_KF32)
-        return make_float2(0.f, 0.f);
+        return h == 0 ? make_float2(v.x, v.y) : make_float2(v.z, v.w);
     else
-        return 0u;
+        return to_float2<DT>(h == 0 ? v.x : v.y);
 }
 
 // Supports present in the plan, largest first, with their first work unit.
@@ -100,7 +101,7 @@ __device__ void build_units(const int32_t *plan, int slots, UnitTable *t) {
         if (c > 0) {
             t->S[m] = S;
             t->first[m] = u;
-            u += c * nchunk_of(S, slots);
+            u += c * nchunk_pairs(S, slots);
             ++m;
         }
     }
@@ -110,20 +111,19 @@ __device__ void build_units(const int32_t *plan, int slots, UnitTable *t) {
 
 // Run records of up to 64 consecutive runs, one per lane, with everything the per-run loop
 // needs precomputed in parallel; the loop then broadcasts run t with v_readlane.
-// FP32 tables are read only at non-negative oversample offsets. The kernel is even in u and
-// in v (eq. C_W: the taper and the w-screen are even in l and in m), so the matrix of offset
-// -o along an axis is the matrix of +o reversed along that axis (position j <-> S-1-j). Reading
-// the 25 of 64 slices with o >= 0 per axis, mirrored where the run's offset is negative, cuts
-// the samples a plane keeps in the caches by 2.5 (about 6 % off grid and degrid on a 32-plane
-// 2048^2 workload; with 16-bit tables the extra index arithmetic costs more than it saves).
-template <int DT>
-constexpr bool mirror_reads() { return DT == WG_KF32; }
-
+// Tables are read only at non-negative oversample offsets. The kernel is even in u and in v
+// (eq. C_W: the taper and the w-screen are even in l and in m), so the matrix of offset -o
+// along an axis is the matrix of +o reversed along that axis (position j <-> S - 1 - j).
+// Reading the 25 of 64 matrices with o >= 0 per axis, backwards along an axis where the
+// run's offset is negative, cuts the samples a plane keeps in the caches by 2.5. Read
+// backwards along u, the load of a class pair starts at the pair's second sample, so the
+// two halves of the load change places.
 template <int NP>
 struct RunBatch {
     int cell0, ph, kb, ok;  // ph: footprint origin phases, (row0 mod S) << 16 | (ax mod S)
-    int mul;                // mirrored reads: signed byte strides (row << 16 | column) of the
-                            // footprint position; kb then starts at the mirrored origin
+    int mul;                // signed byte strides of the footprint position in the table,
+                            // row << 16 | column (a negative column stride: the pair's
+                            // samples arrive swapped); kb is the matrix origin read from
     float gr[NP], gi[NP];   // the run's weighted visibility sum per polarisation
 };
 
@@ -133,6 +133,7 @@ __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <int DT, int NP>
 __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool valid, const int64_t *koff) {
+    constexpr int esz = (DT == WG_KF32) ? 8 : 4;
     RunBatch<NP> b;
     b.ok = 0;
     b.cell0 = b.ph = b.kb = b.mul = 0;
@@ -142,27 +143,23 @@ __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool val
         const int H = (S - 1) >> 1, half = a.n >> 1, hb = a.beta >> 1;
         const int X = a.x[j], Y = a.y[j], k = a.plane[j];
         const int gid = a.grid_id ? a.grid_id[j] : 0;
-        const int ou = a.ou[j], ov = a.ov[j];
-        const int su = mirror_reads<DT>() ? abs(ou) : ou, sv = mirror_reads<DT>() ? abs(ov) : ov;
-        const int sigma = (sv + hb - 1) * a.beta + (su + hb - 1);
+        const int ou = a.ou[j], ov = a.ov[j], W = S + 2;  // W: samples per table row
+        const int sigma = (abs(ov) + hb - 1) * a.beta + (abs(ou) + hb - 1);
         const int ax = X + half - H, row0 = Y + half - H;
-        const int64_t kbase = koff[k] + (int64_t)sigma * S * S;
+        const int64_t kbase = koff[k] + (int64_t)sigma * S * W;
         // runs from wg_compress with the same geometry and table always pass; anything else
         // is skipped rather than read or written out of bounds
         if (ax >= 0 && ax + S <= a.n && row0 >= 0 && row0 + S <= a.n && kbase >= 0 &&
-            kbase + (int64_t)S * S <= a.data_cap && gid >= 0 && gid < a.plan[kPlanGrids]) {
+            kbase + (int64_t)S * W <= a.data_cap && gid >= 0 && gid < a.plan[kPlanGrids]) {
             b.ok = 1;
             b.cell0 = row0 * a.n + ax + (int)(gid * a.cells * NP);
             b.ph = (row0 % S) << 16 | (ax % S);
-            b.kb = (int)kbase;
-            if (mirror_reads<DT>()) {
-                // a negative offset reads position S - 1 - j along its axis: the stride turns
-                // negative and the origin moves to S - 1
-                constexpr int esz = (DT == WG_KF32) ? 8 : 4;
-                const int mu = ou < 0 ? -esz : esz, mv = ov < 0 ? -S * esz : S * esz;
-                b.mul = (int)((unsigned)(unsigned short)mu | (unsigned)(unsigned short)mv << 16);
-                b.kb += (ou < 0 ? S - 1 : 0) + (ov < 0 ? (S - 1) * S : 0);
-            }
+            // footprint column j reads row position 1 + j forwards, S - 1 - j backwards (which
+            // holds the column of footprint position j + 1, the load's first sample, and then
+            // that of j); footprint row i reads matrix row i, or S - 1 - i backwards
+            const int mu = ou < 0 ? -esz : esz, rv = ov < 0 ? -W * esz : W * esz;
+            b.mul = (int)((unsigned)(unsigned short)mu | (unsigned)(unsigned short)rv << 16);
+            b.kb = (int)kbase + (ou < 0 ? S - 1 : 1) + (ov < 0 ? (S - 1) * W : 0);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const float2 g = a.gamma[(int64_t)j * NP + p];
@@ -180,12 +177,13 @@ __device__ inline __amdgpu_buffer_rsrc_t table_rsrc(const void *data, int64_t nu
 }
 
 template <int DT>
-__device__ inline typename KRaw<DT>::type buf_load(__amdgpu_buffer_rsrc_t rs, int off) {
+__device__ inline typename PairRaw<DT>::type pair_load(__amdgpu_buffer_rsrc_t rs, int off) {
     if constexpr (DT == WG_KF32) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
-        return make_float2(__int_as_float(v[0]), __int_as_float(v[1]));
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
     } else {
-        return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        return make_uint2((unsigned)v[0], (unsigned)v[1]);
     }
 }
 
@@ -214,44 +212,59 @@ __device__ inline unsigned in_vgpr(unsigned x) {
     return r;
 }
 
-// The same with signed multipliers (v_dot2_i32_i16); positions are below 2^15.
+// Table byte offset of footprint position w = (column, row) with signed strides m and a
+// wave-uniform origin c in a scalar register: w.x * m.x + w.y * m.y + c as one
+// three-operand v_dot2_i32_i16. (From the builtin the compiler selects the two-operand
+// v_dot2c_i32_i16, whose addend is its destination, and copies the scalar into it first:
+// two operations per slot and run instead of one.)
 typedef short i16x2 __attribute__((ext_vector_type(2)));
-__device__ inline i16x2 as_i16x2(unsigned v) { return __builtin_bit_cast(i16x2, v); }
-__device__ inline int sdot2(u16x2 w, i16x2 m, int c) {
-    return __builtin_amdgcn_sdot2(__builtin_bit_cast(i16x2, w), m, c, false);
-}
-
-// The same with a wave-uniform addend in a scalar register, as one three-operand
-// v_dot2_i32_i16. (From the builtin the compiler selects the two-operand v_dot2c_i32_i16,
-// whose addend is its destination, and copies the scalar into it first: two operations per
-// slot and run instead of one.)
-__device__ inline int sdot2_s(u16x2 w, i16x2 m, int c) {
+__device__ inline unsigned table_off(u16x2 w, unsigned m, unsigned c) {
     int r;
-    asm("v_dot2_i32_i16 %0, %1, %2, %3"
-        : "=v"(r)
-        : "v"(__builtin_bit_cast(unsigned, w)), "v"(__builtin_bit_cast(unsigned, m)), "s"(c));
-    return r;
+    asm("v_dot2_i32_i16 %0, %1, %2, %3" : "=v"(r) : "v"(__builtin_bit_cast(unsigned, w)), "v"(m), "s"(c));
+    return (unsigned)r;
 }
 
-// The lane's classes of a chunk: slot m holds class min(c0 + 64 m + lane, c1 - 1) as (q, p).
+// The lane's class pairs of a chunk: slot m holds pair min(k0 + 64 m + lane, k1 - 1), i.e.
+// row p = pair / ((S + 1) / 2) and first column q = 2 (pair mod ((S + 1) / 2)), as (q, p).
+// Bit m of *idle is set when the slot's pair lies past the lane's share (the lane then
+// repeats the last pair and must neither add nor commit); bit m of *single when the pair's
+// second class does not exist (q = S - 1, the last pair of a row).
 template <int NS>
-__device__ inline void lane_classes(int S, int c0, int c1, int lane, u16x2 *cls) {
-    const float rS = 1.0f / (float)S;
+__device__ inline void lane_pairs(int S, int k0, int k1, int lane, u16x2 *cls, unsigned *idle, unsigned *single) {
+    const int hw = (S + 1) >> 1;
+    const float rh = 1.0f / (float)hw;
+    unsigned id = 0, sg = 0;
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
-        const int c = min(c0 + m * kWave + lane, c1 - 1);
-        const int pp = (int)((float)c * rS + 0.5f * rS);
-        cls[m] = u16x2{(unsigned short)(c - pp * S), (unsigned short)pp};
+        const int raw = k0 + m * kWave + lane;
+        const int k = min(raw, k1 - 1);
+        const int pp = (int)((float)k * rh + 0.5f * rh);
+        const int q = 2 * (k - pp * hw);
+        cls[m] = u16x2{(unsigned short)q, (unsigned short)pp};
+        id |= (raw >= k1 ? 1u : 0u) << m;
+        sg |= (q + 1 >= S ? 1u : 0u) << m;
     }
+    *idle = id;
+    *single = sg;
 }
 
-// Samples and cell rows of one run for the lane's slots, fetched one run ahead.
+// Samples and cells of one run for the lane's pair slots, fetched one run ahead.
 template <int DT>
 struct Stage {
-    typename KRaw<DT>::type k[kSlots];
-    int yc[kSlots];  // cells, set only when the footprint moved
-    bool moved;      // wave-uniform: the run's footprint origin differs from the previous run's
+    typename PairRaw<DT>::type k[kPairSlots];
+    unsigned yc[kPairSlots];  // cell of the pair's first class, with kWrapBit when its second
+                              // class wraps to column 0; set only when the footprint moved
+    bool moved;               // wave-uniform: the run's footprint origin differs from the previous run's
+    bool swap;                // wave-uniform: the run reads its matrix backwards along u, so each
+                              // load holds the pair's second sample first
 };
+
+// The cell of the second class of a pair whose first class has footprint position wpos and
+// cell c: the next column, or column 0 when the first class is in column S - 1.
+__device__ inline unsigned second_cell(u16x2 wpos, unsigned c, int S) {
+    return (int)wpos.x == S - 1 ? c - (unsigned)(S - 1) : c + 1u;
+}
+constexpr unsigned kWrapBit = 0x80000000u;  // cells are below 2^31
 
 // Cell base of "no previous run": no footprint starts there (cell bases are below n*n).
 constexpr unsigned kNoCell = 0xFFFFFFFFu;
@@ -296,77 +309,95 @@ __device__ inline void for_each_unit(int nunits, int32_t *q, F &&body) {
 }
 
 template <int DT, int NP, int NS>
-__device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
-                              const int64_t *koff) {
+__device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int S, int k0, int k1, int rb, int re,
+                                                             int lane, const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
-    constexpr int nslots = NS;
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
 
-    // The lane's classes. Every slot but the last is full for every lane; the last one may
-    // be partial.
-    u16x2 cls[kSlots];
-    lane_classes<NS>(S, c0, c1, lane, cls);
-    const bool last_ok = c0 + (nslots - 1) * kWave + lane < c1;
-    // added to the sample offsets of the last slot: lanes without a class there read past
-    // the table's end (the buffer returns zeros; offsets stay below 2^31 bytes)
-    const unsigned idle_off = last_ok ? 0u : 0x80000000u;
+    u16x2 cls[kPairSlots];
+    unsigned idle, single;
+    lane_pairs<NS>(S, k0, k1, lane, cls, &idle, &single);
+    // an idle slot (past the lane's share of pairs) reads past the table's end, which gives
+    // zeros: it adds nothing, and it never commits
+    unsigned idle_off[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) idle_off[m] = ((idle >> m) & 1u) ? 0x80000000u : 0u;
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
-    const u16x2 mul_k = {(unsigned short)esz, (unsigned short)(S * esz)};  // byte offset in a matrix
-    const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};           // cell offset in the grid
-    // per slot and polarisation: Kahan sum and compensation of the owned cell
-    float acc_r[NS][NP], acc_i[NS][NP], cmp_r[NS][NP], cmp_i[NS][NP];
-    int cur[kSlots];  // owned cell (y*n + x); set from the chunk's first run
-    // Footprint positions of the lane's classes, recomputed only when the footprint moves
+    const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};  // cell offset in the grid
+    // per pair slot, class h and polarisation: Kahan sum and compensation of the owned cell
+    float acc_r[NS][2][NP], acc_i[NS][2][NP], cmp_r[NS][2][NP], cmp_i[NS][2][NP];
+    unsigned cur[kPairSlots][2];  // owned cells (y*n + x); set from the chunk's first run
+    // Footprint positions of the lane's first classes, recomputed only when the footprint moves
     // (consecutive runs of a chunk mostly differ in oversampling offsets or plane alone).
-    u16x2 wpos[kSlots];
+    u16x2 wpos[kPairSlots];
     unsigned last_cell0 = kNoCell;
 #pragma unroll
     for (int m = 0; m < NS; ++m)
 #pragma unroll
-        for (int p = 0; p < NP; ++p) acc_r[m][p] = acc_i[m][p] = cmp_r[m][p] = cmp_i[m][p] = 0.f;
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) acc_r[m][h][p] = acc_i[m][h][p] = cmp_r[m][h][p] = cmp_i[m][h][p] = 0.f;
     // Commit the cell's compensated sums (acc - cmp) of every polarisation; the next cell
     // starts from acc = cmp, i.e. from the value zero, with the compensation term left as it
     // is (Kahan's recurrence holds from any starting pair).
-    auto commit = [&](int m) {
-        float *cell = a.grid + 2 * (int64_t)(unsigned)cur[m];
+    //
+    // The cells of slot m whose flag go[h] is set are committed. A lane holds two neighbouring
+    // cells, so one atomic per class would cover every other cell of twice the cache lines;
+    // instead v_permlane32_swap regroups the values first: the upper half of the wave takes
+    // the second classes of the lower half's pairs, the lower half the first classes of the
+    // upper half's, and each atomic instruction then covers the 64 cells of 32 whole pairs.
+    auto commit = [&](int m, const bool go[2]) {
+        const auto c = __builtin_amdgcn_permlane32_swap(cur[m][0], cur[m][1], false, false);
+        const auto f = __builtin_amdgcn_permlane32_swap(go[0] ? 1u : 0u, go[1] ? 1u : 0u, false, false);
+        float vr[2][NP], vi[2][NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            // polarisation planes: neighbouring lanes' cells stay neighbours in memory
-            unsafeAtomicAdd(cell + 2 * p * a.cells, acc_r[m][p] - cmp_r[m][p]);
-            unsafeAtomicAdd(cell + 2 * p * a.cells + 1, acc_i[m][p] - cmp_i[m][p]);
-            acc_r[m][p] = cmp_r[m][p];
-            acc_i[m][p] = cmp_i[m][p];
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc_r[m][0][p] - cmp_r[m][0][p]),
+                                                            __float_as_uint(acc_r[m][1][p] - cmp_r[m][1][p]), false, false);
+            const auto i = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc_i[m][0][p] - cmp_i[m][0][p]),
+                                                            __float_as_uint(acc_i[m][1][p] - cmp_i[m][1][p]), false, false);
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                vr[g][p] = __uint_as_float(r[g]);
+                vi[g][p] = __uint_as_float(i[g]);
+            }
         }
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+            if (f[g]) {
+                float *cell = a.grid + 2 * (int64_t)(unsigned)c[g];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    // polarisation planes: neighbouring lanes' cells stay neighbours in memory
+                    unsafeAtomicAdd(cell + 2 * p * a.cells, vr[g][p]);
+                    unsafeAtomicAdd(cell + 2 * p * a.cells + 1, vi[g][p]);
+                }
+            }
+        // a committed cell's successor starts from acc = cmp
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                acc_r[m][h][p] = go[h] ? cmp_r[m][h][p] : acc_r[m][h][p];
+                acc_i[m][h][p] = go[h] ? cmp_i[m][h][p] : acc_i[m][h][p];
+            }
     };
+    // Commits are only for classes that exist: not in an idle slot, and not the missing
+    // second class of a row's last pair.
+    auto owns = [&](int m, int h) { return ((idle >> m) & 1u) == 0u && (h == 0 || ((single >> m) & 1u) == 0u); };
     bool first = true;
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
         const RunBatch<NP> b = load_batch<DT, NP>(a, S, base + lane, lane < n, koff);
 
-        // the lane's samples of run t (mirrored positions where the run's offsets are negative);
-        // a lane with no class in the last slot reads beyond the table, which gives zeros
-        auto load_samples = [&](int t, unsigned kbB, typename KRaw<DT>::type *k) {
-            if constexpr (mirror_reads<DT>()) {
-                const i16x2 mul = as_i16x2(in_vgpr((unsigned)rl(b.mul, t)));
-#pragma unroll
-                for (int m = 0; m < NS; ++m) {
-                    const unsigned off = (unsigned)sdot2_s(wpos[m], mul, (int)kbB);
-                    k[m] = buf_load<DT>(rs, (int)(m == NS - 1 ? off | idle_off : off));
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < NS; ++m) {
-                    const unsigned off = dot2(wpos[m], mul_k, kbB);
-                    k[m] = buf_load<DT>(rs, (int)(m == NS - 1 ? off | idle_off : off));
-                }
-            }
-        };
-        // cells (when the footprint moved) and samples of the lane's classes for run t
+        // cells (when the footprint moved) and sample pairs of the lane's slots for run t
         auto fetch = [&](int t, Stage<DT> &st) {
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
+            const unsigned mul = (unsigned)rl(b.mul, t);
             const bool ok = rl(b.ok, t) != 0;
+            st.swap = (mul & 0x8000u) != 0u;
             st.moved = !ok || cell0 != last_cell0;
             last_cell0 = (unsigned)uni((int)(ok ? cell0 : kNoCell));
             if (st.moved) {
@@ -374,10 +405,12 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
 #pragma unroll
                 for (int m = 0; m < NS; ++m) {
                     wpos[m] = footprint_pos(cls[m], ph, ss);
-                    st.yc[m] = (int)dot2(wpos[m], mul_c, cell0);
+                    st.yc[m] = dot2(wpos[m], mul_c, cell0) | ((int)wpos[m].x == S - 1 ? kWrapBit : 0u);
                 }
             }
-            load_samples(t, kbB, st.k);
+            const unsigned mulv = in_vgpr(mul);
+#pragma unroll
+            for (int m = 0; m < NS; ++m) st.k[m] = pair_load<DT>(rs, (int)(table_off(wpos[m], mulv, kbB) | idle_off[m]));
         };
         // A run that failed load_batch's checks (and lane n, past a batch of odd length n)
         // carries gamma = 0: its step adds zero, so the loop needs no branch on it. Such a
@@ -391,30 +424,50 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                 gi[p] = rlf(b.gi[p], t);
             }
             // cells that left the footprint are committed under one wave-uniform branch (most
-            // runs keep their footprint); the idle lanes of the last slot never commit
+            // runs keep their footprint)
             if (st.moved) {
 #pragma unroll
                 for (int m = 0; m < NS; ++m) {
-                    if ((m < nslots - 1 || last_ok) && st.yc[m] != cur[m]) commit(m);
-                    cur[m] = st.yc[m];
+                    const unsigned c0 = st.yc[m] & ~kWrapBit;
+                    const unsigned yc[2] = {c0, (st.yc[m] & kWrapBit) ? c0 - (unsigned)(S - 1) : c0 + 1u};
+                    const bool go[2] = {owns(m, 0) && yc[0] != cur[m][0], owns(m, 1) && yc[1] != cur[m][1]};
+                    commit(m, go);
+                    cur[m][0] = yc[0];
+                    cur[m][1] = yc[1];
                 }
             }
             // Kahan step with the product fused into the compensation:
             // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t; one sample serves every
-            // polarisation. The idle lanes of the last slot add zero samples.
+            // polarisation. Class h takes sample h of the load, or sample 1 - h when the run
+            // reads backwards along u (one copy of the sums per case, under a wave-uniform
+            // branch).
+            auto sums = [&](auto swapped) {
+                constexpr int sw = decltype(swapped)::value;
 #pragma unroll
-            for (int m = 0; m < NS; ++m) {
-                const float2 kv = to_float2<DT>(st.k[m]);
+                for (int m = 0; m < NS; ++m)
 #pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    const float yr = fmaf(gr[p], kv.x, -fmaf(gi[p], kv.y, cmp_r[m][p]));
-                    const float yi = fmaf(gr[p], kv.y, fmaf(gi[p], kv.x, -cmp_i[m][p]));
-                    const float tr = acc_r[m][p] + yr, ti = acc_i[m][p] + yi;
-                    cmp_r[m][p] = (tr - acc_r[m][p]) - yr;
-                    cmp_i[m][p] = (ti - acc_i[m][p]) - yi;
-                    acc_r[m][p] = tr;
-                    acc_i[m][p] = ti;
-                }
+                    for (int h = 0; h < 2; ++h) {
+                        const float2 kv = pair_sample<DT>(st.k[m], h ^ sw);
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) {
+                            const float yr = fmaf(gr[p], kv.x, -fmaf(gi[p], kv.y, cmp_r[m][h][p]));
+                            const float yi = fmaf(gr[p], kv.y, fmaf(gi[p], kv.x, -cmp_i[m][h][p]));
+                            const float tr = acc_r[m][h][p] + yr, ti = acc_i[m][h][p] + yi;
+                            cmp_r[m][h][p] = (tr - acc_r[m][h][p]) - yr;
+                            cmp_i[m][h][p] = (ti - acc_i[m][h][p]) - yi;
+                            acc_r[m][h][p] = tr;
+                            acc_i[m][h][p] = ti;
+                        }
+                    }
+            };
+            // (the two markers differ, so the compiler cannot merge the copies into one with
+            // selects on every sample)
+            if (st.swap) {
+                sums(std::integral_constant<int, 1>{});
+                asm volatile("; samples swapped");
+            } else {
+                sums(std::integral_constant<int, 0>{});
+                asm volatile("; samples in order");
             }
         };
 
@@ -422,7 +475,11 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
         fetch(0, sa);
         if (first) {
 #pragma unroll
-            for (int m = 0; m < NS; ++m) cur[m] = sa.yc[m];
+            for (int m = 0; m < NS; ++m) {
+                const unsigned c0 = sa.yc[m] & ~kWrapBit;
+                cur[m][0] = c0;
+                cur[m][1] = (sa.yc[m] & kWrapBit) ? c0 - (unsigned)(S - 1) : c0 + 1u;
+            }
             first = false;
         }
         // The next run's fetch is issued on every path (past the batch's end it repeats the
@@ -430,26 +487,33 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
         // leave that prefetch in flight; a fetch skipped on some path would make them wait
         // for every outstanding load. With n odd, step t + 1 = n repeats run n - 1's
         // footprint with lane n's zero gamma.
+        // (the scheduling barriers keep each fetch ahead of the sums it overlaps)
         for (int t = 0; t < n; t += 2) {
             fetch(min(t + 1, n - 1), sb);
+            __builtin_amdgcn_sched_barrier(0);
             accumulate(t, sa);
             fetch(min(t + 2, n - 1), sa);
+            __builtin_amdgcn_sched_barrier(0);
             accumulate(t + 1, sb);
         }
     }
+    if (!first) {
 #pragma unroll
-    for (int m = 0; m < NS; ++m)
-        if (!first && (m < nslots - 1 || last_ok)) commit(m);
+        for (int m = 0; m < NS; ++m) {
+            const bool go[2] = {owns(m, 0), owns(m, 1)};
+            commit(m, go);
+        }
+    }
 }
 
-// Classes [c0, c1) of a support-S chunk, split evenly over the chunk's waves; the slot
+// Class pairs [k0, k1) of a support-S chunk, split evenly over the chunk's waves; the slot
 // count per lane is a template parameter so the unrolled slot loops carry no guards.
-__device__ inline void chunk_classes(int S, int chunk, int slots, int &c0, int &c1, int &ns) {
-    const int S2 = S * S, nch = nchunk_of(S, slots);
-    const int cpc = (S2 + nch - 1) / nch;
-    c0 = chunk * cpc;
-    c1 = min(S2, c0 + cpc);
-    ns = uni((c1 - c0 + kWave - 1) / kWave);
+__device__ inline void chunk_pairs(int S, int chunk, int slots, int &k0, int &k1, int &ns) {
+    const int np = npairs(S), nch = nchunk_pairs(S, slots);
+    const int ppc = (np + nch - 1) / nch;
+    k0 = chunk * ppc;
+    k1 = min(np, k0 + ppc);
+    ns = uni((k1 - k0 + kWave - 1) / kWave);
 }
 
 // Slot count as a template parameter, instantiated for 1..MAX only (the kernel's register
@@ -468,18 +532,18 @@ __device__ __attribute__((always_inline)) inline void grid_dispatch(int ns, cons
     }
 }
 
-// Most classes per lane of the gridder: 8 with FP32 tables, 6 with 16-bit tables, for one
-// polarisation; the accumulators of more polarisations take the registers of more slots.
+// Most class pairs per lane of the gridder; the accumulators of more polarisations take the
+// registers of more pairs.
 template <int DT, int NP>
 constexpr int grid_slots() {
-    return NP == 4 ? kSlotsPol4 : NP == 2 ? kSlotsPol2 : DT == WG_KF32 ? kSlots : kSlotsNarrow;
+    return NP == 4 ? kGridPairsPol4 : NP == 2 ? kGridPairsPol2 : DT == WG_KF32 ? kGridPairs : kGridPairsNarrow;
 }
 
 template <int DT, int NP>
 __device__ __attribute__((always_inline)) void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
-    int c0, c1, ns;
-    chunk_classes(S, chunk, grid_slots<DT, NP>(), c0, c1, ns);
-    grid_dispatch<DT, NP, 1, grid_slots<DT, NP>()>(ns, a, S, c0, c1, rb, re, lane, koff);
+    int k0, k1, ns;
+    chunk_pairs(S, chunk, grid_slots<DT, NP>(), k0, k1, ns);
+    grid_dispatch<DT, NP, 1, grid_slots<DT, NP>()>(ns, a, S, k0, k1, rb, re, lane, koff);
 }
 
 // COUNTER: the work list is walked through the counter in a.queue, else statically (one
@@ -496,7 +560,7 @@ __global__ __launch_bounds__(256, 4) void k_grid(GArgs a) {
     auto unit = [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_of(S, grid_slots<DT, NP>());
+        const int S = uni(ut.S[m]), nch = nchunk_pairs(S, grid_slots<DT, NP>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;
@@ -530,20 +594,21 @@ __device__ inline float wave_total_pair(float re, float im) {
     return v;
 }
 
-// Adjoint, with the gridder's decomposition: a wave owns the same cell classes of a local
-// chunk, keeps the grid value of each owned cell in a register and reloads the values only
-// when the footprint moves (about one run in seven), and forms per run the partial dot
+// Adjoint, with the gridder's decomposition: a wave owns the same cell class pairs of a
+// local chunk, keeps the grid value of each owned cell in a register and reloads the values
+// only when the footprint moves (about one run in seven), and forms per run the partial dot
 // product of conj(K) with those values (a short FMA chain per lane, then one lane-swap and
 // DPP tree over the wave for the real and imaginary parts together). The waves sharing a
 // chunk add their partial sums into work[run]; k_degrid_finish hands d to the run's records.
-static_assert(kDegridSlots <= kSlots && kDegridSlotsNarrow <= kSlots && kDegridSlotsPol2 <= kSlots &&
-                  kDegridSlotsPol4 <= kSlots && kSlotsNarrow <= kSlots && kSlotsPol2 <= kSlots &&
-                  kSlotsPol4 <= kSlots,
-              "per-lane stage arrays hold kSlots classes");
+static_assert(kGridPairs <= kPairSlots && kGridPairsNarrow <= kPairSlots && kGridPairsPol2 <= kPairSlots &&
+                  kGridPairsPol4 <= kPairSlots && kDegridPairs <= kPairSlots && kDegridPairsNarrow <= kPairSlots &&
+                  kDegridPairsPol2 <= kPairSlots && kDegridPairsPol4 <= kPairSlots,
+              "per-lane stage arrays hold kPairSlots pairs");
 template <int DT>
 struct DStage {
-    typename KRaw<DT>::type k[kSlots];
+    typename PairRaw<DT>::type k[kPairSlots];
     bool moved;  // wave-uniform: the run's footprint origin differs from the previous run's
+    bool swap;   // wave-uniform: the loads hold each pair's second sample first
 };
 
 // The NP complex values of one cell, one from each polarisation plane ([NP][n][n] grid).
@@ -553,59 +618,48 @@ __device__ inline void load_cell(const float2 *grid, unsigned cell, int64_t cell
     for (int p = 0; p < NP; ++p) v[p] = grid[cell + p * cells];
 }
 
-// Order of the loads per run t: the samples of run t + 1 are issued before run t's sums, and
-// when run t + 1 moves the footprint its grid values are loaded into the owned-cell registers
-// right after run t's last use of them. The wait before run t + 1's sums then covers those
-// grid values and run t + 1's samples while run t + 2's samples stay in flight, whichever path
-// was taken.
+// Order of the loads per run t: the sample pairs of run t + 1 are issued before run t's sums,
+// and when run t + 1 moves the footprint its grid values are loaded into the owned-cell
+// registers right after run t's last use of them. The wait before run t + 1's sums then
+// covers those grid values and run t + 1's samples while run t + 2's samples stay in flight,
+// whichever path was taken.
 template <int DT, int NP, int NS>
-__device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, int S, int c0, int c1, int rb,
+__device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, int S, int k0, int k1, int rb,
                                                                int re, int lane, const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
     const float2 *grid = (const float2 *)a.grid;
-    u16x2 cls[kSlots];
-    lane_classes<NS>(S, c0, c1, lane, cls);
-    const bool last_ok = c0 + (NS - 1) * kWave + lane < c1;
-    // lanes without a class in the last slot read their samples past the table's end (zeros)
-    const unsigned idle_off = last_ok ? 0u : 0x80000000u;
+    u16x2 cls[kPairSlots];
+    unsigned idle, single;
+    lane_pairs<NS>(S, k0, k1, lane, cls, &idle, &single);
+    // idle slots read their samples past the table's end (zeros)
+    unsigned idle_off[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) idle_off[m] = ((idle >> m) & 1u) ? 0x80000000u : 0u;
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
-    const u16x2 mul_k = as_u16x2(in_vgpr((unsigned)(S * esz) << 16 | (unsigned)esz));
     const u16x2 mul_c = as_u16x2(in_vgpr((unsigned)a.n << 16 | 1u));
-    float2 gv[NS][NP];       // grid values of the owned cells
-    u16x2 wpos[kSlots];      // footprint positions, recomputed only when the footprint moves
-    unsigned gcell[kSlots];  // owned cells of the last run that moved the footprint
+    float2 gv[NS][2][NP];       // grid values of the owned cells (0 for a missing second class)
+    u16x2 wpos[kPairSlots];     // footprint positions of the first classes, when the footprint moves
+    unsigned gcell[kPairSlots]; // first class's cell of the last run that moved the footprint
     unsigned last_cell0 = kNoCell;
 #pragma unroll
     for (int m = 0; m < NS; ++m)
 #pragma unroll
-        for (int p = 0; p < NP; ++p) gv[m][p] = make_float2(0.f, 0.f);
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) gv[m][h][p] = make_float2(0.f, 0.f);
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
         const RunBatch<NP> b = load_batch<DT, NP>(a, S, base + lane, lane < n, koff);
 
-        auto load_samples = [&](int t, unsigned kbB, typename KRaw<DT>::type *k) {
-            if constexpr (mirror_reads<DT>()) {
-                const i16x2 mul = as_i16x2(in_vgpr((unsigned)rl(b.mul, t)));
-#pragma unroll
-                for (int m = 0; m < NS; ++m) {
-                    const unsigned off = (unsigned)sdot2_s(wpos[m], mul, (int)kbB);
-                    k[m] = buf_load<DT>(rs, (int)(m == NS - 1 ? off | idle_off : off));
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < NS; ++m) {
-                    const unsigned off = dot2(wpos[m], mul_k, kbB);
-                    k[m] = buf_load<DT>(rs, (int)(m == NS - 1 ? off | idle_off : off));
-                }
-            }
-        };
-        // footprint positions and cells (when the footprint moved) and samples of run t
+        // footprint positions and cells (when the footprint moved) and sample pairs of run t
         auto fetch = [&](int t, DStage<DT> &st) {
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
+            const unsigned mul = (unsigned)rl(b.mul, t);
             const bool ok = rl(b.ok, t) != 0;
+            st.swap = (mul & 0x8000u) != 0u;
             st.moved = !ok || cell0 != last_cell0;
             last_cell0 = (unsigned)uni((int)(ok ? cell0 : kNoCell));
             if (st.moved) {
@@ -616,11 +670,18 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
                     gcell[m] = dot2(wpos[m], mul_c, cell0);
                 }
             }
-            load_samples(t, kbB, st.k);
+            const unsigned mulv = in_vgpr(mul);
+#pragma unroll
+            for (int m = 0; m < NS; ++m) st.k[m] = pair_load<DT>(rs, (int)(table_off(wpos[m], mulv, kbB) | idle_off[m]));
         };
+        // the grid values of the owned cells of the last run that moved the footprint; a
+        // missing second class keeps the value 0
         auto load_values = [&]() {
 #pragma unroll
-            for (int m = 0; m < NS; ++m) load_cell<NP>(grid, gcell[m], a.cells, gv[m]);
+            for (int m = 0; m < NS; ++m) {
+                load_cell<NP>(grid, gcell[m], a.cells, gv[m][0]);
+                if (((single >> m) & 1u) == 0u) load_cell<NP>(grid, second_cell(wpos[m], gcell[m], S), a.cells, gv[m][1]);
+            }
         };
         // this wave's sums: lane l holds component l >> 5 (0 real, 1 imaginary) of run
         // base + (l & 31) in lo and of run base + 32 + (l & 31) in hi
@@ -631,14 +692,27 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
             float pr[NP], pim[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) pr[p] = pim[p] = 0.f;
+            // class h takes sample h of the load, or 1 - h when the run reads backwards along u
+            auto sums = [&](auto swapped) {
+                constexpr int sw = decltype(swapped)::value;
 #pragma unroll
-            for (int m = 0; m < NS; ++m) {
-                const float2 kv = to_float2<DT>(st.k[m]);
+                for (int m = 0; m < NS; ++m)
 #pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    pr[p] = fmaf(kv.x, gv[m][p].x, fmaf(kv.y, gv[m][p].y, pr[p]));
-                    pim[p] = fmaf(kv.x, gv[m][p].y, fmaf(-kv.y, gv[m][p].x, pim[p]));
-                }
+                    for (int h = 0; h < 2; ++h) {
+                        const float2 kv = pair_sample<DT>(st.k[m], h ^ sw);
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) {
+                            pr[p] = fmaf(kv.x, gv[m][h][p].x, fmaf(kv.y, gv[m][h][p].y, pr[p]));
+                            pim[p] = fmaf(kv.x, gv[m][h][p].y, fmaf(-kv.y, gv[m][h][p].x, pim[p]));
+                        }
+                    }
+            };
+            if (st.swap) {
+                sums(std::integral_constant<int, 1>{});
+                asm volatile("; samples swapped");
+            } else {
+                sums(std::integral_constant<int, 0>{});
+                asm volatile("; samples in order");
             }
             // the wave's sums for run t wait in lanes (t & 31) and 32 + (t & 31); two atomics
             // per polarisation and batch add them all
@@ -693,14 +767,14 @@ __device__ inline void degrid_dispatch(int ns, const GArgs &a, int S, int c0, in
 
 template <int DT, int NP>
 constexpr int degrid_slots() {
-    return NP == 4 ? kDegridSlotsPol4 : NP == 2 ? kDegridSlotsPol2 : DT == WG_KF32 ? kDegridSlots : kDegridSlotsNarrow;
+    return NP == 4 ? kDegridPairsPol4 : NP == 2 ? kDegridPairsPol2 : DT == WG_KF32 ? kDegridPairs : kDegridPairsNarrow;
 }
 
 template <int DT, int NP>
 __device__ void degrid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
-    int c0, c1, ns;
-    chunk_classes(S, chunk, degrid_slots<DT, NP>(), c0, c1, ns);
-    degrid_dispatch<DT, NP, 1, degrid_slots<DT, NP>()>(ns, a, S, c0, c1, rb, re, lane, koff);
+    int k0, k1, ns;
+    chunk_pairs(S, chunk, degrid_slots<DT, NP>(), k0, k1, ns);
+    degrid_dispatch<DT, NP, 1, degrid_slots<DT, NP>()>(ns, a, S, k0, k1, rb, re, lane, koff);
 }
 
 template <int DT, int NP>
@@ -715,7 +789,7 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     for_each_unit(nunits, a.queue, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_of(S, degrid_slots<DT, NP>());
+        const int S = uni(ut.S[m]), nch = nchunk_pairs(S, degrid_slots<DT, NP>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;

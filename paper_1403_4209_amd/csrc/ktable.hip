@@ -337,7 +337,7 @@ __global__ void k_supports(BuildArgs a, int s_lo, int s_hi, int32_t *support, in
         const int S = min(s_hi, max(snat, law));
         support[k] = S;
         offset[k] = acc;
-        acc += (int64_t)a.beta * a.beta * S * S;
+        acc += (int64_t)a.beta * a.beta * S * (S + 2);
     }
     offset[a.n_w] = acc;
 }
@@ -375,27 +375,32 @@ __global__ void k_slices(BuildArgs a, const int32_t *__restrict__ support,
     const int sigma = blockIdx.x, k = blockIdx.y;
     const int beta = a.beta;
     const int ov = sigma / beta - beta / 2 + 1, ou = sigma % beta - beta / 2 + 1;
-    const int S = support[k], H = (S - 1) / 2;
-    const int64_t base = offset[k] + (int64_t)sigma * S * S;
+    const int S = support[k], H = (S - 1) / 2, W = S + 2;
+    const int64_t base = offset[k] + (int64_t)sigma * S * W;
     double acc = 0.0;
-    for (int e = threadIdx.x; e < S * S; e += blockDim.x) {
-        const int i = e / S, j = e - (e / S) * S;
+    // rows of S + 2 values: column j of the matrix at position 1 + j, with column S - 1
+    // repeated before the row and column 0 after it, so that two neighbouring columns of a
+    // row, read forwards or (for a mirrored matrix) backwards, are adjacent also where they
+    // wrap; zeta sums the S columns once
+    for (int e = threadIdx.x; e < S * W; e += blockDim.x) {
+        const int i = e / W, jw = e - (e / W) * W, j = jw == 0 ? S - 1 : jw == S + 1 ? 0 : jw - 1;
+        const bool counted = jw >= 1 && jw <= S;
         const int fv = (i - H) * beta - ov, fu = (j - H) * beta - ou;
         const double2 v = a.win[((size_t)k * a.W + (fv + a.Wf)) * a.W + (fu + a.Wf)];
         if (a.dtype == WG_KF32) {
             const float2 f = make_float2((float)v.x, (float)v.y);
             ((float2 *)data)[base + e] = f;
-            acc += (double)f.x;
+            if (counted) acc += (double)f.x;
         } else if (a.dtype == WG_KBF16) {
             double rr, ri;
             const uint32_t lo = to_bf16_bits(v.x, &rr), hi = to_bf16_bits(v.y, &ri);
             ((uint32_t *)data)[base + e] = lo | (hi << 16);
-            acc += rr;
+            if (counted) acc += rr;
         } else {
             double rr, ri;
             const uint32_t lo = to_f16_bits(v.x, &rr), hi = to_f16_bits(v.y, &ri);
             ((uint32_t *)data)[base + e] = lo | (hi << 16);
-            acc += rr;
+            if (counted) acc += rr;
         }
     }
     red[threadIdx.x] = acc;
@@ -464,7 +469,7 @@ extern "C" int wg_ktable_sizes(const wg_geom *g, int64_t *data_elems_max, size_t
     int st = wg::check_geom(g);
     if (st != WG_OK) return st;
     if (!data_elems_max || !ws_bytes) return WG_EINVAL;
-    *data_elems_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * g->s_hi;
+    *data_elems_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * (g->s_hi + 2);
     *ws_bytes = wg::ws_layout(g).total;
     return WG_OK;
 }
@@ -516,7 +521,7 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
 
     // With room for every plane at s_hi and no host copies requested, nothing waits: the
     // matrices are cut on the device right away and s_max reports the upper bound s_hi.
-    const int64_t cap_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * g->s_hi;
+    const int64_t cap_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * (g->s_hi + 2);
     const bool sync = support_out || offset_out || kt->data_cap < cap_max;
     if (sync) {
         std::vector<int32_t> sup(g->n_w);

@@ -10,14 +10,19 @@ namespace wg {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxS = WG_MAX_SUPPORT;
-constexpr int kSlots = 7;          // most cell classes per lane in the gridder (120 VGPRs; 8 measure alike with 5 spilled)
-constexpr int kSlotsNarrow = 6;    // the same with BF16/FP16 tables (measured faster there)
-constexpr int kDegridSlots = 7;    // the same for the degridder (FP32 tables: 3.06 ms, 3.14 with 5)
-constexpr int kDegridSlotsNarrow = 6;  // with BF16/FP16 tables (2.51 ms, 2.57 with 5)
-constexpr int kSlotsPol2 = 5;      // gridder with two polarisations (any table type)
-constexpr int kSlotsPol4 = 3;      // gridder with four polarisations (2 to 5 measured alike)
-constexpr int kDegridSlotsPol2 = 5;  // degridder with two polarisations (4.33 vs 4.61 ms with 4)
-constexpr int kDegridSlotsPol4 = 3;  // with four (9.55 vs 11.65 ms with 2, 20.8 with 1)
+// Class pairs per lane (each pair is two cell classes fetched with one load; the last pair
+// of a footprint row has one class): the largest count any kernel instantiation uses, and
+// the counts per kernel, table type and polarisation count.
+constexpr int kPairSlots = 5;
+constexpr int kGridPairs = 3;          // gridder, FP32 tables, one polarisation (4 spill at 128 VGPRs)
+constexpr int kGridPairsNarrow = 3;    // the same with BF16/FP16 tables (4 spill)
+constexpr int kGridPairsPol2 = 2;      // gridder with two polarisations (any table type; 3 spill)
+constexpr int kGridPairsPol4 = 1;      // gridder with four polarisations (2 spill)
+constexpr int kDegridPairs = 3;        // degridder, FP32 tables, one polarisation (7.8 ms on the
+                                       // 4096^2 workload, 8.0 with 4 and 8.1 with 5)
+constexpr int kDegridPairsNarrow = 5;  // the same with BF16/FP16 tables (6.7 ms, 6.8 with 4, 7.0 with 3)
+constexpr int kDegridPairsPol2 = 3;    // degridder with two polarisations (4 measure alike)
+constexpr int kDegridPairsPol4 = 3;    // degridder with four polarisations (5.5 ms on 2048^2, 5.65 with 2)
 
 // ---------------------------------------------------------------------------------------
 // Plan layout (int32 words). Items are local chunks (first run, one past last run) of
@@ -47,10 +52,12 @@ inline int64_t plan_segcnt_at(int64_t capacity) { return kPlanHdr + 2 * capacity
 inline int64_t plan_tiles_at(int64_t capacity, int64_t n_seg) { return plan_segcnt_at(capacity) + n_seg + 1; }
 inline int64_t n_scan_tiles(int64_t n_seg) { return (n_seg + kScanTile - 1) / kScanTile; }
 
-// Decomposition of a support-S local chunk into waves: the S*S cell classes (y mod S,
-// x mod S) are numbered c = p*S + q and spread evenly over nchunk_of(S, slots) waves, at most
-// `slots` classes per lane.
-__host__ __device__ inline int nchunk_of(int S, int slots) { return (S * S + kWave * slots - 1) / (kWave * slots); }
+// Decomposition of a support-S local chunk into waves: the cell classes (y mod S, x mod S)
+// of footprint row p are paired as (q, q + 1) for q = 0, 2, ..., S - 1 (the last pair has no
+// second class), S (S + 1) / 2 pairs in all, numbered row by row and spread evenly over
+// nchunk_pairs(S, slots) waves, at most `slots` pairs per lane.
+__host__ __device__ inline int npairs(int S) { return S * (S + 1) / 2; }
+__host__ __device__ inline int nchunk_pairs(int S, int slots) { return (npairs(S) + kWave * slots - 1) / (kWave * slots); }
 
 // Status helpers
 #define WG_HIP_CHECK(expr)                                   \

@@ -277,7 +277,9 @@ class KernelTable:
         del ws
 
     def data_complex(self) -> torch.Tensor:
-        """The table samples as complex64 (upcast from bf16/f16), shape [offset[-1]]."""
+        """The table samples as complex64 (upcast from bf16/f16), shape [offset[-1]], in the
+        library's layout: per plane beta^2 matrices of S rows of S + 2 samples, matrix column
+        j at row position 1 + j, position 0 repeating column S - 1 and position S + 1 column 0."""
         n = self.offset[-1]
         if self.dtype == "f32":
             return torch.view_as_complex(self.data_d[: 8 * n].view(torch.float32).view(n, 2))

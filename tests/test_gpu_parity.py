@@ -59,6 +59,27 @@ class Err(float):
         return f"L2 {format(self.l2, spec)} max-abs {format(self.maxabs, spec)}"
 
 
+def unpad_table(tb, beta):
+    """The library's table in the oracle's layout: its matrices have rows of S + 2 values,
+    matrix column j at position 1 + j, position 0 repeating column S - 1 and position S + 1
+    column 0 (so two neighbouring columns are one load, forwards or backwards, also where they
+    wrap). Checks that layout (offsets from the supports, every repeated value equal bit for
+    bit) and returns the S x S matrices back to back, with their offsets."""
+    data = tb.data_complex().cpu().numpy().astype(np.complex128)
+    sup = [int(v) for v in tb.support]
+    off_pad, off = [0], [0]
+    for S in sup:
+        off_pad.append(off_pad[-1] + beta * beta * S * (S + 2))
+        off.append(off[-1] + beta * beta * S * S)
+    assert list(tb.offset) == off_pad
+    planes = []
+    for k, S in enumerate(sup):
+        m = data[off_pad[k]:off_pad[k + 1]].reshape(beta * beta, S, S + 2)
+        assert np.array_equal(m[:, :, 0], m[:, :, S]) and np.array_equal(m[:, :, S + 1], m[:, :, 1])
+        planes.append(m[:, :, 1:S + 1].reshape(-1))
+    return np.concatenate(planes), off
+
+
 def rel_l2(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
@@ -129,8 +150,8 @@ def test_table_parity(case, dtype):
     ref = otable(geom, dtype)
     ref64 = otable(geom, "f64")
     assert list(tb.support) == [int(s) for s in ref["support"]]
-    assert list(tb.offset) == [int(o) for o in ref["offset"]]
-    got = tb.data_complex().cpu().numpy().astype(np.complex128)
+    got, off = unpad_table(tb, geom["beta"])
+    assert off == [int(o) for o in ref["offset"]]
     exp = ref["data"]
     ulp = {"f32": 2.0 ** -23, "bf16": 2.0 ** -7, "f16": 2.0 ** -10}[dtype]
     sub = 2.0 ** -24 if dtype == "f16" else 0.0       # f16 subnormal spacing
@@ -162,8 +183,8 @@ def test_table_with_200_planes():
     tb = wg.KernelTable(g, "f32", device=DEV)
     ref = otable(geom, "f32")
     assert list(tb.support) == [int(s) for s in ref["support"]]
-    assert list(tb.offset) == [int(o) for o in ref["offset"]]
-    got = tb.data_complex().cpu().numpy().astype(np.complex128)
+    got, off = unpad_table(tb, geom["beta"])
+    assert off == [int(o) for o in ref["offset"]]
     for part in (np.real, np.imag):
         d = np.abs(part(got) - part(ref["data"]))
         assert np.all(d <= 2.0 ** -23 * np.abs(part(ref["data"])) + 1e-13)
@@ -184,8 +205,10 @@ def test_table_async_build_matches_oracle():
     assert tb.kt.s_max == geom["s_hi"]
     ref = otable(geom, "f32")
     assert np.array_equal(tb.support_d.cpu().numpy(), ref["support"])
-    assert np.array_equal(tb.offset_d.cpu().numpy(), ref["offset"])
-    got = tb.data_complex().cpu().numpy().astype(np.complex128)
+    tb.support = [int(v) for v in tb.support_d.cpu().numpy()]
+    tb.offset = [int(v) for v in tb.offset_d.cpu().numpy()]
+    got, off = unpad_table(tb, geom["beta"])
+    assert off == [int(o) for o in ref["offset"]]
     assert np.all(np.abs(got - ref["data"]) <= 2.0 ** -23 * np.abs(ref["data"]) + 1e-13)
 
 
@@ -230,7 +253,7 @@ def test_compressed_grid_matches_uncompressed_gpu():
 
 
 # -------------------------------------------------------------------------- degridding
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 3e-3)])
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 3e-3), ("f16", 1e-3)])
 @pytest.mark.parametrize("case", ["cfg1", "cfg4"])
 def test_degrid_parity(case, dtype, tol):
     geom, data = cfg1() if case == "cfg1" else cfg4_small()
@@ -453,7 +476,7 @@ def test_golden_index_ties_through_wg_compress():
     s_max = max(geom["support"])
     off_h = [0]
     for S in geom["support"]:
-        off_h.append(off_h[-1] + geom["beta"] ** 2 * S * S)
+        off_h.append(off_h[-1] + geom["beta"] ** 2 * S * (S + 2))
     off = torch.tensor(off_h, dtype=torch.int64, device=DEV)
     wb = torch.as_tensor(okt.w_bounds(n_w, geom["w_max"])).to(DEV)
     zeta = torch.zeros(n_w * geom["beta"] ** 2, dtype=torch.float64, device=DEV)
@@ -1053,22 +1076,27 @@ def test_failed_runs_interleaved_with_good_ones():
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 @pytest.mark.parametrize("case", ["cfg1", "cfg4"])
-def test_fp32_table_is_even_in_each_offset(case):
-    """The FP32 gridder and degridder read only slices of non-negative oversample offsets,
-    mirrored where a run's offset is negative. That rests on the kernel being even in u and
-    in v (eq. C_W with an even taper and w-screen): on the built table, the matrix of offset
-    -o along an axis equals the matrix of +o reversed along that axis, to FP32 rounding of
-    the two transform outputs (1e-6 of the plane's largest sample)."""
+def test_table_is_even_in_each_offset(case, dtype):
+    """The kernel is even in u and in v (eq. C_W with an even taper and w-screen): on the
+    built table, the matrix of offset -o along an axis equals the matrix of +o reversed along
+    that axis (which the gridder and degridder read in its place). With FP32 storage the two
+    agree to FP32 rounding of the two transform outputs (1e-6 of the plane's largest sample);
+    a 16-bit element is the same rounding of two FP64 values that agree to about 1e-12, so it
+    is equal or one unit in the last place apart."""
     geom = cfg1()[0] if case == "cfg1" else cfg4_small()[0]
     g = wg.geom_from_dict(geom)
-    tb = wg.KernelTable(g, "f32", device=DEV)
-    data = tb.data_complex().cpu().numpy()
+    tb = wg.KernelTable(g, dtype, device=DEV)
     beta, hb = geom["beta"], geom["beta"] // 2
-    worst = 0.0
+    data, off = unpad_table(tb, beta)
+    ulp = {"f32": 0.0, "bf16": 2.0 ** -7, "f16": 2.0 ** -10}[dtype]
+    sub = 2.0 ** -24 if dtype == "f16" else 0.0
+    worst = worst_ulp = 0.0
+    differ = total = 0
     for k in range(geom["n_w"]):
         S = tb.support[k]
-        plane = data[tb.offset[k]:tb.offset[k + 1]].reshape(beta, beta, S, S)   # [ov][ou][i][j]
+        plane = data[off[k]:off[k + 1]].reshape(beta, beta, S, S)   # [ov][ou][i][j]
         peak = np.max(np.abs(plane))
         for ov in range(-hb + 1, hb + 1):
             for ou in range(-hb + 1, hb + 1):
@@ -1079,8 +1107,18 @@ def test_fp32_table_is_even_in_each_offset(case):
                 if ov < 0:
                     src = src[::-1, :]
                 worst = max(worst, float(np.max(np.abs(m - src))) / peak)
-    say(f"  {case}: largest mirror difference {worst:.2e} of the plane peak")
-    assert worst < 1e-6
+                if ulp:
+                    for a, b in ((m.real, src.real), (m.imag, src.imag)):
+                        d = np.abs(a - b)
+                        worst_ulp = max(worst_ulp, float(np.max(d / (ulp * np.abs(b) + sub + 1e-30 * peak))))
+                        differ += int(np.count_nonzero(d))
+                        total += d.size
+    say(f"  {case} {dtype}: largest mirror difference {worst:.2e} of the plane peak"
+        + (f", {worst_ulp:.2f} units in the last place, {differ} of {total} components differ" if ulp else ""))
+    if dtype == "f32":
+        assert worst < 1e-6
+    else:
+        assert worst_ulp <= 1.0 + 1e-9
 
 
 @pytest.mark.parametrize("case", ["cfg1", "cfg4"])
