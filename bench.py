@@ -45,6 +45,9 @@ def parse():
                     help="time the headline step only (no table study, table types, other workloads or modes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (to scale HBM counters)")
+    ap.add_argument("--profile-workload", type=int, default=0, choices=(0, 2, 3, 5), metavar="CFG",
+                    help="only run WARMUP + STEPS full steps of workload CFG (2, 3 or 5) and print their "
+                         "phase times, for profiler runs")
     return ap.parse_args()
 
 
@@ -276,6 +279,15 @@ def main():
     from paper_1403_4209_amd import wgrid as wg
 
     dev = torch.device("cuda:0")
+    if args.profile_workload:
+        w = workloads.make(args.profile_workload, device=dev)
+        c = Case(w)
+        ms_step, ph = c.time_steps(args.steps, args.warmup)
+        st = c.gridder.runs.stats()
+        print(json.dumps({"workload": args.profile_workload, "records": int(st.n_records), "runs": int(st.n_runs),
+                          "upd_real": int(st.upd_real), "ms_per_step": round(ms_step, 3),
+                          "phases_ms": phases_dict(ph)}), flush=True)
+        return
     w = workloads.make(3, device=dev)
     c = Case(w)
     ms_step, ph = c.time_steps(args.steps, args.warmup)
