@@ -308,6 +308,13 @@ __device__ inline void for_each_unit(int nunits, int32_t *q, F &&body) {
     }
 }
 
+// Per wave (four per workgroup): the commit list of one footprint move, as arrays of cells
+// and of the real and imaginary values per polarisation. Sized for the largest
+// instantiation: 2 classes x 3 pairs x 64 lanes entries of 3 words (one polarisation), or
+// fewer pairs with more polarisations.
+constexpr int kCommitMax = 2 * 3 * 64;
+__shared__ float g_commit[4][kCommitMax * 5];
+
 template <int DT, int NP, int NS>
 __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int S, int k0, int k1, int rb, int re,
                                                              int lane, const int64_t *koff) {
@@ -341,46 +348,49 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
     // starts from acc = cmp, i.e. from the value zero, with the compensation term left as it
     // is (Kahan's recurrence holds from any starting pair).
     //
-    // The cells of slot m whose flag go[h] is set are committed. A lane holds two neighbouring
-    // cells, so one atomic per class would cover every other cell of twice the cache lines;
-    // instead v_permlane32_swap regroups the values first: the upper half of the wave takes
-    // the second classes of the lower half's pairs, the lower half the first classes of the
-    // upper half's, and each atomic instruction then covers the 64 cells of 32 whole pairs.
-    auto commit = [&](int m, const bool go[2]) {
-        const auto c = __builtin_amdgcn_permlane32_swap(cur[m][0], cur[m][1], false, false);
-        const auto f = __builtin_amdgcn_permlane32_swap(go[0] ? 1u : 0u, go[1] ? 1u : 0u, false, false);
-        float vr[2][NP], vi[2][NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc_r[m][0][p] - cmp_r[m][0][p]),
-                                                            __float_as_uint(acc_r[m][1][p] - cmp_r[m][1][p]), false, false);
-            const auto i = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc_i[m][0][p] - cmp_i[m][0][p]),
-                                                            __float_as_uint(acc_i[m][1][p] - cmp_i[m][1][p]), false, false);
-#pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                vr[g][p] = __uint_as_float(r[g]);
-                vi[g][p] = __uint_as_float(i[g]);
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < 2; ++g)
-            if (f[g]) {
-                float *cell = a.grid + 2 * (int64_t)(unsigned)c[g];
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    // polarisation planes: neighbouring lanes' cells stay neighbours in memory
-                    unsafeAtomicAdd(cell + 2 * p * a.cells, vr[g][p]);
-                    unsafeAtomicAdd(cell + 2 * p * a.cells + 1, vi[g][p]);
-                }
-            }
-        // a committed cell's successor starts from acc = cmp
+    // Commits are compacted. When the footprint moves, each (slot, class) of the wave whose
+    // cell leaves writes that cell and its values to the wave's list in LDS (its place from
+    // two ballots and mbcnt, so the list runs lane by lane, first class before second: a row
+    // of leaving cells stays a run of neighbouring cells, whereas one atomic per slot and
+    // class would cover every other cell), and the list is then added to the grid 64 entries
+    // per atomic instruction. Most moves commit one column of the footprint, a few lanes per
+    // slot: issued slot by slot, that took about a dozen atomic instructions with three or
+    // four active lanes each.
+    constexpr int kStride = 2 * NS * kWave;  // entries of one list array: every class of the wave
+    static_assert(kStride * (1 + 2 * NP) <= kCommitMax * 5, "commit list fits the wave's LDS");
+    float *cl_v = &g_commit[threadIdx.x / kWave][0];
+    unsigned *cl_c = (unsigned *)cl_v;
+    unsigned nlist = 0;  // wave-uniform
+    auto collect = [&](int m, const bool go[2]) {
+        const uint64_t b0 = __ballot(go[0]), b1 = __ballot(go[1]);
+        if ((b0 | b1) == 0ull) return;
+        const unsigned pre = __builtin_amdgcn_mbcnt_hi((unsigned)(b1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b1,
+                             __builtin_amdgcn_mbcnt_hi((unsigned)(b0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b0, nlist))));
 #pragma unroll
         for (int h = 0; h < 2; ++h)
+            if (go[h]) {
+                const unsigned e = pre + (h == 1 && go[0] ? 1u : 0u);
+                cl_c[e] = cur[m][h];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    cl_v[kStride * (1 + 2 * p) + e] = acc_r[m][h][p] - cmp_r[m][h][p];
+                    cl_v[kStride * (2 + 2 * p) + e] = acc_i[m][h][p] - cmp_i[m][h][p];
+                    acc_r[m][h][p] = cmp_r[m][h][p];
+                    acc_i[m][h][p] = cmp_i[m][h][p];
+                }
+            }
+        nlist += (unsigned)(__builtin_popcountll(b0) + __builtin_popcountll(b1));
+    };
+    auto flush = [&]() {
+        for (unsigned e = (unsigned)lane; e < nlist; e += kWave) {
+            float *cell = a.grid + 2 * (int64_t)cl_c[e];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                acc_r[m][h][p] = go[h] ? cmp_r[m][h][p] : acc_r[m][h][p];
-                acc_i[m][h][p] = go[h] ? cmp_i[m][h][p] : acc_i[m][h][p];
+                unsafeAtomicAdd(cell + 2 * p * a.cells, cl_v[kStride * (1 + 2 * p) + e]);
+                unsafeAtomicAdd(cell + 2 * p * a.cells + 1, cl_v[kStride * (2 + 2 * p) + e]);
             }
+        }
+        nlist = 0;
     };
     // Commits are only for classes that exist: not in an idle slot, and not the missing
     // second class of a row's last pair.
@@ -431,10 +441,11 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                     const unsigned c0 = st.yc[m] & ~kWrapBit;
                     const unsigned yc[2] = {c0, (st.yc[m] & kWrapBit) ? c0 - (unsigned)(S - 1) : c0 + 1u};
                     const bool go[2] = {owns(m, 0) && yc[0] != cur[m][0], owns(m, 1) && yc[1] != cur[m][1]};
-                    commit(m, go);
+                    collect(m, go);
                     cur[m][0] = yc[0];
                     cur[m][1] = yc[1];
                 }
+                flush();
             }
             // Kahan step with the product fused into the compensation:
             // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t; one sample serves every
@@ -501,8 +512,9 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
 #pragma unroll
         for (int m = 0; m < NS; ++m) {
             const bool go[2] = {owns(m, 0), owns(m, 1)};
-            commit(m, go);
+            collect(m, go);
         }
+        flush();
     }
 }
 
