@@ -125,15 +125,17 @@ typedef struct wg_geom {
  *   zeta    [n_w*beta*beta]  sum of the real parts of each S_k x S_k matrix (eq. sum; the
  *                      repeated columns excluded), of the values as stored in `data`, in
  *                      FP64 (C-3)
- *   data               C-1: plane k holds beta*beta matrices of S_k rows, each row S_k + 2
- *                      samples, row-major, matrix index (o_v + beta/2 - 1)*beta +
- *                      (o_u + beta/2 - 1) for oversample offsets o in (-beta/2, beta/2];
- *                      matrix element [i][j], 0 <= j < S_k, is the kernel at fine offsets
- *                      ((i-H)*beta - o_v, (j-H)*beta - o_u), H = (S_k-1)/2, normalised so the
- *                      w=0 kernel's centre is 1 (eq. choose with row = v, column = u), and
- *                      sits at row position 1 + j; position 0 repeats [i][S_k - 1] and
- *                      position S_k + 1 repeats [i][0] (so that two neighbouring columns,
- *                      read forwards or backwards, are adjacent also where they wrap).
+ *   data               C-1: plane k holds beta*beta matrices of S_k rows, each row
+ *                      S_k + 2P samples (P = 1 for WG_KF32, 3 for WG_KBF16 and WG_KF16),
+ *                      row-major, matrix index (o_v + beta/2 - 1)*beta + (o_u + beta/2 - 1)
+ *                      for oversample offsets o in (-beta/2, beta/2]; matrix element [i][j],
+ *                      0 <= j < S_k, is the kernel at fine offsets ((i-H)*beta - o_v,
+ *                      (j-H)*beta - o_u), H = (S_k-1)/2, normalised so the w=0 kernel's
+ *                      centre is 1 (eq. choose with row = v, column = u), and sits at row
+ *                      position P + j; positions 0..P-1 repeat columns S_k-P..S_k-1 and
+ *                      positions P+S_k..P+S_k+P-1 repeat columns 0..P-1 (so that P + 1
+ *                      neighbouring columns, one 16-byte load, read forwards or backwards,
+ *                      are adjacent also where they wrap).
  *   data_cap           capacity of `data` in complex elements.
  *   dtype, n_w, beta   must match the geometry; s_max is written by wg_ktable_build.
  * All pointers are device memory owned by the caller.
@@ -217,8 +219,8 @@ int wg_version(void);
 
 /*
  * Sizes for wg_ktable_build, from the geometry alone (Algorithm convgen).
- * [host] data_elems_max: complex elements `data` must hold (every plane at s_hi:
- *        n_w * beta^2 * s_hi * (s_hi + 2)).
+ * [host] data_elems_max: complex elements `data` must hold for any table type (every plane
+ *        at s_hi with the widest padding: n_w * beta^2 * s_hi * (s_hi + 6)).
  * [host] ws_bytes: device workspace the build needs.
  * Errors: WG_EINVAL (NULL pointer or invalid geometry), WG_EUNSUPPORTED (limits above).
  */

@@ -8,12 +8,13 @@
 // compensation, and commits (one FP32 atomic add per component) only when the cell leaves
 // the footprint -- the ownership idea of Romein's gridder, applied per wavefront.
 //
-// Classes are owned in pairs (q, q + 1) of one footprint row: the two samples sit next to
-// each other in a table row (padded with the last column before it and the first column
-// after it, so that the pair that wraps from column S - 1 to column 0 is adjacent too, read
-// forwards or, for a mirrored matrix, backwards) and one 16-byte load (8 bytes with 16-bit
-// tables) fetches both. A vector load instruction costs about the same whatever its width,
-// and the instruction rate of the vector memory path is what bounds these kernels.
+// Classes are owned in groups of neighbouring columns of one footprint row, as many as one
+// 16-byte load holds: pairs (q, q + 1) with FP32 tables, quads (q, ..., q + 3) with 16-bit
+// tables. Their samples sit next to each other in a table row (padded with G - 1 repeated
+// columns on each side, so that a group that wraps from column S - 1 to column 0 is
+// adjacent too, read forwards or, for a mirrored matrix, backwards) and one load fetches
+// them all. A vector load instruction costs about the same whatever its width, and the
+// instruction rate of the vector memory path is what bounds these kernels.
 #include <type_traits>
 
 #include "wg_common.hpp"
@@ -47,23 +48,19 @@ struct GArgs {
     const uint8_t *flag;
 };
 
-template <int DT>
-__device__ inline float2 load_k(const void *data, int64_t idx) {
-    if (DT == WG_KF32) return ((const float2 *)data)[idx];
-    const uint32_t u = ((const uint32_t *)data)[idx];
-    if (DT == WG_KBF16) return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xFFFF0000u));
-    _Float16 lo, hi;
-    const uint16_t l16 = (uint16_t)(u & 0xFFFFu), h16 = (uint16_t)(u >> 16);
-    __builtin_memcpy(&lo, &l16, 2);
-    __builtin_memcpy(&hi, &h16, 2);
-    return make_float2((float)lo, (float)hi);
-}
+// Classes per group in a kernel: what one 16-byte load of its table type holds (pairs with
+// FP32 tables, quads with 16-bit tables), except pairs for 16-bit tables with four
+// polarisations, whose accumulators do not fit four classes per slot in 128 VGPRs.
+template <int DT, int NP>
+constexpr int kgroup() { return DT == WG_KF32 ? 2 : NP == 4 ? 2 : 4; }
 
-// The two samples of a class pair as fetched (converted to float only when used, so that a
-// wave can keep several loads in flight): four floats with FP32 tables, two packed complex
-// 16-bit values otherwise.
-template <int DT> struct PairRaw { using type = uint2; };
-template <> struct PairRaw<WG_KF32> { using type = float4; };
+// The samples of a class group as fetched (converted to float only when used, so that a
+// wave can keep several loads in flight): two complex FP32 values, or G packed complex
+// 16-bit values.
+template <int DT, int G> struct GroupRaw { using type = uint4; };
+template <> struct GroupRaw<WG_KBF16, 2> { using type = uint2; };
+template <> struct GroupRaw<WG_KF16, 2> { using type = uint2; };
+template <> struct GroupRaw<WG_KF32, 2> { using type = float4; };
 
 template <int DT>
 __device__ inline float2 to_float2(uint32_t u) {
@@ -78,13 +75,15 @@ __device__ inline float2 to_float2(uint32_t u) {
     }
 }
 
-// Sample h (0: first class of the pair, 1: second) as a complex float.
-template <int DT>
-__device__ inline float2 pair_sample(const typename PairRaw<DT>::type &v, int h) {
+// Sample h < G of a group as a complex float.
+template <int DT, int G>
+__device__ inline float2 group_sample(const typename GroupRaw<DT, G>::type &v, int h) {
     if constexpr (DT == WG_KF32)
         return h == 0 ? make_float2(v.x, v.y) : make_float2(v.z, v.w);
-    else
+    else if constexpr (G == 2)
         return to_float2<DT>(h == 0 ? v.x : v.y);
+    else
+        return to_float2<DT>(h == 0 ? v.x : h == 1 ? v.y : h == 2 ? v.z : v.w);
 }
 
 // Supports present in the plan, largest first, with their first work unit.
@@ -94,14 +93,14 @@ struct UnitTable {
     int first[34];
 };
 
-__device__ void build_units(const int32_t *plan, int slots, UnitTable *t) {
+__device__ void build_units(const int32_t *plan, int G, int slots, UnitTable *t) {
     int u = 0, m = 0;
     for (int S = kMaxS; S >= 1; S -= 2) {
         const int c = plan[kPlanCount + S];
         if (c > 0) {
             t->S[m] = S;
             t->first[m] = u;
-            u += c * nchunk_pairs(S, slots);
+            u += c * nchunk_groups(S, G, slots);
             ++m;
         }
     }
@@ -116,14 +115,14 @@ __device__ void build_units(const int32_t *plan, int slots, UnitTable *t) {
 // along an axis is the matrix of +o reversed along that axis (position j <-> S - 1 - j).
 // Reading the 25 of 64 matrices with o >= 0 per axis, backwards along an axis where the
 // run's offset is negative, cuts the samples a plane keeps in the caches by 2.5. Read
-// backwards along u, the load of a class pair starts at the pair's second sample, so the
-// two halves of the load change places.
+// backwards along u, the load of a class group starts at the group's last sample, so the
+// samples arrive in reverse order.
 template <int NP>
 struct RunBatch {
     int cell0, ph, kb, ok;  // ph: footprint origin phases, (row0 mod S) << 16 | (ax mod S)
     int mul;                // signed byte strides of the footprint position in the table,
-                            // row << 16 | column (a negative column stride: the pair's
-                            // samples arrive swapped); kb is the matrix origin read from
+                            // row << 16 | column (a negative column stride: the group's
+                            // samples arrive reversed); kb is the matrix origin read from
     float gr[NP], gi[NP];   // the run's weighted visibility sum per polarisation
 };
 
@@ -134,6 +133,8 @@ __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 template <int DT, int NP>
 __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool valid, const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
+    constexpr int G = kgroup<DT, NP>(), P = pad_of(DT);
+    static_assert(G - 1 <= P, "the row padding covers a group's wrap");
     RunBatch<NP> b;
     b.ok = 0;
     b.cell0 = b.ph = b.kb = b.mul = 0;
@@ -143,7 +144,7 @@ __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool val
         const int H = (S - 1) >> 1, half = a.n >> 1, hb = a.beta >> 1;
         const int X = a.x[j], Y = a.y[j], k = a.plane[j];
         const int gid = a.grid_id ? a.grid_id[j] : 0;
-        const int ou = a.ou[j], ov = a.ov[j], W = S + 2;  // W: samples per table row
+        const int ou = a.ou[j], ov = a.ov[j], W = S + 2 * P;  // W: samples per table row
         const int sigma = (abs(ov) + hb - 1) * a.beta + (abs(ou) + hb - 1);
         const int ax = X + half - H, row0 = Y + half - H;
         const int64_t kbase = koff[k] + (int64_t)sigma * S * W;
@@ -154,12 +155,13 @@ __device__ inline RunBatch<NP> load_batch(const GArgs &a, int S, int j, bool val
             b.ok = 1;
             b.cell0 = row0 * a.n + ax + (int)(gid * a.cells * NP);
             b.ph = (row0 % S) << 16 | (ax % S);
-            // footprint column j reads row position 1 + j forwards, S - 1 - j backwards (which
-            // holds the column of footprint position j + 1, the load's first sample, and then
-            // that of j); footprint row i reads matrix row i, or S - 1 - i backwards
+            // a group whose first class sits in footprint column j loads from row position
+            // P + j forwards, P + S - G - j backwards (whose G samples are the columns of
+            // footprint positions j + G - 1 down to j); footprint row i reads matrix row i,
+            // or S - 1 - i backwards
             const int mu = ou < 0 ? -esz : esz, rv = ov < 0 ? -W * esz : W * esz;
             b.mul = (int)((unsigned)(unsigned short)mu | (unsigned)(unsigned short)rv << 16);
-            b.kb = (int)kbase + (ou < 0 ? S - 1 : 1) + (ov < 0 ? (S - 1) * W : 0);
+            b.kb = (int)kbase + (ou < 0 ? P + S - G : P) + (ov < 0 ? (S - 1) * W : 0);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const float2 g = a.gamma[(int64_t)j * NP + p];
@@ -176,14 +178,17 @@ __device__ inline __amdgpu_buffer_rsrc_t table_rsrc(const void *data, int64_t nu
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(data), (short)0, (int)num_bytes, 0x00020000);
 }
 
-template <int DT>
-__device__ inline typename PairRaw<DT>::type pair_load(__amdgpu_buffer_rsrc_t rs, int off) {
-    if constexpr (DT == WG_KF32) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-        return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
-    } else {
+template <int DT, int G>
+__device__ inline typename GroupRaw<DT, G>::type group_load(__amdgpu_buffer_rsrc_t rs, int off) {
+    if constexpr (DT != WG_KF32 && G == 2) {
         const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
         return make_uint2((unsigned)v[0], (unsigned)v[1]);
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        if constexpr (DT == WG_KF32)
+            return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
+        else
+            return make_uint4((unsigned)v[0], (unsigned)v[1], (unsigned)v[2], (unsigned)v[3]);
     }
 }
 
@@ -224,47 +229,43 @@ __device__ inline unsigned table_off(u16x2 w, unsigned m, unsigned c) {
     return (unsigned)r;
 }
 
-// The lane's class pairs of a chunk: slot m holds pair min(k0 + 64 m + lane, k1 - 1), i.e.
-// row p = pair / ((S + 1) / 2) and first column q = 2 (pair mod ((S + 1) / 2)), as (q, p).
-// Bit m of *idle is set when the slot's pair lies past the lane's share (the lane then
-// repeats the last pair and must neither add nor commit); bit m of *single when the pair's
-// second class does not exist (q = S - 1, the last pair of a row).
-template <int NS>
-__device__ inline void lane_pairs(int S, int k0, int k1, int lane, u16x2 *cls, unsigned *idle, unsigned *single) {
-    const int hw = (S + 1) >> 1;
-    const float rh = 1.0f / (float)hw;
-    unsigned id = 0, sg = 0;
+// The lane's class groups of a chunk: slot m holds group min(k0 + 64 m + lane, k1 - 1), i.e.
+// row p = k / gpr and first column q = G (k mod gpr) with gpr = ceil(S / G) groups per row,
+// as (q, p); nval[m] = min(G, S - q) of its classes exist. Only the last slot can lie past
+// the lane's share (*idle: the lane then repeats the last group and must neither add nor
+// commit), since the slot count is ceil((k1 - k0) / 64).
+template <int NS, int G>
+__device__ inline void lane_groups(int S, int k0, int k1, int lane, u16x2 *cls, int *nval, bool *idle) {
+    const int gpr = groups_per_row(S, G);
+    const float rg = 1.0f / (float)gpr;
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
-        const int raw = k0 + m * kWave + lane;
-        const int k = min(raw, k1 - 1);
-        const int pp = (int)((float)k * rh + 0.5f * rh);
-        const int q = 2 * (k - pp * hw);
+        const int k = min(k0 + m * kWave + lane, k1 - 1);
+        const int pp = (int)((float)k * rg + 0.5f * rg);
+        const int q = G * (k - pp * gpr);
         cls[m] = u16x2{(unsigned short)q, (unsigned short)pp};
-        id |= (raw >= k1 ? 1u : 0u) << m;
-        sg |= (q + 1 >= S ? 1u : 0u) << m;
+        nval[m] = min(G, S - q);
     }
-    *idle = id;
-    *single = sg;
+    *idle = k0 + (NS - 1) * kWave + lane >= k1;
 }
 
-// Samples and cells of one run for the lane's pair slots, fetched one run ahead.
-template <int DT>
+// Samples and cells of one run for the lane's group slots, fetched one run ahead.
+template <int DT, int G>
 struct Stage {
-    typename PairRaw<DT>::type k[kPairSlots];
-    unsigned yc[kPairSlots];  // cell of the pair's first class, with kWrapBit when its second
-                              // class wraps to column 0; set only when the footprint moved
-    bool moved;               // wave-uniform: the run's footprint origin differs from the previous run's
-    bool swap;                // wave-uniform: the run reads its matrix backwards along u, so each
-                              // load holds the pair's second sample first
+    typename GroupRaw<DT, G>::type k[kGroupSlots];
+    unsigned yc[kGroupSlots];  // cell of the group's first class; set only when the footprint moved
+    int wrap[kGroupSlots];     // classes of the group before it wraps from footprint column S - 1
+                               // to column 0 (S minus the first class's column); set with yc
+    bool moved;                // wave-uniform: the run's footprint origin differs from the previous run's
+    bool swap;                 // wave-uniform: the run reads its matrix backwards along u, so each
+                               // load holds the group's samples in reverse order
 };
 
-// The cell of the second class of a pair whose first class has footprint position wpos and
-// cell c: the next column, or column 0 when the first class is in column S - 1.
-__device__ inline unsigned second_cell(u16x2 wpos, unsigned c, int S) {
-    return (int)wpos.x == S - 1 ? c - (unsigned)(S - 1) : c + 1u;
+// Cell of class h of a group whose first class has cell c and `wrap` classes before the
+// footprint's column S - 1: the next columns, continuing from column 0 after the wrap.
+__device__ inline unsigned class_cell(unsigned c, int h, int wrap, int S) {
+    return h == 0 ? c : c + (unsigned)h - (h >= wrap ? (unsigned)S : 0u);
 }
-constexpr unsigned kWrapBit = 0x80000000u;  // cells are below 2^31
 
 // Cell base of "no previous run": no footprint starts there (cell bases are below n*n).
 constexpr unsigned kNoCell = 0xFFFFFFFFu;
@@ -309,39 +310,38 @@ __device__ inline void for_each_unit(int nunits, int32_t *q, F &&body) {
 }
 
 // Per wave (four per workgroup): the commit list of one footprint move, as arrays of cells
-// and of the real and imaginary values per polarisation. Sized for the largest
-// instantiation: 2 classes x 3 pairs x 64 lanes entries of 3 words (one polarisation), or
-// fewer pairs with more polarisations.
-constexpr int kCommitMax = 2 * 3 * 64;
-__shared__ float g_commit[4][kCommitMax * 5];
+// and of the real and imaginary values per polarisation; sized for the largest
+// instantiation (16-bit quads with four polarisations: 4 classes x 64 lanes x 9 words).
+constexpr int kCommitWords = 4 * 64 * 9;
+__shared__ float g_commit[4][kCommitWords];
 
 template <int DT, int NP, int NS>
 __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int S, int k0, int k1, int rb, int re,
                                                              int lane, const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
+    constexpr int G = kgroup<DT, NP>();
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
 
-    u16x2 cls[kPairSlots];
-    unsigned idle, single;
-    lane_pairs<NS>(S, k0, k1, lane, cls, &idle, &single);
-    // an idle slot (past the lane's share of pairs) reads past the table's end, which gives
-    // zeros: it adds nothing, and it never commits
-    unsigned idle_off[NS];
-#pragma unroll
-    for (int m = 0; m < NS; ++m) idle_off[m] = ((idle >> m) & 1u) ? 0x80000000u : 0u;
+    u16x2 cls[kGroupSlots];
+    int nval[kGroupSlots];
+    bool idle;
+    lane_groups<NS, G>(S, k0, k1, lane, cls, nval, &idle);
+    // an idle last slot (past the lane's share of groups) reads past the table's end, which
+    // gives zeros: it adds nothing, and it never commits
+    const unsigned idle_off = idle ? 0x80000000u : 0u;
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
     const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};  // cell offset in the grid
-    // per pair slot, class h and polarisation: Kahan sum and compensation of the owned cell
-    float acc_r[NS][2][NP], acc_i[NS][2][NP], cmp_r[NS][2][NP], cmp_i[NS][2][NP];
-    unsigned cur[kPairSlots][2];  // owned cells (y*n + x); set from the chunk's first run
+    // per group slot, class h and polarisation: Kahan sum and compensation of the owned cell
+    float acc_r[NS][G][NP], acc_i[NS][G][NP], cmp_r[NS][G][NP], cmp_i[NS][G][NP];
+    unsigned cur[kGroupSlots][G];  // owned cells (y*n + x); set from the chunk's first run
     // Footprint positions of the lane's first classes, recomputed only when the footprint moves
     // (consecutive runs of a chunk mostly differ in oversampling offsets or plane alone).
-    u16x2 wpos[kPairSlots];
+    u16x2 wpos[kGroupSlots];
     unsigned last_cell0 = kNoCell;
 #pragma unroll
     for (int m = 0; m < NS; ++m)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < G; ++h)
 #pragma unroll
             for (int p = 0; p < NP; ++p) acc_r[m][h][p] = acc_i[m][h][p] = cmp_r[m][h][p] = cmp_i[m][h][p] = 0.f;
     // Commit the cell's compensated sums (acc - cmp) of every polarisation; the next cell
@@ -350,26 +350,33 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
     //
     // Commits are compacted. When the footprint moves, each (slot, class) of the wave whose
     // cell leaves writes that cell and its values to the wave's list in LDS (its place from
-    // two ballots and mbcnt, so the list runs lane by lane, first class before second: a row
-    // of leaving cells stays a run of neighbouring cells, whereas one atomic per slot and
-    // class would cover every other cell), and the list is then added to the grid 64 entries
-    // per atomic instruction. Most moves commit one column of the footprint, a few lanes per
+    // one ballot per class and mbcnt, so the list runs lane by lane, class by class: a row of
+    // leaving cells stays a run of neighbouring cells, whereas one atomic per slot and class
+    // would cover every G-th cell), and the list is then added to the grid 64 entries per
+    // atomic instruction. Most moves commit one column of the footprint, a few lanes per
     // slot: issued slot by slot, that took about a dozen atomic instructions with three or
     // four active lanes each.
-    constexpr int kStride = 2 * NS * kWave;  // entries of one list array: every class of the wave
-    static_assert(kStride * (1 + 2 * NP) <= kCommitMax * 5, "commit list fits the wave's LDS");
+    constexpr int kStride = G * NS * kWave;  // entries of one list array: every class of the wave
+    static_assert(kStride * (1 + 2 * NP) <= kCommitWords, "commit list fits the wave's LDS");
     float *cl_v = &g_commit[threadIdx.x / kWave][0];
     unsigned *cl_c = (unsigned *)cl_v;
     unsigned nlist = 0;  // wave-uniform
-    auto collect = [&](int m, const bool go[2]) {
-        const uint64_t b0 = __ballot(go[0]), b1 = __ballot(go[1]);
-        if ((b0 | b1) == 0ull) return;
-        const unsigned pre = __builtin_amdgcn_mbcnt_hi((unsigned)(b1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b1,
-                             __builtin_amdgcn_mbcnt_hi((unsigned)(b0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b0, nlist))));
+    auto collect = [&](int m, const bool *go) {
+        uint64_t bal[G];
+        uint64_t any = 0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < G; ++h) {
+            bal[h] = __ballot(go[h]);
+            any |= bal[h];
+        }
+        if (any == 0ull) return;
+        unsigned e = nlist;
+#pragma unroll
+        for (int h = 0; h < G; ++h)
+            e = __builtin_amdgcn_mbcnt_hi((unsigned)(bal[h] >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal[h], e));
+#pragma unroll
+        for (int h = 0; h < G; ++h)
             if (go[h]) {
-                const unsigned e = pre + (h == 1 && go[0] ? 1u : 0u);
                 cl_c[e] = cur[m][h];
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
@@ -378,8 +385,10 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                     acc_r[m][h][p] = cmp_r[m][h][p];
                     acc_i[m][h][p] = cmp_i[m][h][p];
                 }
+                ++e;
             }
-        nlist += (unsigned)(__builtin_popcountll(b0) + __builtin_popcountll(b1));
+#pragma unroll
+        for (int h = 0; h < G; ++h) nlist += (unsigned)__builtin_popcountll(bal[h]);
     };
     auto flush = [&]() {
         for (unsigned e = (unsigned)lane; e < nlist; e += kWave) {
@@ -392,17 +401,17 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
         }
         nlist = 0;
     };
-    // Commits are only for classes that exist: not in an idle slot, and not the missing
-    // second class of a row's last pair.
-    auto owns = [&](int m, int h) { return ((idle >> m) & 1u) == 0u && (h == 0 || ((single >> m) & 1u) == 0u); };
+    // Commits are only for classes that exist: not in an idle last slot, and not past the
+    // end of a row's short last group.
+    auto owns = [&](int m, int h) { return (m < NS - 1 || !idle) && h < nval[m]; };
     bool first = true;
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
         const RunBatch<NP> b = load_batch<DT, NP>(a, S, base + lane, lane < n, koff);
 
-        // cells (when the footprint moved) and sample pairs of the lane's slots for run t
-        auto fetch = [&](int t, Stage<DT> &st) {
+        // cells (when the footprint moved) and sample groups of the lane's slots for run t
+        auto fetch = [&](int t, Stage<DT, G> &st) {
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
             const unsigned mul = (unsigned)rl(b.mul, t);
@@ -415,18 +424,22 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
 #pragma unroll
                 for (int m = 0; m < NS; ++m) {
                     wpos[m] = footprint_pos(cls[m], ph, ss);
-                    st.yc[m] = dot2(wpos[m], mul_c, cell0) | ((int)wpos[m].x == S - 1 ? kWrapBit : 0u);
+                    st.yc[m] = dot2(wpos[m], mul_c, cell0);
+                    st.wrap[m] = S - (int)wpos[m].x;
                 }
             }
             const unsigned mulv = in_vgpr(mul);
 #pragma unroll
-            for (int m = 0; m < NS; ++m) st.k[m] = pair_load<DT>(rs, (int)(table_off(wpos[m], mulv, kbB) | idle_off[m]));
+            for (int m = 0; m < NS; ++m) {
+                const unsigned off = table_off(wpos[m], mulv, kbB);
+                st.k[m] = group_load<DT, G>(rs, (int)(m == NS - 1 ? off | idle_off : off));
+            }
         };
         // A run that failed load_batch's checks (and lane n, past a batch of odd length n)
         // carries gamma = 0: its step adds zero, so the loop needs no branch on it. Such a
         // failed run counts as moved, with cells inside the first grid's corner, so the next
         // good run commits what was held there (zero) and moves on.
-        auto accumulate = [&](int t, const Stage<DT> &st) {
+        auto accumulate = [&](int t, const Stage<DT, G> &st) {
             float gr[NP], gi[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
@@ -438,27 +451,31 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
             if (st.moved) {
 #pragma unroll
                 for (int m = 0; m < NS; ++m) {
-                    const unsigned c0 = st.yc[m] & ~kWrapBit;
-                    const unsigned yc[2] = {c0, (st.yc[m] & kWrapBit) ? c0 - (unsigned)(S - 1) : c0 + 1u};
-                    const bool go[2] = {owns(m, 0) && yc[0] != cur[m][0], owns(m, 1) && yc[1] != cur[m][1]};
+                    unsigned yc[G];
+                    bool go[G];
+#pragma unroll
+                    for (int h = 0; h < G; ++h) {
+                        yc[h] = class_cell(st.yc[m], h, st.wrap[m], S);
+                        go[h] = owns(m, h) && yc[h] != cur[m][h];
+                    }
                     collect(m, go);
-                    cur[m][0] = yc[0];
-                    cur[m][1] = yc[1];
+#pragma unroll
+                    for (int h = 0; h < G; ++h) cur[m][h] = yc[h];
                 }
                 flush();
             }
             // Kahan step with the product fused into the compensation:
             // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t; one sample serves every
-            // polarisation. Class h takes sample h of the load, or sample 1 - h when the run
-            // reads backwards along u (one copy of the sums per case, under a wave-uniform
+            // polarisation. Class h takes sample h of the load, or sample G - 1 - h when the
+            // run reads backwards along u (one copy of the sums per case, under a wave-uniform
             // branch).
             auto sums = [&](auto swapped) {
                 constexpr int sw = decltype(swapped)::value;
 #pragma unroll
                 for (int m = 0; m < NS; ++m)
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const float2 kv = pair_sample<DT>(st.k[m], h ^ sw);
+                    for (int h = 0; h < G; ++h) {
+                        const float2 kv = group_sample<DT, G>(st.k[m], sw ? G - 1 - h : h);
 #pragma unroll
                         for (int p = 0; p < NP; ++p) {
                             const float yr = fmaf(gr[p], kv.x, -fmaf(gi[p], kv.y, cmp_r[m][h][p]));
@@ -475,22 +492,20 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
             // selects on every sample)
             if (st.swap) {
                 sums(std::integral_constant<int, 1>{});
-                asm volatile("; samples swapped");
+                asm volatile("; samples reversed");
             } else {
                 sums(std::integral_constant<int, 0>{});
                 asm volatile("; samples in order");
             }
         };
 
-        Stage<DT> sa, sb;
+        Stage<DT, G> sa, sb;
         fetch(0, sa);
         if (first) {
 #pragma unroll
-            for (int m = 0; m < NS; ++m) {
-                const unsigned c0 = sa.yc[m] & ~kWrapBit;
-                cur[m][0] = c0;
-                cur[m][1] = (sa.yc[m] & kWrapBit) ? c0 - (unsigned)(S - 1) : c0 + 1u;
-            }
+            for (int m = 0; m < NS; ++m)
+#pragma unroll
+                for (int h = 0; h < G; ++h) cur[m][h] = class_cell(sa.yc[m], h, sa.wrap[m], S);
             first = false;
         }
         // The next run's fetch is issued on every path (past the batch's end it repeats the
@@ -511,20 +526,22 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
     if (!first) {
 #pragma unroll
         for (int m = 0; m < NS; ++m) {
-            const bool go[2] = {owns(m, 0), owns(m, 1)};
+            bool go[G];
+#pragma unroll
+            for (int h = 0; h < G; ++h) go[h] = owns(m, h);
             collect(m, go);
         }
         flush();
     }
 }
 
-// Class pairs [k0, k1) of a support-S chunk, split evenly over the chunk's waves; the slot
+// Class groups [k0, k1) of a support-S chunk, split evenly over the chunk's waves; the slot
 // count per lane is a template parameter so the unrolled slot loops carry no guards.
-__device__ inline void chunk_pairs(int S, int chunk, int slots, int &k0, int &k1, int &ns) {
-    const int np = npairs(S), nch = nchunk_pairs(S, slots);
-    const int ppc = (np + nch - 1) / nch;
-    k0 = chunk * ppc;
-    k1 = min(np, k0 + ppc);
+__device__ inline void chunk_groups(int S, int G, int chunk, int slots, int &k0, int &k1, int &ns) {
+    const int ng = ngroups(S, G), nch = nchunk_groups(S, G, slots);
+    const int gpc = (ng + nch - 1) / nch;
+    k0 = chunk * gpc;
+    k1 = min(ng, k0 + gpc);
     ns = uni((k1 - k0 + kWave - 1) / kWave);
 }
 
@@ -544,17 +561,20 @@ __device__ __attribute__((always_inline)) inline void grid_dispatch(int ns, cons
     }
 }
 
-// Most class pairs per lane of the gridder; the accumulators of more polarisations take the
-// registers of more pairs.
+// Most class groups per lane of the gridder; the accumulators of more classes per group and
+// of more polarisations take the registers of more groups.
 template <int DT, int NP>
 constexpr int grid_slots() {
-    return NP == 4 ? kGridPairsPol4 : NP == 2 ? kGridPairsPol2 : DT == WG_KF32 ? kGridPairs : kGridPairsNarrow;
+    if constexpr (DT == WG_KF32)
+        return NP == 4 ? kGridGroupsPol4 : NP == 2 ? kGridGroupsPol2 : kGridGroups;
+    else
+        return NP == 1 ? kGridGroupsNarrow : kGridGroupsNarrowPol;
 }
 
 template <int DT, int NP>
 __device__ __attribute__((always_inline)) void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
     int k0, k1, ns;
-    chunk_pairs(S, chunk, grid_slots<DT, NP>(), k0, k1, ns);
+    chunk_groups(S, kgroup<DT, NP>(), chunk, grid_slots<DT, NP>(), k0, k1, ns);
     grid_dispatch<DT, NP, 1, grid_slots<DT, NP>()>(ns, a, S, k0, k1, rb, re, lane, koff);
 }
 
@@ -564,7 +584,7 @@ template <int DT, int NP, bool COUNTER>
 __global__ __launch_bounds__(256, 4) void k_grid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, grid_slots<DT, NP>(), &ut);
+    if (threadIdx.x == 0) build_units(a.plan, kgroup<DT, NP>(), grid_slots<DT, NP>(), &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -572,7 +592,7 @@ __global__ __launch_bounds__(256, 4) void k_grid(GArgs a) {
     auto unit = [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_pairs(S, grid_slots<DT, NP>());
+        const int S = uni(ut.S[m]), nch = nchunk_groups(S, kgroup<DT, NP>(), grid_slots<DT, NP>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;
@@ -606,21 +626,22 @@ __device__ inline float wave_total_pair(float re, float im) {
     return v;
 }
 
-// Adjoint, with the gridder's decomposition: a wave owns the same cell class pairs of a
+// Adjoint, with the gridder's decomposition: a wave owns the same cell class groups of a
 // local chunk, keeps the grid value of each owned cell in a register and reloads the values
 // only when the footprint moves (about one run in seven), and forms per run the partial dot
 // product of conj(K) with those values (a short FMA chain per lane, then one lane-swap and
 // DPP tree over the wave for the real and imaginary parts together). The waves sharing a
 // chunk add their partial sums into work[run]; k_degrid_finish hands d to the run's records.
-static_assert(kGridPairs <= kPairSlots && kGridPairsNarrow <= kPairSlots && kGridPairsPol2 <= kPairSlots &&
-                  kGridPairsPol4 <= kPairSlots && kDegridPairs <= kPairSlots && kDegridPairsNarrow <= kPairSlots &&
-                  kDegridPairsPol2 <= kPairSlots && kDegridPairsPol4 <= kPairSlots,
-              "per-lane stage arrays hold kPairSlots pairs");
-template <int DT>
+static_assert(kGridGroups <= kGroupSlots && kGridGroupsNarrow <= kGroupSlots && kGridGroupsPol2 <= kGroupSlots &&
+                  kGridGroupsPol4 <= kGroupSlots && kGridGroupsNarrowPol <= kGroupSlots &&
+                  kDegridGroups <= kGroupSlots && kDegridGroupsNarrow <= kGroupSlots &&
+                  kDegridGroupsPol <= kGroupSlots && kDegridGroupsNarrowPol <= kGroupSlots,
+              "per-lane stage arrays hold kGroupSlots groups");
+template <int DT, int G>
 struct DStage {
-    typename PairRaw<DT>::type k[kPairSlots];
+    typename GroupRaw<DT, G>::type k[kGroupSlots];
     bool moved;  // wave-uniform: the run's footprint origin differs from the previous run's
-    bool swap;   // wave-uniform: the loads hold each pair's second sample first
+    bool swap;   // wave-uniform: the loads hold each group's samples in reverse order
 };
 
 // The NP complex values of one cell, one from each polarisation plane ([NP][n][n] grid).
@@ -630,7 +651,7 @@ __device__ inline void load_cell(const float2 *grid, unsigned cell, int64_t cell
     for (int p = 0; p < NP; ++p) v[p] = grid[cell + p * cells];
 }
 
-// Order of the loads per run t: the sample pairs of run t + 1 are issued before run t's sums,
+// Order of the loads per run t: the sample groups of run t + 1 are issued before run t's sums,
 // and when run t + 1 moves the footprint its grid values are loaded into the owned-cell
 // registers right after run t's last use of them. The wait before run t + 1's sums then
 // covers those grid values and run t + 1's samples while run t + 2's samples stay in flight,
@@ -639,25 +660,25 @@ template <int DT, int NP, int NS>
 __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, int S, int k0, int k1, int rb,
                                                                int re, int lane, const int64_t *koff) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
+    constexpr int G = kgroup<DT, NP>();
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
     const float2 *grid = (const float2 *)a.grid;
-    u16x2 cls[kPairSlots];
-    unsigned idle, single;
-    lane_pairs<NS>(S, k0, k1, lane, cls, &idle, &single);
-    // idle slots read their samples past the table's end (zeros)
-    unsigned idle_off[NS];
-#pragma unroll
-    for (int m = 0; m < NS; ++m) idle_off[m] = ((idle >> m) & 1u) ? 0x80000000u : 0u;
+    u16x2 cls[kGroupSlots];
+    int nval[kGroupSlots];
+    bool idle;
+    lane_groups<NS, G>(S, k0, k1, lane, cls, nval, &idle);
+    // an idle last slot reads its samples past the table's end (zeros)
+    const unsigned idle_off = idle ? 0x80000000u : 0u;
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
     const u16x2 mul_c = as_u16x2(in_vgpr((unsigned)a.n << 16 | 1u));
-    float2 gv[NS][2][NP];       // grid values of the owned cells (0 for a missing second class)
-    u16x2 wpos[kPairSlots];     // footprint positions of the first classes, when the footprint moves
-    unsigned gcell[kPairSlots]; // first class's cell of the last run that moved the footprint
+    float2 gv[NS][G][NP];        // grid values of the owned cells (0 for a class that does not exist)
+    u16x2 wpos[kGroupSlots];     // footprint positions of the first classes, when the footprint moves
+    unsigned gcell[kGroupSlots]; // first class's cell of the last run that moved the footprint
     unsigned last_cell0 = kNoCell;
 #pragma unroll
     for (int m = 0; m < NS; ++m)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < G; ++h)
 #pragma unroll
             for (int p = 0; p < NP; ++p) gv[m][h][p] = make_float2(0.f, 0.f);
 
@@ -665,8 +686,8 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
         const int n = min(kWave, re - base);
         const RunBatch<NP> b = load_batch<DT, NP>(a, S, base + lane, lane < n, koff);
 
-        // footprint positions and cells (when the footprint moved) and sample pairs of run t
-        auto fetch = [&](int t, DStage<DT> &st) {
+        // footprint positions and cells (when the footprint moved) and sample groups of run t
+        auto fetch = [&](int t, DStage<DT, G> &st) {
             const unsigned cell0 = (unsigned)rl(b.cell0, t);
             const unsigned kbB = (unsigned)rl(b.kb, t) * esz;
             const unsigned mul = (unsigned)rl(b.mul, t);
@@ -684,15 +705,21 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
             }
             const unsigned mulv = in_vgpr(mul);
 #pragma unroll
-            for (int m = 0; m < NS; ++m) st.k[m] = pair_load<DT>(rs, (int)(table_off(wpos[m], mulv, kbB) | idle_off[m]));
+            for (int m = 0; m < NS; ++m) {
+                const unsigned off = table_off(wpos[m], mulv, kbB);
+                st.k[m] = group_load<DT, G>(rs, (int)(m == NS - 1 ? off | idle_off : off));
+            }
         };
         // the grid values of the owned cells of the last run that moved the footprint; a
-        // missing second class keeps the value 0
+        // class past the end of a row's short last group keeps the value 0
         auto load_values = [&]() {
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 load_cell<NP>(grid, gcell[m], a.cells, gv[m][0]);
-                if (((single >> m) & 1u) == 0u) load_cell<NP>(grid, second_cell(wpos[m], gcell[m], S), a.cells, gv[m][1]);
+                const int wrap = S - (int)wpos[m].x;
+#pragma unroll
+                for (int h = 1; h < G; ++h)
+                    if (h < nval[m]) load_cell<NP>(grid, class_cell(gcell[m], h, wrap, S), a.cells, gv[m][h]);
             }
         };
         // this wave's sums: lane l holds component l >> 5 (0 real, 1 imaginary) of run
@@ -700,18 +727,19 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
         float lo[NP], hi[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) lo[p] = hi[p] = 0.f;
-        auto consume = [&](int t, const DStage<DT> &st) {
+        auto consume = [&](int t, const DStage<DT, G> &st) {
             float pr[NP], pim[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) pr[p] = pim[p] = 0.f;
-            // class h takes sample h of the load, or 1 - h when the run reads backwards along u
+            // class h takes sample h of the load, or G - 1 - h when the run reads backwards
+            // along u
             auto sums = [&](auto swapped) {
                 constexpr int sw = decltype(swapped)::value;
 #pragma unroll
                 for (int m = 0; m < NS; ++m)
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const float2 kv = pair_sample<DT>(st.k[m], h ^ sw);
+                    for (int h = 0; h < G; ++h) {
+                        const float2 kv = group_sample<DT, G>(st.k[m], sw ? G - 1 - h : h);
 #pragma unroll
                         for (int p = 0; p < NP; ++p) {
                             pr[p] = fmaf(kv.x, gv[m][h][p].x, fmaf(kv.y, gv[m][h][p].y, pr[p]));
@@ -721,7 +749,7 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
             };
             if (st.swap) {
                 sums(std::integral_constant<int, 1>{});
-                asm volatile("; samples swapped");
+                asm volatile("; samples reversed");
             } else {
                 sums(std::integral_constant<int, 0>{});
                 asm volatile("; samples in order");
@@ -737,7 +765,7 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
             }
         };
 
-        DStage<DT> sa, sb;
+        DStage<DT, G> sa, sb;
         fetch(0, sa);
         if (sa.moved) load_values();
         // the next run's fetch is issued on every path, as in the gridder
@@ -779,13 +807,16 @@ __device__ inline void degrid_dispatch(int ns, const GArgs &a, int S, int c0, in
 
 template <int DT, int NP>
 constexpr int degrid_slots() {
-    return NP == 4 ? kDegridPairsPol4 : NP == 2 ? kDegridPairsPol2 : DT == WG_KF32 ? kDegridPairs : kDegridPairsNarrow;
+    if constexpr (DT == WG_KF32)
+        return NP == 1 ? kDegridGroups : kDegridGroupsPol;
+    else
+        return NP == 1 ? kDegridGroupsNarrow : kDegridGroupsNarrowPol;
 }
 
 template <int DT, int NP>
 __device__ void degrid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
     int k0, k1, ns;
-    chunk_pairs(S, chunk, degrid_slots<DT, NP>(), k0, k1, ns);
+    chunk_groups(S, kgroup<DT, NP>(), chunk, degrid_slots<DT, NP>(), k0, k1, ns);
     degrid_dispatch<DT, NP, 1, degrid_slots<DT, NP>()>(ns, a, S, k0, k1, rb, re, lane, koff);
 }
 
@@ -793,7 +824,7 @@ template <int DT, int NP>
 __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, degrid_slots<DT, NP>(), &ut);
+    if (threadIdx.x == 0) build_units(a.plan, kgroup<DT, NP>(), degrid_slots<DT, NP>(), &ut);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -801,7 +832,7 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     for_each_unit(nunits, a.queue, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_pairs(S, degrid_slots<DT, NP>());
+        const int S = uni(ut.S[m]), nch = nchunk_groups(S, kgroup<DT, NP>(), degrid_slots<DT, NP>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + S]) + item;

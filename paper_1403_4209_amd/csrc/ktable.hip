@@ -337,7 +337,7 @@ __global__ void k_supports(BuildArgs a, int s_lo, int s_hi, int32_t *support, in
         const int S = min(s_hi, max(snat, law));
         support[k] = S;
         offset[k] = acc;
-        acc += (int64_t)a.beta * a.beta * S * (S + 2);
+        acc += (int64_t)a.beta * a.beta * S * (S + 2 * pad_of(a.dtype));
     }
     offset[a.n_w] = acc;
 }
@@ -375,16 +375,22 @@ __global__ void k_slices(BuildArgs a, const int32_t *__restrict__ support,
     const int sigma = blockIdx.x, k = blockIdx.y;
     const int beta = a.beta;
     const int ov = sigma / beta - beta / 2 + 1, ou = sigma % beta - beta / 2 + 1;
-    const int S = support[k], H = (S - 1) / 2, W = S + 2;
+    const int P = pad_of(a.dtype);
+    const int S = support[k], H = (S - 1) / 2, W = S + 2 * P;
     const int64_t base = offset[k] + (int64_t)sigma * S * W;
     double acc = 0.0;
-    // rows of S + 2 values: column j of the matrix at position 1 + j, with column S - 1
-    // repeated before the row and column 0 after it, so that two neighbouring columns of a
-    // row, read forwards or (for a mirrored matrix) backwards, are adjacent also where they
-    // wrap; zeta sums the S columns once
+    // rows of S + 2P values (P = 1 for FP32, 3 for 16-bit): column j of the matrix at
+    // position P + j, with columns S - P..S - 1 repeated before the row and 0..P - 1 after
+    // it, so that P + 1 neighbouring columns of a row, read forwards or (for a mirrored
+    // matrix) backwards, are adjacent also where they wrap; zeta sums the S columns once.
+    // (Positions wrap only by less than one row: P < S, or P >= S only for S = 1, where
+    // every position holds the single column.)
     for (int e = threadIdx.x; e < S * W; e += blockDim.x) {
-        const int i = e / W, jw = e - (e / W) * W, j = jw == 0 ? S - 1 : jw == S + 1 ? 0 : jw - 1;
-        const bool counted = jw >= 1 && jw <= S;
+        const int i = e / W, jw = e - (e / W) * W;
+        int j = jw - P;
+        while (j < 0) j += S;
+        while (j >= S) j -= S;
+        const bool counted = jw >= P && jw < P + S;
         const int fv = (i - H) * beta - ov, fu = (j - H) * beta - ou;
         const double2 v = a.win[((size_t)k * a.W + (fv + a.Wf)) * a.W + (fu + a.Wf)];
         if (a.dtype == WG_KF32) {
@@ -469,7 +475,7 @@ extern "C" int wg_ktable_sizes(const wg_geom *g, int64_t *data_elems_max, size_t
     int st = wg::check_geom(g);
     if (st != WG_OK) return st;
     if (!data_elems_max || !ws_bytes) return WG_EINVAL;
-    *data_elems_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * (g->s_hi + 2);
+    *data_elems_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * (g->s_hi + 2 * wg::kPadMax);
     *ws_bytes = wg::ws_layout(g).total;
     return WG_OK;
 }
@@ -521,7 +527,7 @@ extern "C" int wg_ktable_build(const wg_geom *g, wg_ktable *kt, void *ws, size_t
 
     // With room for every plane at s_hi and no host copies requested, nothing waits: the
     // matrices are cut on the device right away and s_max reports the upper bound s_hi.
-    const int64_t cap_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * (g->s_hi + 2);
+    const int64_t cap_max = (int64_t)g->n_w * g->beta * g->beta * g->s_hi * (g->s_hi + 2 * wg::pad_of(kt->dtype));
     const bool sync = support_out || offset_out || kt->data_cap < cap_max;
     if (sync) {
         std::vector<int32_t> sup(g->n_w);

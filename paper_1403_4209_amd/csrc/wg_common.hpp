@@ -10,19 +10,26 @@ namespace wg {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxS = WG_MAX_SUPPORT;
-// Class pairs per lane (each pair is two cell classes fetched with one load; the last pair
-// of a footprint row has one class): the largest count any kernel instantiation uses, and
-// the counts per kernel, table type and polarisation count.
-constexpr int kPairSlots = 5;
-constexpr int kGridPairs = 3;          // gridder, FP32 tables, one polarisation (4 spill at 128 VGPRs)
-constexpr int kGridPairsNarrow = 3;    // the same with BF16/FP16 tables (4 spill)
-constexpr int kGridPairsPol2 = 2;      // gridder with two polarisations (any table type; 3 spill)
-constexpr int kGridPairsPol4 = 1;      // gridder with four polarisations (2 spill)
-constexpr int kDegridPairs = 3;        // degridder, FP32 tables, one polarisation (7.8 ms on the
-                                       // 4096^2 workload, 8.0 with 4 and 8.1 with 5)
-constexpr int kDegridPairsNarrow = 5;  // the same with BF16/FP16 tables (6.7 ms, 6.8 with 4, 7.0 with 3)
-constexpr int kDegridPairsPol2 = 3;    // degridder with two polarisations (4 measure alike)
-constexpr int kDegridPairsPol4 = 3;    // degridder with four polarisations (5.5 ms on 2048^2, 5.65 with 2)
+// Cell classes are owned in groups of neighbouring columns of one footprint row, as many as
+// one 16-byte table load holds: pairs with FP32 tables, quads with 16-bit tables (the last
+// group of a row may be short). Table rows carry group - 1 repeated columns on each side.
+__host__ __device__ constexpr int group_of(int dtype) { return dtype == WG_KF32 ? 2 : 4; }
+__host__ __device__ constexpr int pad_of(int dtype) { return group_of(dtype) - 1; }
+constexpr int kPadMax = 3;  // the widest padding (16-bit tables)
+
+// Groups per lane: the largest count any kernel instantiation uses, and the counts per
+// kernel, table type and polarisation count (measured; one more spills at 128 VGPRs where
+// noted).
+constexpr int kGroupSlots = 3;
+constexpr int kGridGroups = 3;          // gridder, FP32 pairs, one polarisation (4 spill)
+constexpr int kGridGroupsNarrow = 2;    // gridder, 16-bit quads, one polarisation
+constexpr int kGridGroupsPol2 = 2;      // gridder, FP32 pairs, two polarisations (3 spill)
+constexpr int kGridGroupsPol4 = 1;      // gridder, FP32 pairs, four polarisations (2 spill)
+constexpr int kGridGroupsNarrowPol = 1; // gridder, 16-bit quads, two or four polarisations
+constexpr int kDegridGroups = 3;        // degridder, FP32 pairs, one polarisation
+constexpr int kDegridGroupsNarrow = 3;  // degridder, 16-bit quads, one polarisation
+constexpr int kDegridGroupsPol = 3;     // degridder, FP32 pairs, two or four polarisations
+constexpr int kDegridGroupsNarrowPol = 2;  // degridder, 16-bit quads, two or four polarisations
 
 // ---------------------------------------------------------------------------------------
 // Plan layout (int32 words). Items are local chunks (first run, one past last run) of
@@ -53,11 +60,15 @@ inline int64_t plan_tiles_at(int64_t capacity, int64_t n_seg) { return plan_segc
 inline int64_t n_scan_tiles(int64_t n_seg) { return (n_seg + kScanTile - 1) / kScanTile; }
 
 // Decomposition of a support-S local chunk into waves: the cell classes (y mod S, x mod S)
-// of footprint row p are paired as (q, q + 1) for q = 0, 2, ..., S - 1 (the last pair has no
-// second class), S (S + 1) / 2 pairs in all, numbered row by row and spread evenly over
-// nchunk_pairs(S, slots) waves, at most `slots` pairs per lane.
-__host__ __device__ inline int npairs(int S) { return S * (S + 1) / 2; }
-__host__ __device__ inline int nchunk_pairs(int S, int slots) { return (npairs(S) + kWave * slots - 1) / (kWave * slots); }
+// of footprint row p are grouped as (q, ..., q + G - 1) for q = 0, G, 2G, ... (the last group
+// of a row holds what is left of it), ceil(S / G) groups per row and S ceil(S / G) in all,
+// numbered row by row and spread evenly over nchunk_groups(S, G, slots) waves, at most
+// `slots` groups per lane.
+__host__ __device__ inline int groups_per_row(int S, int G) { return (S + G - 1) / G; }
+__host__ __device__ inline int ngroups(int S, int G) { return S * groups_per_row(S, G); }
+__host__ __device__ inline int nchunk_groups(int S, int G, int slots) {
+    return (ngroups(S, G) + kWave * slots - 1) / (kWave * slots);
+}
 
 // Status helpers
 #define WG_HIP_CHECK(expr)                                   \

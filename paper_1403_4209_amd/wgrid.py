@@ -278,8 +278,9 @@ class KernelTable:
 
     def data_complex(self) -> torch.Tensor:
         """The table samples as complex64 (upcast from bf16/f16), shape [offset[-1]], in the
-        library's layout: per plane beta^2 matrices of S rows of S + 2 samples, matrix column
-        j at row position 1 + j, position 0 repeating column S - 1 and position S + 1 column 0."""
+        library's layout: per plane beta^2 matrices of S rows of S + 2P samples (P = 1 for
+        FP32, 3 for 16-bit tables), matrix column j at row position P + j, positions 0..P-1
+        repeating columns S-P..S-1 and positions P+S..P+S+P-1 columns 0..P-1."""
         n = self.offset[-1]
         if self.dtype == "f32":
             return torch.view_as_complex(self.data_d[: 8 * n].view(torch.float32).view(n, 2))

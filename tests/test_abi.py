@@ -47,7 +47,7 @@ def test_status_strings_and_version(wg):
 def test_ktable_sizes_and_geometry_validation(wg):
     g = wg.make_geom(2048, 8, 32, 9, 63, 256, 60.0, 3.0e4)
     elems, ws = wg.wg_ktable_sizes(g)
-    assert elems == 32 * 64 * 63 * 65 and ws > 0   # matrices of S rows of S + 2 at s_hi
+    assert elems == 32 * 64 * 63 * 69 and ws > 0   # matrices of S rows of S + 6 at s_hi (the widest padding)
     bad = [
         wg.make_geom(2047, 8, 32, 9, 63, 256, 60.0, 3.0e4),   # odd N
         wg.make_geom(2048, 6, 32, 9, 63, 256, 60.0, 3.0e4),   # beta not a power of two

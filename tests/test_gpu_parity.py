@@ -60,23 +60,28 @@ class Err(float):
 
 
 def unpad_table(tb, beta):
-    """The library's table in the oracle's layout: its matrices have rows of S + 2 values,
-    matrix column j at position 1 + j, position 0 repeating column S - 1 and position S + 1
-    column 0 (so two neighbouring columns are one load, forwards or backwards, also where they
+    """The library's table in the oracle's layout: its matrices have rows of S + 2P values
+    (P = 1 with FP32 tables, 3 with 16-bit ones), matrix column j at position P + j,
+    positions 0..P-1 repeating columns S-P..S-1 and positions P+S..P+S+P-1 columns 0..P-1
+    (so that P + 1 neighbouring columns are one load, forwards or backwards, also where they
     wrap). Checks that layout (offsets from the supports, every repeated value equal bit for
     bit) and returns the S x S matrices back to back, with their offsets."""
+    P = 1 if tb.dtype == "f32" else 3
     data = tb.data_complex().cpu().numpy().astype(np.complex128)
     sup = [int(v) for v in tb.support]
     off_pad, off = [0], [0]
     for S in sup:
-        off_pad.append(off_pad[-1] + beta * beta * S * (S + 2))
+        off_pad.append(off_pad[-1] + beta * beta * S * (S + 2 * P))
         off.append(off[-1] + beta * beta * S * S)
     assert list(tb.offset) == off_pad
     planes = []
     for k, S in enumerate(sup):
-        m = data[off_pad[k]:off_pad[k + 1]].reshape(beta * beta, S, S + 2)
-        assert np.array_equal(m[:, :, 0], m[:, :, S]) and np.array_equal(m[:, :, S + 1], m[:, :, 1])
-        planes.append(m[:, :, 1:S + 1].reshape(-1))
+        m = data[off_pad[k]:off_pad[k + 1]].reshape(beta * beta, S, S + 2 * P)
+        core = m[:, :, P:P + S]
+        for x in range(P):
+            assert np.array_equal(m[:, :, x], core[:, :, (x - P) % S])
+            assert np.array_equal(m[:, :, P + S + x], core[:, :, x % S])
+        planes.append(core.reshape(-1))
     return np.concatenate(planes), off
 
 
