@@ -958,7 +958,9 @@ def _pol_case(case, npol, circular):
 
 @pytest.mark.parametrize("case,npol,circular,per_channel,dtype", [
     ("cfg1", 4, False, False, "f32"), ("cfg1", 2, True, False, "f32"), ("cfg4", 4, False, False, "f32"),
-    ("cfg4", 4, True, True, "f32"), ("cfg4", 4, False, False, "bf16")])
+    ("cfg4", 4, True, True, "f32"), ("cfg4", 4, False, False, "bf16"),
+    # 16-bit tables with two products take class quads, with four products class pairs
+    ("cfg4", 2, True, False, "f16"), ("cfg1", 4, False, False, "f16")])
 def test_polarised_records(case, npol, circular, per_channel, dtype):
     """Records of 2 or 4 polarisation products with per-product weights and flags: runs
     bit-exact (a record is griddable with one unflagged product), gamma per product and the
