@@ -76,22 +76,23 @@ def grid_source_hash() -> str:
 
 def read_counters():
     """Per-launch figures of k_grid and k_degrid from the committed rocprofv3 counter
-    summary (HBM bytes, VALU issue fraction), or {} when the gridder's sources have changed
-    since the counters were taken."""
+    summary (HBM bytes, VALU issue fraction, texture-data unit busy fraction), or {} when the
+    gridder's sources have changed since the counters were taken."""
     try:
         with open(PROFILE_COUNTERS) as f:
             kv = {k.strip(): v.strip() for k, v in (line.split(":", 1) for line in f if ":" in line)}
         if kv["grid_sources_sha256_16"].split()[0] != grid_source_hash():
             return {}
-        return {k: float(v.split()[0]) for k, v in kv.items() if k.startswith(("traffic_", "valu_issue_"))}
+        return {k: float(v.split()[0]) for k, v in kv.items() if k.startswith(("traffic_", "valu_issue_", "td_busy_"))}
     except Exception:
         return {}
 
 
 def roofline(kernel, updates, ms, counters):
-    """The kernel against the FP32 vector peak (the binding ceiling: gridding is a scatter of
-    8-flop complex multiply-adds whose table samples the caches serve), with its measured HBM
-    traffic per launch and the VALU issue fraction from the counter summary."""
+    """The kernel against the FP32 vector peak (gridding is a scatter of 8-flop complex
+    multiply-adds whose table samples the caches serve), with its measured HBM traffic per
+    launch and the VALU issue and vector-memory (texture-data unit) busy fractions from the
+    counter summary."""
     tf = FLOPS_PER_UPDATE * updates / (ms * 1e-3) / 1e12
     key = "k_grid" if kernel.startswith("k_grid") else "k_degrid"
     traffic = counters.get(f"traffic_{key}")
@@ -103,6 +104,9 @@ def roofline(kernel, updates, ms, counters):
                                "frac": round(gbs / HBM_PEAK_GBS, 4)}
     if f"valu_issue_{key}" in counters:
         out["valu_issue_frac"] = counters[f"valu_issue_{key}"]
+    if f"td_busy_{key}" in counters:
+        # the vector memory path: fraction of cycles the texture-data units are busy
+        out["vmem_td_busy_frac"] = counters[f"td_busy_{key}"]
     return out
 
 
