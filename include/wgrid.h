@@ -76,7 +76,7 @@ typedef enum wg_kdtype {
                                   WG_GRID_PER_CHANNEL.                                         */
 
 /* Limits of this build. */
-#define WG_MAX_SUPPORT 63    /* largest kernel support (odd)                            */
+#define WG_MAX_SUPPORT 511   /* largest kernel support (odd)                            */
 #define WG_MAX_PLANES 256    /* largest number of w-planes                              */
 #define WG_MAX_FFT 2048      /* largest beta * m_img (oversampled table side)           */
 

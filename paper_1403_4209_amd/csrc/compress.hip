@@ -191,9 +191,9 @@ constexpr int kStage = 1024;
 constexpr int kSegWaves = 16;  // segments (one per wave) per k_segments workgroup
 
 struct BlockAgg {
-    int cnt[64];       // chunks per support
-    int fill[64];      // emit: slots handed out per support
-    int base[64];      // emit: first slot reserved per support
+    int cnt[kNumS];    // chunks per support (index S >> 1)
+    int fill[kNumS];   // emit: slots handed out per support
+    int base[kNumS];   // emit: first slot reserved per support
     int nstaged;
     int2 items[kStage];
     int itemS[kStage];
@@ -204,16 +204,16 @@ struct BlockAgg {
 template <bool EMIT>
 __device__ inline void close_item(const CArgs &a, BlockAgg &agg, int S, int begin, int end) {
     if (!EMIT) {
-        atomicAdd(&agg.cnt[S], 1);
+        atomicAdd(&agg.cnt[sidx(S)], 1);
         return;
     }
     const int i = atomicAdd(&agg.nstaged, 1);
     if (i < kStage) {
         agg.items[i] = make_int2(begin, end);
         agg.itemS[i] = S;
-        atomicAdd(&agg.cnt[S], 1);
+        atomicAdd(&agg.cnt[sidx(S)], 1);
     } else {
-        const int slot = atomicAdd(&a.plan[kPlanCur + S], 1);
+        const int slot = atomicAdd(&a.plan[kPlanCur + sidx(S)], 1);
         a.items[2 * slot] = begin;
         a.items[2 * slot + 1] = end;
     }
@@ -231,7 +231,8 @@ __global__ __launch_bounds__(1024) void k_segments(CArgs a) {
         s_wb[i] = a.wbound[i];
         s_sup[i] = a.support[a.stack ? 0 : i];  // stacking: plane 0's support for every plane
     }
-    if (threadIdx.x < 64) {
+    static_assert(kNumS <= 1024, "one thread per support counter");
+    if (threadIdx.x < kNumS) {
         agg.cnt[threadIdx.x] = 0;
         agg.fill[threadIdx.x] = 0;
     }
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(1024) void k_segments(CArgs a) {
     }
     __syncthreads();
     if (!EMIT) {
-        if (threadIdx.x < 64 && agg.cnt[threadIdx.x]) atomicAdd(&a.plan[kPlanCount + threadIdx.x], agg.cnt[threadIdx.x]);
+        if (threadIdx.x < kNumS && agg.cnt[threadIdx.x]) atomicAdd(&a.plan[kPlanCount + threadIdx.x], agg.cnt[threadIdx.x]);
         if (threadIdx.x == 0) {
             if (agg.st[0]) atomicAdd((unsigned long long *)&a.stats->n_griddable, agg.st[0]);
             if (agg.st[1]) atomicAdd((unsigned long long *)&a.stats->n_compressed, agg.st[1]);
@@ -260,14 +261,14 @@ __global__ __launch_bounds__(1024) void k_segments(CArgs a) {
             if (agg.st[3]) atomicAdd((unsigned long long *)&a.stats->upd_saved, agg.st[3]);
         }
     } else {
-        if (threadIdx.x < 64 && agg.cnt[threadIdx.x])
+        if (threadIdx.x < kNumS && agg.cnt[threadIdx.x])
             agg.base[threadIdx.x] = atomicAdd(&a.plan[kPlanCur + threadIdx.x], agg.cnt[threadIdx.x]);
         if (threadIdx.x == 0 && agg.norm != 0.0) atomicAdd(&a.stats->normaliser, agg.norm);
         __syncthreads();
         const int nst = min(agg.nstaged, kStage);
         for (int i = threadIdx.x; i < nst; i += blockDim.x) {
             const int S = agg.itemS[i];
-            const int slot = agg.base[S] + atomicAdd(&agg.fill[S], 1);
+            const int slot = agg.base[sidx(S)] + atomicAdd(&agg.fill[sidx(S)], 1);
             a.items[2 * slot] = agg.items[i].x;
             a.items[2 * slot + 1] = agg.items[i].y;
         }
@@ -558,11 +559,11 @@ __global__ __launch_bounds__(1024) void k_scan_top(CArgs a, int64_t n_tiles) {
         a.stats->n_runs = carry;
         int acc = 0;
         for (int S = kMaxS; S >= 1; S -= 2) {
-            a.plan[kPlanOff + S] = acc;
-            a.plan[kPlanCur + S] = acc;
-            acc += a.plan[kPlanCount + S];
+            a.plan[kPlanOff + sidx(S)] = acc;
+            a.plan[kPlanCur + sidx(S)] = acc;
+            acc += a.plan[kPlanCount + sidx(S)];
         }
-        a.plan[kPlanOff + 64] = acc;
+        a.plan[kPlanOff + kNumS] = acc;
         a.stats->n_items = acc;
     }
 }

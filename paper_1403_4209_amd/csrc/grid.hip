@@ -89,23 +89,48 @@ __device__ inline float2 group_sample(const typename GroupRaw<DT, G>::type &v, i
 // Supports present in the plan, largest first, with their first work unit.
 struct UnitTable {
     int n;
-    int S[33];
-    int first[34];
+    int S[kNumS];
+    int first[kNumS + 1];
 };
 
-__device__ void build_units(const int32_t *plan, int G, int slots, UnitTable *t) {
-    int u = 0, m = 0;
-    for (int S = kMaxS; S >= 1; S -= 2) {
-        const int c = plan[kPlanCount + S];
-        if (c > 0) {
-            t->S[m] = S;
-            t->first[m] = u;
-            u += c * nchunk_groups(S, G, slots);
-            ++m;
+// Built by the first wave of the workgroup: lane l takes the four supports
+// kMaxS - 2 (4l + k), k = 0..3 (largest first), and a wave prefix sum over the lanes' unit
+// and support counts places them.
+static_assert(kNumS == 4 * kWave, "four supports per lane");
+__device__ void build_units(const int32_t *plan, int G, int slots, UnitTable *t, int lane) {
+    int cnt[4], units[4];
+    int u = 0, np = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int S = kMaxS - 2 * (4 * lane + k);
+        cnt[k] = plan[kPlanCount + sidx(S)];
+        units[k] = cnt[k] * nchunk_groups(S, G, slots);
+        u += units[k];
+        np += cnt[k] > 0 ? 1 : 0;
+    }
+    // inclusive prefix sums over the lanes
+    int su = u, sn = np;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int pu = __shfl_up(su, d, kWave), pn = __shfl_up(sn, d, kWave);
+        if (lane >= d) {
+            su += pu;
+            sn += pn;
         }
     }
-    t->first[m] = u;
-    t->n = m;
+    int first = su - u, m = sn - np;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (cnt[k] > 0) {
+            t->S[m] = kMaxS - 2 * (4 * lane + k);
+            t->first[m] = first;
+            first += units[k];
+            ++m;
+        }
+    if (lane == kWave - 1) {
+        t->first[sn] = su;
+        t->n = sn;
+    }
 }
 
 // Run records of up to 64 consecutive runs, one per lane, with everything the per-run loop
@@ -309,15 +334,17 @@ __device__ inline void for_each_unit(int nunits, int32_t *q, F &&body) {
     }
 }
 
-// Per wave (four per workgroup): the commit list of one footprint move, as arrays of cells
-// and of the real and imaginary values per polarisation; sized for the largest
-// instantiation (16-bit quads with four polarisations: 4 classes x 64 lanes x 9 words).
-constexpr int kCommitWords = 4 * 64 * 9;
-__shared__ float g_commit[4][kCommitWords];
+template <int DT, int NP>
+constexpr int grid_slots();
+
+// Words of one wave's commit list (the cells of one footprint move, and their real and
+// imaginary values per polarisation): one entry per class the wave owns.
+template <int DT, int NP>
+constexpr int commit_words() { return kgroup<DT, NP>() * grid_slots<DT, NP>() * kWave * (1 + 2 * NP); }
 
 template <int DT, int NP, int NS>
 __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int S, int k0, int k1, int rb, int re,
-                                                             int lane, const int64_t *koff) {
+                                                             int lane, const int64_t *koff, float *cl_v) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
     constexpr int G = kgroup<DT, NP>();
     const __amdgpu_buffer_rsrc_t rs = table_rsrc(a.data, a.data_cap * esz);
@@ -357,8 +384,7 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
     // slot: issued slot by slot, that took about a dozen atomic instructions with three or
     // four active lanes each.
     constexpr int kStride = G * NS * kWave;  // entries of one list array: every class of the wave
-    static_assert(kStride * (1 + 2 * NP) <= kCommitWords, "commit list fits the wave's LDS");
-    float *cl_v = &g_commit[threadIdx.x / kWave][0];
+    static_assert(kStride * (1 + 2 * NP) <= commit_words<DT, NP>(), "commit list fits the wave's LDS");
     unsigned *cl_c = (unsigned *)cl_v;
     unsigned nlist = 0;  // wave-uniform
     auto collect = [&](int m, const bool *go) {
@@ -549,15 +575,15 @@ __device__ inline void chunk_groups(int S, int G, int chunk, int slots, int &k0,
 // allocation is the largest over its instantiations).
 template <int DT, int NP, int NS, int MAX>
 __device__ __attribute__((always_inline)) inline void grid_dispatch(int ns, const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
-                                     const int64_t *koff) {
+                                     const int64_t *koff, float *cl) {
     if constexpr (NS < MAX) {
         if (ns == NS) {
-            grid_chunk_ns<DT, NP, NS>(a, S, c0, c1, rb, re, lane, koff);
+            grid_chunk_ns<DT, NP, NS>(a, S, c0, c1, rb, re, lane, koff, cl);
             return;
         }
-        grid_dispatch<DT, NP, NS + 1, MAX>(ns, a, S, c0, c1, rb, re, lane, koff);
+        grid_dispatch<DT, NP, NS + 1, MAX>(ns, a, S, c0, c1, rb, re, lane, koff, cl);
     } else {
-        grid_chunk_ns<DT, NP, MAX>(a, S, c0, c1, rb, re, lane, koff);
+        grid_chunk_ns<DT, NP, MAX>(a, S, c0, c1, rb, re, lane, koff, cl);
     }
 }
 
@@ -572,10 +598,11 @@ constexpr int grid_slots() {
 }
 
 template <int DT, int NP>
-__device__ __attribute__((always_inline)) void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane, const int64_t *koff) {
+__device__ __attribute__((always_inline)) void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane,
+                                                          const int64_t *koff, float *cl) {
     int k0, k1, ns;
     chunk_groups(S, kgroup<DT, NP>(), chunk, grid_slots<DT, NP>(), k0, k1, ns);
-    grid_dispatch<DT, NP, 1, grid_slots<DT, NP>()>(ns, a, S, k0, k1, rb, re, lane, koff);
+    grid_dispatch<DT, NP, 1, grid_slots<DT, NP>()>(ns, a, S, k0, k1, rb, re, lane, koff, cl);
 }
 
 // COUNTER: the work list is walked through the counter in a.queue, else statically (one
@@ -584,7 +611,9 @@ template <int DT, int NP, bool COUNTER>
 __global__ __launch_bounds__(256, 4) void k_grid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, kgroup<DT, NP>(), grid_slots<DT, NP>(), &ut);
+    __shared__ float commit_lists[4 * commit_words<DT, NP>()];  // one per wave (256 threads)
+    float *cl = commit_lists + (threadIdx.x / kWave) * commit_words<DT, NP>();
+    if (threadIdx.x < kWave) build_units(a.plan, kgroup<DT, NP>(), grid_slots<DT, NP>(), &ut, threadIdx.x);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -595,8 +624,8 @@ __global__ __launch_bounds__(256, 4) void k_grid(GArgs a) {
         const int S = uni(ut.S[m]), nch = nchunk_groups(S, kgroup<DT, NP>(), grid_slots<DT, NP>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
-        const int slot = uni(a.plan[kPlanOff + S]) + item;
-        grid_chunk<DT, NP>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
+        const int slot = uni(a.plan[kPlanOff + sidx(S)]) + item;
+        grid_chunk<DT, NP>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff, cl);
     };
     if constexpr (COUNTER)
         for_each_unit(nunits, a.queue, unit);
@@ -824,7 +853,7 @@ template <int DT, int NP>
 __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
-    if (threadIdx.x == 0) build_units(a.plan, kgroup<DT, NP>(), degrid_slots<DT, NP>(), &ut);
+    if (threadIdx.x < kWave) build_units(a.plan, kgroup<DT, NP>(), degrid_slots<DT, NP>(), &ut, threadIdx.x);
     for (int k = threadIdx.x; k <= a.n_w; k += blockDim.x) koff[k] = a.offset[k];
     __syncthreads();
     const int nunits = uni(ut.first[ut.n]);
@@ -835,7 +864,7 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
         const int S = uni(ut.S[m]), nch = nchunk_groups(S, kgroup<DT, NP>(), degrid_slots<DT, NP>());
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
-        const int slot = uni(a.plan[kPlanOff + S]) + item;
+        const int slot = uni(a.plan[kPlanOff + sidx(S)]) + item;
         degrid_chunk<DT, NP>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
     });
 }

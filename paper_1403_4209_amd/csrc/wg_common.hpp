@@ -10,6 +10,8 @@ namespace wg {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxS = WG_MAX_SUPPORT;
+constexpr int kNumS = (kMaxS + 1) / 2;  // odd supports 1..kMaxS; support S has index S >> 1
+__host__ __device__ inline int sidx(int S) { return S >> 1; }
 // Cell classes are owned in groups of neighbouring columns of one footprint row, as many as
 // one 16-byte table load holds: pairs with FP32 tables, quads with 16-bit tables (the last
 // group of a row may be short). Table rows carry group - 1 repeated columns on each side.
@@ -35,9 +37,9 @@ constexpr int kDegridGroupsNarrowPol = 2;  // degridder, 16-bit quads, two or fo
 // Plan layout (int32 words). Items are local chunks (first run, one past last run) of
 // consecutive runs of one segment that share a support; they are grouped by support, the
 // largest support first.
-//   [kPlanCount + S]   items with support S              (S = 1..63, odd)
-//   [kPlanOff + S]     first item slot of support S       (kPlanOff + 64 = total)
-//   [kPlanCur + S]     append cursor of support S
+//   [kPlanCount + S/2] items with support S              (S = 1..kMaxS, odd)
+//   [kPlanOff + S/2]   first item slot of support S       (kPlanOff + kNumS = total)
+//   [kPlanCur + S/2]   append cursor of support S
 //   [kPlanQueueDegrid] degridder work-list counter and exit count (2 words), zero between launches
 //   [kPlanQueueGrid]   the same for the gridder's counter walk (large grids)
 //   [kPlanGrids]       number of grids the runs address (channels, w-planes or 1)
@@ -46,12 +48,13 @@ constexpr int kDegridGroupsNarrowPol = 2;  // degridder, 16-bit quads, two or fo
 //   then               scan tile totals: n_tiles + 1 words
 // ---------------------------------------------------------------------------------------
 constexpr int kPlanCount = 0;
-constexpr int kPlanOff = 64;
-constexpr int kPlanCur = 129;
-constexpr int kPlanQueueDegrid = 200;
-constexpr int kPlanQueueGrid = 208;
-constexpr int kPlanGrids = 240;  // read by every batch: kept off the work counter's cache line
-constexpr int kPlanHdr = 256;
+constexpr int kPlanOff = kNumS;
+constexpr int kPlanCur = 2 * kNumS + 1;
+constexpr int kPlanQueueDegrid = 800;  // each counter on its own 128-byte line
+constexpr int kPlanQueueGrid = 832;
+constexpr int kPlanGrids = 864;  // read by every batch: kept off the work counters' cache lines
+constexpr int kPlanHdr = 896;
+static_assert(kPlanCur + kNumS <= kPlanQueueDegrid, "plan header words do not overlap");
 constexpr int kScanTile = 4096;
 
 inline int64_t plan_items_at() { return kPlanHdr; }
@@ -106,7 +109,7 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
-// Float mod for small positive divisors: x mod S for 0 <= x < 2^22 and S <= 63.
+// Float mod for small positive divisors: x mod S for 0 <= x < 2^22 and 1 <= S <= 2^10.
 __device__ inline int mod_small(int x, int S, float rS) {
     int q = (int)((float)x * rS);
     int r = x - q * S;

@@ -48,6 +48,9 @@ def test_ktable_sizes_and_geometry_validation(wg):
     g = wg.make_geom(2048, 8, 32, 9, 63, 256, 60.0, 3.0e4)
     elems, ws = wg.wg_ktable_sizes(g)
     assert elems == 32 * 64 * 63 * 69 and ws > 0   # matrices of S rows of S + 6 at s_hi (the widest padding)
+    # the largest support: a 2048-point oversampled plane (beta 4, 512 image samples) holds it
+    elems, ws = wg.wg_ktable_sizes(wg.make_geom(4500, 4, 16, 9, 511, 512, 1.0, 3.0e4))
+    assert elems == 16 * 16 * 511 * 517 and ws > 0
     bad = [
         wg.make_geom(2047, 8, 32, 9, 63, 256, 60.0, 3.0e4),   # odd N
         wg.make_geom(2048, 6, 32, 9, 63, 256, 60.0, 3.0e4),   # beta not a power of two
@@ -62,7 +65,7 @@ def test_ktable_sizes_and_geometry_validation(wg):
         with pytest.raises(wg.WgError) as e:
             wg.wg_ktable_sizes(g)
         assert e.value.status == wg.WG_EINVAL
-    for g in [wg.make_geom(2048, 8, 32, 9, 65, 256, 60.0, 3.0e4),      # support above the limit
+    for g in [wg.make_geom(2048, 2, 32, 9, 513, 1024, 60.0, 3.0e4),    # support above the limit
               wg.make_geom(2048, 8, 300, 9, 63, 256, 60.0, 3.0e4),     # too many planes
               wg.make_geom(2048, 8, 32, 9, 63, 1024, 60.0, 3.0e4)]:    # FFT above the limit
         with pytest.raises(wg.WgError) as e:

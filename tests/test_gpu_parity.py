@@ -250,6 +250,41 @@ def test_grid_parity(case, dtype, tol):
     assert err_acc < 1e-5
 
 
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 3e-3)])
+def test_large_supports_match_oracle(dtype, tol):
+    """Supports of 101 to 255 (beyond 63: the plan's per-support words, the gridder's unit
+    table, class groups of more than 32 per footprint row and hundreds of waves per chunk):
+    config 1's records on a 2048^2 grid with oversampling 4 and four w-planes. Runs
+    bit-exact; grid and degrid against the FP64 oracle, and against the oracle on the same
+    rounded table within 1e-5."""
+    w = workloads.make(1, n=1024, beta=4, n_w=4, s_lo=101, s_hi=255, m_img=256)
+    geom = dict(w.geom)
+    geom["n"] = 2048   # the same cell size on a grid twice as wide: every footprint fits
+    data = wl_dict(w)
+    say("large supports", dtype)
+    table, gr, G = run_gpu(geom, data, dtype=dtype)
+    assert list(table.support) == [int(v) for v in otable(geom, "f64")["support"]]
+    assert max(table.support) == 255
+    tq = otable(geom, dtype)
+    orc = oracle.compress(geom, tq, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"])
+    compare_runs(gr, orc)
+    t64 = otable(geom, "f64")
+    o64 = oracle.compress(geom, t64, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"])
+    Gg = G.cpu().numpy().astype(np.complex128)
+    err = rel_l2(Gg, oracle.grid(geom, t64, o64))
+    err_q = rel_l2(Gg, oracle.grid(geom, tq, orc))
+    say(f"  grid rel L2 vs FP64 oracle {err:.3e}; vs oracle with the rounded table {err_q:.3e}")
+    assert err < tol and err_q < 1e-5
+    rng = np.random.default_rng(11)
+    n = geom["n"]
+    g = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64)
+    out = gr.degrid(torch.as_tensor(g).to(DEV)).cpu().numpy().astype(np.complex128)
+    ref = oracle.degrid(geom, t64, o64, g.astype(np.complex128), data["uvw"], data["wt"], data["vis"].shape)
+    errd = rel_l2(out, ref)
+    say(f"  degrid rel L2 vs FP64 oracle {errd:.3e}")
+    assert errd < tol
+
+
 def test_compressed_grid_matches_uncompressed_gpu():
     geom, data = cfg4_small()
     _, _, Gc = run_gpu(geom, data, compress=True)
