@@ -513,6 +513,50 @@ def main():
         out["polarisations"] = {"workload": "the plain FP32 workload's records", **pol}
         del wp, c2, w2
 
+        # heavy w-projection: the thesis's batch-5 imaging configuration 2 (4500^2, 16
+        # w-planes, oversampling 4, supports up to 349) on four-product records
+        wh = workloads.polarised(6, 4, device=dev)
+        gh = wg.geom_from_dict(wh.geom, n_pol=4)
+        ev[0].record()
+        th = wg.KernelTable(gh, "f32", device=dev)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_kt = ev[0].elapsed_time(ev[1])
+        grh = wg.Gridder(gh, th, torch.as_tensor(wh.uvw).to(dev), torch.as_tensor(wh.inv_lambda).to(dev),
+                         wh.weight, wh.flag)
+        gridh = torch.zeros(grh.grid_shape(), dtype=torch.complex64, device=dev)
+        vouth = torch.empty(grh.vis_shape(), dtype=torch.complex64, device=dev)
+        tch = tgh = tdh = 0.0
+        nh = 2
+        for i in range(nh + 1):
+            gridh.zero_()
+            ev[0].record()
+            grh.compress(wh.vis)
+            ev[1].record()
+            grh.grid(out=gridh)
+            ev[2].record()
+            grh.degrid(gridh, out=vouth)
+            ev[3].record()
+            torch.cuda.synchronize()
+            if i:
+                tch += ev[0].elapsed_time(ev[1])
+                tgh += ev[1].elapsed_time(ev[2])
+                tdh += ev[2].elapsed_time(ev[3])
+        tch, tgh, tdh = tch / nh, tgh / nh, tdh / nh
+        sh = grh.runs.stats()
+        out["heavy_4500"] = {
+            "workload": ("heavy w-projection: 44 stations (946 baselines) x 1 channel x 1024 timesteps of 10 s = "
+                         f"{int(sh.n_records):,} records x 4 polarisation products, grid 4500x4500 complex64 per "
+                         "product, oversampling 4, 16 w-planes, supports 9..349, FP32 tables"),
+            "runs": int(sh.n_runs), "supports": [int(v) for v in th.support],
+            "upd_real_per_product": int(sh.upd_real),
+            "ktable_ms": round(t_kt, 3), "compress_ms": round(tch, 4), "grid_ms": round(tgh, 4),
+            "degrid_ms": round(tdh, 4),
+            "grid_gupds_products": round(sh.upd_real * 4 / (tgh * 1e-3) / 1e9, 2),
+            "degrid_gupds_products": round(sh.upd_real * 4 / (tdh * 1e-3) / 1e9, 2)}
+        del wh, th, grh, gridh, vouth
+        torch.cuda.empty_cache()
+
         out["differentiation_4096"], c5 = workload_step(
             5, args.steps, args.warmup, "differentiation workload: 256 stations (32,640 baselines) x 8 channels x "
             "256 timesteps = 66,846,720 records, 4096x4096, 32 w-planes, supports 7..31")

@@ -252,19 +252,20 @@ def test_grid_parity(case, dtype, tol):
 
 @pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 3e-3)])
 def test_large_supports_match_oracle(dtype, tol):
-    """Supports of 101 to 255 (beyond 63: the plan's per-support words, the gridder's unit
-    table, class groups of more than 32 per footprint row and hundreds of waves per chunk):
-    config 1's records on a 2048^2 grid with oversampling 4 and four w-planes. Runs
-    bit-exact; grid and degrid against the FP64 oracle, and against the oracle on the same
-    rounded table within 1e-5."""
-    w = workloads.make(1, n=1024, beta=4, n_w=4, s_lo=101, s_hi=255, m_img=256)
+    """Supports of 101 to 349 (beyond 63: the plan's per-support words, the gridder's unit
+    table, class groups of more than 32 per footprint row and hundreds of waves per chunk;
+    349 is the largest support of the thesis's heavy configuration): config 1's records on
+    a 2048^2 grid with oversampling 4, 512 image samples and four w-planes. Runs bit-exact;
+    grid and degrid against the FP64 oracle, and against the oracle on the same rounded
+    table within 1e-5."""
+    w = workloads.make(1, n=1024, beta=4, n_w=4, s_lo=101, s_hi=349, m_img=512)
     geom = dict(w.geom)
     geom["n"] = 2048   # the same cell size on a grid twice as wide: every footprint fits
     data = wl_dict(w)
     say("large supports", dtype)
     table, gr, G = run_gpu(geom, data, dtype=dtype)
     assert list(table.support) == [int(v) for v in otable(geom, "f64")["support"]]
-    assert max(table.support) == 255
+    assert max(table.support) == 349
     tq = otable(geom, dtype)
     orc = oracle.compress(geom, tq, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"])
     compare_runs(gr, orc)

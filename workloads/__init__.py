@@ -47,6 +47,12 @@ CONFIGS = {
     # Differentiation: 256 stations within 80 km, 4096^2, supports up to 31.
     5: dict(n_st=256, radius=80.0e3, n_t=256, dt=2.0, n_ch=8, f_lo=120.0e6, f_hi=180.0e6,
             n_src=100, n=4096, beta=8, n_w=32, s_lo=7, s_hi=31),
+    # Heavy w-projection (the thesis's batch-5 imaging configuration 2: 4500^2 grid, 16
+    # w-planes, oversampling 4, supports up to 349), on records shaped like its first LOFAR
+    # data set (one channel, 10 s records) at a seventh of its 6.58 M records: 946
+    # baselines x 1024 timesteps, to be used with four polarisation products.
+    6: dict(n_st=44, radius=50.0e3, n_t=1024, dt=10.0, n_ch=1, f_lo=150.0e6, f_hi=150.0e6,
+            n_src=100, n=4500, beta=4, n_w=16, s_lo=9, s_hi=349, m_img=512),
 }
 
 
