@@ -861,9 +861,13 @@ __global__ __launch_bounds__(256) void k_degrid(GArgs a) {
     for_each_unit(nunits, a.queue, [&](int u) {
         int m = 0;
         while (u >= ut.first[m + 1]) ++m;
-        const int S = uni(ut.S[m]), nch = nchunk_groups(S, kgroup<DT, NP>(), degrid_slots<DT, NP>());
+        const int S = uni(ut.S[m]);
+        // share-major within a support: the waves in flight take the same share of different
+        // chunks, so the partial sums they add into work[] go to different runs (a chunk of
+        // large support has hundreds of shares, all adding into the same runs' entries)
         const int rel = u - uni(ut.first[m]);
-        const int item = rel / nch, chunk = rel - item * nch;
+        const int nit = uni(a.plan[kPlanCount + sidx(S)]);
+        const int chunk = rel / nit, item = rel - chunk * nit;
         const int slot = uni(a.plan[kPlanOff + sidx(S)]) + item;
         degrid_chunk<DT, NP>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff);
     });
