@@ -24,14 +24,14 @@ constexpr int kPadMax = 3;  // the widest padding (16-bit tables)
 // noted).
 constexpr int kGroupSlots = 3;
 constexpr int kGridGroups = 3;          // gridder, FP32 pairs, one polarisation (4 spill)
-constexpr int kGridGroupsNarrow = 2;    // gridder, 16-bit quads, one polarisation
+constexpr int kGridGroupsNarrow = 2;    // gridder, 16-bit quads, one polarisation (3 take 183 VGPRs)
 constexpr int kGridGroupsPol2 = 2;      // gridder, FP32 pairs, two polarisations (3 spill)
 constexpr int kGridGroupsPol4 = 1;      // gridder, FP32 pairs, four polarisations (2 spill)
-constexpr int kGridGroupsNarrowPol = 1; // gridder, 16-bit quads, two or four polarisations
+constexpr int kGridGroupsNarrowPol = 1; // gridder, 16-bit tables: quads with two, pairs with four polarisations
 constexpr int kDegridGroups = 3;        // degridder, FP32 pairs, one polarisation
 constexpr int kDegridGroupsNarrow = 3;  // degridder, 16-bit quads, one polarisation
 constexpr int kDegridGroupsPol = 3;     // degridder, FP32 pairs, two or four polarisations
-constexpr int kDegridGroupsNarrowPol = 2;  // degridder, 16-bit quads, two or four polarisations
+constexpr int kDegridGroupsNarrowPol = 2;  // degridder, 16-bit tables: quads with two, pairs with four
 
 // ---------------------------------------------------------------------------------------
 // Plan layout (int32 words). Items are local chunks (first run, one past last run) of
