@@ -270,7 +270,8 @@ int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const 
  * with WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first. Accumulation is FP32 with Kahan
  * compensation per owned cell between commits; commits use FP32 atomic adds, so the last
  * bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
- * Errors: WG_EINVAL, WG_EHIP.
+ * Errors: WG_EINVAL, WG_EUNSUPPORTED (kt->data_cap >= 2^28 elements: table byte offsets
+ * are 32-bit), WG_EHIP.
  */
 int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs, const wg_stats *stats,
             float *grid, wg_stream_t stream);
