@@ -286,6 +286,32 @@ def test_large_supports_match_oracle(dtype, tol):
     assert errd < tol
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("S", [1, 3])
+def test_tiny_supports_match_oracle(S, dtype):
+    """Supports 1 and 3, where a class group (a pair with FP32 tables, a quad with 16-bit
+    ones) is longer than or as long as a footprint row: its samples come from the padding
+    columns, partly repeated, and with quads some of its classes do not exist. Config 1's
+    records; grid and degrid against the oracle on the same rounded table within 1e-5."""
+    w = workloads.make(1, s_lo=S, s_hi=S)
+    geom, data = w.geom, wl_dict(w)
+    say("tiny support", S, dtype)
+    table, gr, G = run_gpu(geom, data, dtype=dtype)
+    assert list(table.support) == [S] * geom["n_w"]
+    tq = otable(geom, dtype)
+    orc = oracle.compress(geom, tq, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"])
+    compare_runs(gr, orc)
+    err = rel_l2(G.cpu().numpy().astype(np.complex128), oracle.grid(geom, tq, orc))
+    rng = np.random.default_rng(13)
+    n = geom["n"]
+    g = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64)
+    out = gr.degrid(torch.as_tensor(g).to(DEV)).cpu().numpy().astype(np.complex128)
+    errd = rel_l2(out, oracle.degrid(geom, tq, orc, g.astype(np.complex128), data["uvw"], data["wt"],
+                                     data["vis"].shape))
+    say(f"  grid {err:.3e}, degrid {errd:.3e} against the oracle on the rounded table")
+    assert err < 1e-5 and errd < 1e-5
+
+
 def test_compressed_grid_matches_uncompressed_gpu():
     geom, data = cfg4_small()
     _, _, Gc = run_gpu(geom, data, compress=True)
