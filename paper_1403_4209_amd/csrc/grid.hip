@@ -701,15 +701,18 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
     const u16x2 mul_c = as_u16x2(in_vgpr((unsigned)a.n << 16 | 1u));
     float2 gv[NS][G][NP];        // grid values of the owned cells (0 for a class that does not exist)
+    unsigned vcell[NS][G];       // the cell whose values gv holds
     u16x2 wpos[kGroupSlots];     // footprint positions of the first classes, when the footprint moves
     unsigned gcell[kGroupSlots]; // first class's cell of the last run that moved the footprint
     unsigned last_cell0 = kNoCell;
 #pragma unroll
     for (int m = 0; m < NS; ++m)
 #pragma unroll
-        for (int h = 0; h < G; ++h)
+        for (int h = 0; h < G; ++h) {
+            vcell[m][h] = kNoCell;
 #pragma unroll
             for (int p = 0; p < NP; ++p) gv[m][h][p] = make_float2(0.f, 0.f);
+        }
 
     for (int base = rb; base < re; base += kWave) {
         const int n = min(kWave, re - base);
@@ -739,16 +742,23 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
                 st.k[m] = group_load<DT, G>(rs, (int)(m == NS - 1 ? off | idle_off : off));
             }
         };
-        // the grid values of the owned cells of the last run that moved the footprint; a
-        // class past the end of a row's short last group keeps the value 0
+        // the grid values of the owned cells of the last run that moved the footprint, loaded
+        // only for the classes whose cell changed: a footprint that moves by a cell changes the
+        // cells of one row or column of classes (1 in S of them), and a load instruction none
+        // of whose lanes changed is skipped; a class past the end of a row's short last group
+        // keeps the value 0
         auto load_values = [&]() {
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
-                load_cell<NP>(grid, gcell[m], a.cells, gv[m][0]);
                 const int wrap = S - (int)wpos[m].x;
 #pragma unroll
-                for (int h = 1; h < G; ++h)
-                    if (h < nval[m]) load_cell<NP>(grid, class_cell(gcell[m], h, wrap, S), a.cells, gv[m][h]);
+                for (int h = 0; h < G; ++h) {
+                    const unsigned c = class_cell(gcell[m], h, wrap, S);
+                    if (h < nval[m] && c != vcell[m][h]) {
+                        load_cell<NP>(grid, c, a.cells, gv[m][h]);
+                        vcell[m][h] = c;
+                    }
+                }
             }
         };
         // this wave's sums: lane l holds component l >> 5 (0 real, 1 imaginary) of run
