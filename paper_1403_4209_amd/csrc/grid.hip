@@ -379,10 +379,15 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
     // cell leaves writes that cell and its values to the wave's list in LDS (its place from
     // one ballot per class and mbcnt, so the list runs lane by lane, class by class: a row of
     // leaving cells stays a run of neighbouring cells, whereas one atomic per slot and class
-    // would cover every G-th cell), and the list is then added to the grid 64 entries per
-    // atomic instruction. Most moves commit one column of the footprint, a few lanes per
-    // slot: issued slot by slot, that took about a dozen atomic instructions with three or
-    // four active lanes each.
+    // would cover every G-th cell). Most moves commit one column of the footprint, a few
+    // lanes per slot: issued slot by slot, that took about a dozen atomic instructions with
+    // three or four active lanes each.
+    //
+    // The list is then added to the grid 32 entries per atomic instruction, lanes 2e and
+    // 2e + 1 taking the real and imaginary parts of entry e: one instruction covers the
+    // contiguous values of 32 neighbouring cells (two or three cache lines), where one lane
+    // per entry and one instruction per component touched twice as many lines, each half
+    // used; the L2's atomic cost goes by the lines an instruction touches.
     constexpr int kStride = G * NS * kWave;  // entries of one list array: every class of the wave
     static_assert(kStride * (1 + 2 * NP) <= commit_words<DT, NP>(), "commit list fits the wave's LDS");
     unsigned *cl_c = (unsigned *)cl_v;
@@ -417,13 +422,11 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
         for (int h = 0; h < G; ++h) nlist += (unsigned)__builtin_popcountll(bal[h]);
     };
     auto flush = [&]() {
-        for (unsigned e = (unsigned)lane; e < nlist; e += kWave) {
-            float *cell = a.grid + 2 * (int64_t)cl_c[e];
+        const unsigned comp = (unsigned)lane & 1u;
+        for (unsigned e = (unsigned)lane >> 1; e < nlist; e += kWave / 2) {
+            float *val = a.grid + (2u * cl_c[e] + comp);  // cell indices < 2^31
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                unsafeAtomicAdd(cell + 2 * p * a.cells, cl_v[kStride * (1 + 2 * p) + e]);
-                unsafeAtomicAdd(cell + 2 * p * a.cells + 1, cl_v[kStride * (2 + 2 * p) + e]);
-            }
+            for (int p = 0; p < NP; ++p) unsafeAtomicAdd(val + 2 * p * a.cells, cl_v[kStride * (1 + comp + 2 * p) + e]);
         }
         nlist = 0;
     };
