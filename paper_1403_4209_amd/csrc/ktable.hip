@@ -41,6 +41,15 @@ struct BuildArgs {
     double *tap;   // [M] taper at the image samples
 };
 
+// Work index of block b in a launch of `total` blocks: blocks are dealt to the 8 XCDs in
+// turn, so XCD x takes the x-th eighth of the work range (neighbouring lines and columns,
+// whose values share cache lines, then meet in one L2); the last total % 8 blocks keep
+// their own index.
+__device__ inline int xcd_work_index(int b, int total) {
+    const int q = total >> 3;
+    return b >= 8 * q ? b : (b & 7) * q + (b >> 3);
+}
+
 __device__ inline double plane_w(int k, int n_w, double w_max) {
     if (n_w == 1) return 0.0;
     double q = (double)k / (double)(n_w - 1);
@@ -212,7 +221,8 @@ template <int LGM>
 __global__ __launch_bounds__(128) void k_rows(BuildArgs a) {
     extern __shared__ double2 lds[];
     double2 *buf0 = lds, *xin = lds + a.L;
-    const int q = a.M / 2 + (int)blockIdx.x, k = blockIdx.y;
+    const int t = xcd_work_index((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+    const int q = a.M / 2 + t % (int)gridDim.x, k = t / (int)gridDim.x;
     const double xq = 2.0 * (double)(q - a.M / 2) / (double)a.M;
     const double m = xq / (2.0 * a.du);
     const double tq = a.tap[q];
@@ -285,8 +295,10 @@ __global__ __launch_bounds__(128) void k_cols(BuildArgs a) {
     extern __shared__ double2 lds[];
     constexpr bool kStage = (LGM + 3) / 4 >= 3;  // three or more passes: the column goes to LDS
     double2 *buf0 = lds, *xin = lds + a.L;
-    const int fu_b = (int)blockIdx.x == a.L / 2 ? -a.L / 2 : (int)blockIdx.x;
-    const int cu = fu_b + a.L / 2, k = blockIdx.y;
+    const int t = xcd_work_index((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+    const int bx = t % (int)gridDim.x, k = t / (int)gridDim.x;
+    const int fu_b = bx == a.L / 2 ? -a.L / 2 : bx;
+    const int cu = fu_b + a.L / 2;
     const double2 *in = a.A + ((size_t)k * a.L + cu) * a.M;
     if constexpr (kStage) {
         for (int q = threadIdx.x; q < a.M; q += blockDim.x) xin[q] = in[q];
@@ -372,7 +384,8 @@ __device__ inline uint16_t to_f16_bits(double x, double *rounded) {
 __global__ void k_slices(BuildArgs a, const int32_t *__restrict__ support,
                          const int64_t *__restrict__ offset, void *data, double *zeta) {
     __shared__ double red[256];
-    const int sigma = blockIdx.x, k = blockIdx.y;
+    const int t = xcd_work_index((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+    const int sigma = t % (int)gridDim.x, k = t / (int)gridDim.x;
     const int beta = a.beta;
     const int ov = sigma / beta - beta / 2 + 1, ou = sigma % beta - beta / 2 + 1;
     const int P = pad_of(a.dtype);
