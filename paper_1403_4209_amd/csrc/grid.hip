@@ -4,9 +4,10 @@
 // common support S) x one share of its cell classes. A class (p, q) stands for the grid
 // cells with y = p mod S and x = q mod S; every footprint position holds exactly one cell of
 // each class. Lane l owns a few classes: as the footprint slides along the trajectory the
-// lane keeps updating the same cell, accumulating gamma*K in registers with Kahan
-// compensation, and commits (one FP32 atomic add per component) only when the cell leaves
-// the footprint -- the ownership idea of Romein's gridder, applied per wavefront.
+// lane keeps updating the same cell, accumulating gamma*K in FP32 registers (the thesis's
+// gridder works in single precision throughout), and commits with FP32 atomic adds only when
+// the cell leaves the footprint -- the ownership idea of Romein's gridder, applied per
+// wavefront.
 //
 // Classes are owned in groups of neighbouring columns of one footprint row, as many as one
 // 16-byte load holds: pairs (q, q + 1) with FP32 tables, quads (q, ..., q + 3) with 16-bit
@@ -358,8 +359,8 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
     const unsigned idle_off = idle ? 0x80000000u : 0u;
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
     const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};  // cell offset in the grid
-    // per group slot, class h and polarisation: Kahan sum and compensation of the owned cell
-    float acc_r[NS][G][NP], acc_i[NS][G][NP], cmp_r[NS][G][NP], cmp_i[NS][G][NP];
+    // per group slot, class h and polarisation: the owned cell's sum since its last commit
+    float acc_r[NS][G][NP], acc_i[NS][G][NP];
     unsigned cur[kGroupSlots][G];  // owned cells (y*n + x); set from the chunk's first run
     // Footprint positions of the lane's first classes, recomputed only when the footprint moves
     // (consecutive runs of a chunk mostly differ in oversampling offsets or plane alone).
@@ -370,10 +371,8 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
 #pragma unroll
         for (int h = 0; h < G; ++h)
 #pragma unroll
-            for (int p = 0; p < NP; ++p) acc_r[m][h][p] = acc_i[m][h][p] = cmp_r[m][h][p] = cmp_i[m][h][p] = 0.f;
-    // Commit the cell's compensated sums (acc - cmp) of every polarisation; the next cell
-    // starts from acc = cmp, i.e. from the value zero, with the compensation term left as it
-    // is (Kahan's recurrence holds from any starting pair).
+            for (int p = 0; p < NP; ++p) acc_r[m][h][p] = acc_i[m][h][p] = 0.f;
+    // Commit the cell's sums of every polarisation; the next cell starts from zero.
     //
     // Commits are compacted. When the footprint moves, each (slot, class) of the wave whose
     // cell leaves writes that cell and its values to the wave's list in LDS (its place from
@@ -411,10 +410,10 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                 cl_c[e] = cur[m][h];
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
-                    cl_v[kStride * (1 + 2 * p) + e] = acc_r[m][h][p] - cmp_r[m][h][p];
-                    cl_v[kStride * (2 + 2 * p) + e] = acc_i[m][h][p] - cmp_i[m][h][p];
-                    acc_r[m][h][p] = cmp_r[m][h][p];
-                    acc_i[m][h][p] = cmp_i[m][h][p];
+                    cl_v[kStride * (1 + 2 * p) + e] = acc_r[m][h][p];
+                    cl_v[kStride * (2 + 2 * p) + e] = acc_i[m][h][p];
+                    acc_r[m][h][p] = 0.f;
+                    acc_i[m][h][p] = 0.f;
                 }
                 ++e;
             }
@@ -493,11 +492,9 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                 }
                 flush();
             }
-            // Kahan step with the product fused into the compensation:
-            // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t; one sample serves every
-            // polarisation. Class h takes sample h of the load, or sample G - 1 - h when the
-            // run reads backwards along u (one copy of the sums per case, under a wave-uniform
-            // branch).
+            // acc += gamma*K, two FMAs per component; one sample serves every polarisation.
+            // Class h takes sample h of the load, or sample G - 1 - h when the run reads
+            // backwards along u (one copy of the sums per case, under a wave-uniform branch).
             auto sums = [&](auto swapped) {
                 constexpr int sw = decltype(swapped)::value;
 #pragma unroll
@@ -507,13 +504,8 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                         const float2 kv = group_sample<DT, G>(st.k[m], sw ? G - 1 - h : h);
 #pragma unroll
                         for (int p = 0; p < NP; ++p) {
-                            const float yr = fmaf(gr[p], kv.x, -fmaf(gi[p], kv.y, cmp_r[m][h][p]));
-                            const float yi = fmaf(gr[p], kv.y, fmaf(gi[p], kv.x, -cmp_i[m][h][p]));
-                            const float tr = acc_r[m][h][p] + yr, ti = acc_i[m][h][p] + yi;
-                            cmp_r[m][h][p] = (tr - acc_r[m][h][p]) - yr;
-                            cmp_i[m][h][p] = (ti - acc_i[m][h][p]) - yi;
-                            acc_r[m][h][p] = tr;
-                            acc_i[m][h][p] = ti;
+                            acc_r[m][h][p] = fmaf(gr[p], kv.x, fmaf(-gi[p], kv.y, acc_r[m][h][p]));
+                            acc_i[m][h][p] = fmaf(gr[p], kv.y, fmaf(gi[p], kv.x, acc_i[m][h][p]));
                         }
                     }
             };

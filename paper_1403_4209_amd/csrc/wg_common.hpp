@@ -20,14 +20,14 @@ __host__ __device__ constexpr int pad_of(int dtype) { return group_of(dtype) - 1
 constexpr int kPadMax = 3;  // the widest padding (16-bit tables)
 
 // Groups per lane: the largest count any kernel instantiation uses, and the counts per
-// kernel, table type and polarisation count (measured; one more spills at 128 VGPRs where
-// noted).
+// kernel, table type and polarisation count (measured; the notes give what one more group
+// per lane did).
 constexpr int kGroupSlots = 3;
-constexpr int kGridGroups = 3;          // gridder, FP32 pairs, one polarisation (4 spill)
-constexpr int kGridGroupsNarrow = 2;    // gridder, 16-bit quads, one polarisation (3 take 183 VGPRs)
-constexpr int kGridGroupsPol2 = 2;      // gridder, FP32 pairs, two polarisations (3 spill)
-constexpr int kGridGroupsPol4 = 1;      // gridder, FP32 pairs, four polarisations (2 spill)
-constexpr int kGridGroupsNarrowPol = 1; // gridder, 16-bit tables: quads with two, pairs with four polarisations
+constexpr int kGridGroups = 3;          // gridder, FP32 pairs, one polarisation (4: 126 VGPRs, no faster)
+constexpr int kGridGroupsNarrow = 2;    // gridder, 16-bit quads, one polarisation (3: 139 VGPRs)
+constexpr int kGridGroupsPol2 = 2;      // gridder, FP32 pairs, two polarisations (3: 125 VGPRs, no faster)
+constexpr int kGridGroupsPol4 = 1;      // gridder, FP32 pairs, four polarisations (2: 126 VGPRs, no faster)
+constexpr int kGridGroupsNarrowPol = 1; // gridder, 16-bit tables: quads with two (2: 133 VGPRs), pairs with four polarisations
 constexpr int kDegridGroups = 3;        // degridder, FP32 pairs, one polarisation
 constexpr int kDegridGroupsNarrow = 3;  // degridder, 16-bit quads, one polarisation
 constexpr int kDegridGroupsPol = 3;     // degridder, FP32 pairs, two or four polarisations
