@@ -65,8 +65,8 @@ inline int64_t n_scan_tiles(int64_t n_seg) { return (n_seg + kScanTile - 1) / kS
 // Decomposition of a support-S local chunk into waves: the cell classes (y mod S, x mod S)
 // of footprint row p are grouped as (q, ..., q + G - 1) for q = 0, G, 2G, ... (the last group
 // of a row holds what is left of it), ceil(S / G) groups per row and S ceil(S / G) in all,
-// numbered row by row and spread evenly over nchunk_groups(S, G, slots) waves, at most
-// `slots` groups per lane.
+// numbered row by row and dealt in order to nchunk_groups(S, G, slots) waves, 64 x `slots`
+// groups to each but the last.
 __host__ __device__ inline int groups_per_row(int S, int G) { return (S + G - 1) / G; }
 __host__ __device__ inline int ngroups(int S, int G) { return S * groups_per_row(S, G); }
 __host__ __device__ inline int nchunk_groups(int S, int G, int slots) {
