@@ -14,8 +14,8 @@ times; the one-call wg_grid_records; BF16 and FP16 tables (times, speedups, and 
 errors against the FP64 oracle measured in the CPU-baseline leg); the uncompressed variant;
 the other throughput workloads (plain FP32, 2048^2; differentiation, 66.8 M records) as
 full steps; the table-generation study; w-stacking and polarisations; the image finaliser;
-the dominant kernel's roofline against the FP32 vector peak with its measured HBM traffic
-and VALU issue; and the CPU oracle baseline.
+the dominant kernel's roofline against the FP32 vector peak with its measured HBM traffic,
+vector memory issue interval and VALU instruction rate; and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -32,6 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2 (packed FP32) x 2.4 GHz
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FLOPS_PER_UPDATE = 8             # one complex multiply-add per grid-point update
+# CU cycles per 64-lane 16-byte vector load measured by a probe of loads from an L2-resident
+# table (60 B per CU-clock): the issue interval of the vector memory path
+VMEM_PROBE_CYCLES = 17.1
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "grid_cfg3_counters.txt")
 
 
@@ -76,14 +79,16 @@ def grid_source_hash() -> str:
 
 def read_counters():
     """Per-launch figures of k_grid and k_degrid from the committed rocprofv3 counter
-    summary (HBM bytes, VALU issue fraction, texture-data unit busy fraction), or {} when the
-    gridder's sources have changed since the counters were taken."""
+    summary (HBM bytes, VALU instructions per SIMD-cycle, CU cycles per vector memory
+    instruction, texture-data unit busy fraction), or {} when the gridder's sources have
+    changed since the counters were taken."""
     try:
         with open(PROFILE_COUNTERS) as f:
             kv = {k.strip(): v.strip() for k, v in (line.split(":", 1) for line in f if ":" in line)}
         if kv["grid_sources_sha256_16"].split()[0] != grid_source_hash():
             return {}
-        return {k: float(v.split()[0]) for k, v in kv.items() if k.startswith(("traffic_", "valu_issue_", "td_busy_"))}
+        return {k: float(v.split()[0]) for k, v in kv.items()
+                if k.startswith(("traffic_", "valu_ipc_", "vmem_cycles_per_inst_", "td_busy_"))}
     except Exception:
         return {}
 
@@ -91,8 +96,9 @@ def read_counters():
 def roofline(kernel, updates, ms, counters):
     """The kernel against the FP32 vector peak (gridding is a scatter of 8-flop complex
     multiply-adds whose table samples the caches serve), with its measured HBM traffic per
-    launch and the VALU issue and vector-memory (texture-data unit) busy fractions from the
-    counter summary."""
+    launch and, from the counter summary, what binds it: the vector memory instruction rate
+    (CU cycles per instruction against the about 17 of a probe of 16-byte loads from L2) and
+    the VALU instruction rate."""
     tf = FLOPS_PER_UPDATE * updates / (ms * 1e-3) / 1e12
     key = "k_grid" if kernel.startswith("k_grid") else "k_degrid"
     traffic = counters.get(f"traffic_{key}")
@@ -102,11 +108,15 @@ def roofline(kernel, updates, ms, counters):
         gbs = traffic / (ms * 1e-3) / 1e9
         out["hbm_measured"] = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    if f"valu_issue_{key}" in counters:
-        out["valu_issue_frac"] = counters[f"valu_issue_{key}"]
+    if f"vmem_cycles_per_inst_{key}" in counters:
+        c = counters[f"vmem_cycles_per_inst_{key}"]
+        out["vmem_issue"] = {"cycles_per_inst": c, "probe_cycles_per_inst": VMEM_PROBE_CYCLES,
+                             "frac": round(VMEM_PROBE_CYCLES / c, 4)}
     if f"td_busy_{key}" in counters:
         # the vector memory path: fraction of cycles the texture-data units are busy
         out["vmem_td_busy_frac"] = counters[f"td_busy_{key}"]
+    if f"valu_ipc_{key}" in counters:
+        out["valu_insts_per_simd_cycle"] = counters[f"valu_ipc_{key}"]
     return out
 
 
