@@ -10,8 +10,9 @@ visibilities) and resident in HBM before timing starts.
 
 Prints ONE JSON line. `value` = grid-point updates per second over the step (the gridder's
 updates plus the degridder's, each the sum over runs of S^2). Extra fields: per-phase
-times; the one-call wg_grid_records; BF16 and FP16 tables (times, speedups, and their
-errors against the FP64 oracle measured in the CPU-baseline leg); the uncompressed variant;
+times; the one-call wg_grid_records; BF16 and FP16 tables and the thesis's plain FP32 sums
+per owned cell (times, speedups, and their errors against the FP64 oracle measured in the
+CPU-baseline leg); the uncompressed variant;
 the other throughput workloads (plain FP32, 2048^2; differentiation, 66.8 M records) as
 full steps; the table-generation study; w-stacking and polarisations; the image finaliser;
 the dominant kernel's roofline against the FP32 vector peak with its measured HBM traffic,
@@ -388,6 +389,15 @@ def main():
                              "full_grid_vs_f32_table_grid": rel_err(cd.grid, g32)}
             extra_tables[dt] = cd.table
             del cd
+        # the thesis's plain FP32 sums per owned cell (WG_PLAIN_SUMS) with the FP32 table
+        cp = Case(w, table=c.table, plain_sums=True)
+        tg, td = cp.time_grid_degrid(args.steps)
+        precision["f32_plain_sums"] = {"grid_ms": round(tg, 4), "degrid_ms": round(td, 4),
+                                       "grid_gupds_real": round(U / (tg * 1e-3) / 1e9, 2),
+                                       "speedup_grid_vs_f32": round(t_grid / tg, 3),
+                                       "full_grid_vs_f32_table_grid": rel_err(cp.grid, g32)}
+        extra_tables["f32_plain_sums"] = c.table
+        del cp
         out["precision"] = precision
 
         # compression off: every griddable record is its own run
@@ -582,7 +592,8 @@ def main():
             f32 = wg.KernelTable(base, "f32", device=dev) if tables["f32"] is None else tables["f32"]
             for dt in tables:
                 tb = f32 if dt == "f32" else tables[dt]
-                g = wg.Gridder(base, tb, torch.as_tensor(uvw_s).to(dev), torch.as_tensor(w.inv_lambda).to(dev))
+                g = wg.Gridder(wg.geom_from_dict(w.geom, plain_sums=dt == "f32_plain_sums"), tb,
+                               torch.as_tensor(uvw_s).to(dev), torch.as_tensor(w.inv_lambda).to(dev))
                 grids[dt] = g.grid_records(torch.as_tensor(vis_s).to(dev))
             torch.cuda.synchronize()
             return grids

@@ -69,6 +69,9 @@ typedef enum wg_kdtype {
 #define WG_POL_CIRCULAR 8u     /* the records' products are RR, RL, LR, LL (or RR, LL) rather
                                   than XX, XY, YX, YY (or XX, YY); used by wg_finalise's Stokes
                                   conversion only                                              */
+#define WG_PLAIN_SUMS 16u      /* wg_grid: plain FP32 sums per owned cell between commits, as the
+                                  thesis's single-precision gridder; without it the sums are
+                                  Kahan-compensated                                            */
 #define WG_W_STACKING 4u       /* w-stacking (eq. stacking): one grid per w-plane, every record
                                   gridded with the w = 0 kernel (plane 0's support, slices and
                                   zeta) on the grid of its w-plane; the w-term is applied in the
@@ -94,8 +97,9 @@ typedef enum wg_kdtype {
  *           beta*m_img <= WG_MAX_FFT, and (s_hi-1)/2*beta + beta/2 < beta*m_img/2).
  *   du      uv cell size in wavelengths (> 0); the image field of view is 1/du.
  *   w_max   largest |w| tabulated, wavelengths (>= 0).
- *   flags   WG_COMPRESS, WG_POL_CIRCULAR, and at most one of WG_GRID_PER_CHANNEL and
- *           WG_W_STACKING; or 0 (unknown bits or both grid modes: WG_EINVAL).
+ *   flags   WG_COMPRESS, WG_POL_CIRCULAR, WG_PLAIN_SUMS, and at most one of
+ *           WG_GRID_PER_CHANNEL and WG_W_STACKING; or 0 (unknown bits or both grid modes:
+ *           WG_EINVAL).
  *   n_pol   polarisations per record P: 1 (0 is read as 1), 2 (the parallel hands XX, YY or
  *           RR, LL) or 4 (XX, XY, YX, YY or RR, RL, LR, LL), in that order; others are
  *           WG_EINVAL.
@@ -267,9 +271,10 @@ int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const 
  * gamma[p] * K[i][j] with
  * a = x + n/2 - H, row0 = y + n/2 - H, K the run's matrix. ACCUMULATES into `grid`
  * (complex64 [P][n][n], or [nc][P][n][n] with WG_GRID_PER_CHANNEL or [n_w][P][n][n]
- * with WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first. Accumulation is FP32, as in the
- * thesis's single-precision gridder: plain sums per owned cell between commits, and
- * commits with FP32 atomic adds, so the last bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
+ * with WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first. Accumulation is FP32: Kahan-
+ * compensated sums per owned cell between commits (plain sums with g->flags & WG_PLAIN_SUMS,
+ * as in the thesis's single-precision gridder), and commits with FP32 atomic adds, so the last
+ * bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
  * Errors: WG_EINVAL, WG_EUNSUPPORTED (kt->data_cap >= 2^28 elements: table byte offsets
  * are 32-bit), WG_EHIP.
  */

@@ -11,7 +11,8 @@ int check_geom(const wg_geom *g) {
     if (g->s_lo < 1 || g->s_hi < g->s_lo || !(g->s_lo & 1) || !(g->s_hi & 1)) return WG_EINVAL;
     if (!(g->du > 0.0) || !(g->w_max >= 0.0) || g->du != g->du) return WG_EINVAL;
     if (g->m_img < 16 || !is_pow2(g->m_img)) return WG_EINVAL;
-    if ((g->flags & ~(WG_COMPRESS | WG_GRID_PER_CHANNEL | WG_W_STACKING | WG_POL_CIRCULAR)) != 0) return WG_EINVAL;
+    if ((g->flags & ~(WG_COMPRESS | WG_GRID_PER_CHANNEL | WG_W_STACKING | WG_POL_CIRCULAR | WG_PLAIN_SUMS)) != 0)
+        return WG_EINVAL;
     if ((g->flags & WG_GRID_PER_CHANNEL) && (g->flags & WG_W_STACKING)) return WG_EINVAL;
     if (g->n_pol != 0 && g->n_pol != 1 && g->n_pol != 2 && g->n_pol != 4) return WG_EINVAL;
     if (g->n > 32768 || g->beta > 32 || g->n_w > WG_MAX_PLANES || g->s_hi > WG_MAX_SUPPORT)

@@ -4,10 +4,10 @@
 // common support S) x one share of its cell classes. A class (p, q) stands for the grid
 // cells with y = p mod S and x = q mod S; every footprint position holds exactly one cell of
 // each class. Lane l owns a few classes: as the footprint slides along the trajectory the
-// lane keeps updating the same cell, accumulating gamma*K in FP32 registers (the thesis's
-// gridder works in single precision throughout), and commits with FP32 atomic adds only when
-// the cell leaves the footprint -- the ownership idea of Romein's gridder, applied per
-// wavefront.
+// lane keeps updating the same cell, accumulating gamma*K in FP32 registers with Kahan
+// compensation (or, on request, plain FP32 sums as in the thesis's single-precision gridder),
+// and commits with FP32 atomic adds only when the cell leaves the footprint -- the ownership
+// idea of Romein's gridder, applied per wavefront.
 //
 // Classes are owned in groups of neighbouring columns of one footprint row, as many as one
 // 16-byte load holds: pairs (q, q + 1) with FP32 tables, quads (q, ..., q + 3) with 16-bit
@@ -343,7 +343,8 @@ constexpr int grid_slots();
 template <int DT, int NP>
 constexpr int commit_words() { return kgroup<DT, NP>() * grid_slots<DT, NP>() * kWave * (1 + 2 * NP); }
 
-template <int DT, int NP, int NS>
+// KAHAN: compensated sums per owned cell, else plain FP32 sums.
+template <int DT, int NP, int NS, bool KAHAN>
 __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int S, int k0, int k1, int rb, int re,
                                                              int lane, const int64_t *koff, float *cl_v) {
     constexpr int esz = (DT == WG_KF32) ? 8 : 4;
@@ -360,7 +361,8 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
     const u16x2 ss = {(unsigned short)S, (unsigned short)S};
     const u16x2 mul_c = {(unsigned short)1, (unsigned short)a.n};  // cell offset in the grid
     // per group slot, class h and polarisation: the owned cell's sum since its last commit
-    float acc_r[NS][G][NP], acc_i[NS][G][NP];
+    // and its Kahan compensation (zero throughout with plain sums)
+    float acc_r[NS][G][NP], acc_i[NS][G][NP], cmp_r[NS][G][NP], cmp_i[NS][G][NP];
     unsigned cur[kGroupSlots][G];  // owned cells (y*n + x); set from the chunk's first run
     // Footprint positions of the lane's first classes, recomputed only when the footprint moves
     // (consecutive runs of a chunk mostly differ in oversampling offsets or plane alone).
@@ -371,8 +373,10 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
 #pragma unroll
         for (int h = 0; h < G; ++h)
 #pragma unroll
-            for (int p = 0; p < NP; ++p) acc_r[m][h][p] = acc_i[m][h][p] = 0.f;
-    // Commit the cell's sums of every polarisation; the next cell starts from zero.
+            for (int p = 0; p < NP; ++p) acc_r[m][h][p] = acc_i[m][h][p] = cmp_r[m][h][p] = cmp_i[m][h][p] = 0.f;
+    // Commit the cell's compensated sums (acc - cmp) of every polarisation; the next cell
+    // starts from acc = cmp, i.e. from the value zero, with the compensation term left as it
+    // is (Kahan's recurrence holds from any starting pair). With plain sums cmp stays zero.
     //
     // Commits are compacted. When the footprint moves, each (slot, class) of the wave whose
     // cell leaves writes that cell and its values to the wave's list in LDS (its place from
@@ -410,10 +414,10 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                 cl_c[e] = cur[m][h];
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
-                    cl_v[kStride * (1 + 2 * p) + e] = acc_r[m][h][p];
-                    cl_v[kStride * (2 + 2 * p) + e] = acc_i[m][h][p];
-                    acc_r[m][h][p] = 0.f;
-                    acc_i[m][h][p] = 0.f;
+                    cl_v[kStride * (1 + 2 * p) + e] = acc_r[m][h][p] - cmp_r[m][h][p];
+                    cl_v[kStride * (2 + 2 * p) + e] = acc_i[m][h][p] - cmp_i[m][h][p];
+                    acc_r[m][h][p] = cmp_r[m][h][p];
+                    acc_i[m][h][p] = cmp_i[m][h][p];
                 }
                 ++e;
             }
@@ -492,7 +496,9 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                 }
                 flush();
             }
-            // acc += gamma*K, two FMAs per component; one sample serves every polarisation.
+            // Kahan step with the product fused into the compensation:
+            // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t; with plain sums
+            // s += gamma*K, two FMAs per component. One sample serves every polarisation.
             // Class h takes sample h of the load, or sample G - 1 - h when the run reads
             // backwards along u (one copy of the sums per case, under a wave-uniform branch).
             auto sums = [&](auto swapped) {
@@ -504,8 +510,18 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                         const float2 kv = group_sample<DT, G>(st.k[m], sw ? G - 1 - h : h);
 #pragma unroll
                         for (int p = 0; p < NP; ++p) {
-                            acc_r[m][h][p] = fmaf(gr[p], kv.x, fmaf(-gi[p], kv.y, acc_r[m][h][p]));
-                            acc_i[m][h][p] = fmaf(gr[p], kv.y, fmaf(gi[p], kv.x, acc_i[m][h][p]));
+                            if constexpr (KAHAN) {
+                                const float yr = fmaf(gr[p], kv.x, -fmaf(gi[p], kv.y, cmp_r[m][h][p]));
+                                const float yi = fmaf(gr[p], kv.y, fmaf(gi[p], kv.x, -cmp_i[m][h][p]));
+                                const float tr = acc_r[m][h][p] + yr, ti = acc_i[m][h][p] + yi;
+                                cmp_r[m][h][p] = (tr - acc_r[m][h][p]) - yr;
+                                cmp_i[m][h][p] = (ti - acc_i[m][h][p]) - yi;
+                                acc_r[m][h][p] = tr;
+                                acc_i[m][h][p] = ti;
+                            } else {
+                                acc_r[m][h][p] = fmaf(gr[p], kv.x, fmaf(-gi[p], kv.y, acc_r[m][h][p]));
+                                acc_i[m][h][p] = fmaf(gr[p], kv.y, fmaf(gi[p], kv.x, acc_i[m][h][p]));
+                            }
                         }
                     }
             };
@@ -570,17 +586,17 @@ __device__ inline void chunk_groups(int S, int G, int chunk, int slots, int &k0,
 
 // Slot count as a template parameter, instantiated for 1..MAX only (the kernel's register
 // allocation is the largest over its instantiations).
-template <int DT, int NP, int NS, int MAX>
+template <int DT, int NP, int NS, int MAX, bool KAHAN>
 __device__ __attribute__((always_inline)) inline void grid_dispatch(int ns, const GArgs &a, int S, int c0, int c1, int rb, int re, int lane,
                                      const int64_t *koff, float *cl) {
     if constexpr (NS < MAX) {
         if (ns == NS) {
-            grid_chunk_ns<DT, NP, NS>(a, S, c0, c1, rb, re, lane, koff, cl);
+            grid_chunk_ns<DT, NP, NS, KAHAN>(a, S, c0, c1, rb, re, lane, koff, cl);
             return;
         }
-        grid_dispatch<DT, NP, NS + 1, MAX>(ns, a, S, c0, c1, rb, re, lane, koff, cl);
+        grid_dispatch<DT, NP, NS + 1, MAX, KAHAN>(ns, a, S, c0, c1, rb, re, lane, koff, cl);
     } else {
-        grid_chunk_ns<DT, NP, MAX>(a, S, c0, c1, rb, re, lane, koff, cl);
+        grid_chunk_ns<DT, NP, MAX, KAHAN>(a, S, c0, c1, rb, re, lane, koff, cl);
     }
 }
 
@@ -594,17 +610,17 @@ constexpr int grid_slots() {
         return NP == 1 ? kGridGroupsNarrow : kGridGroupsNarrowPol;
 }
 
-template <int DT, int NP>
+template <int DT, int NP, bool KAHAN>
 __device__ __attribute__((always_inline)) void grid_chunk(const GArgs &a, int S, int chunk, int rb, int re, int lane,
                                                           const int64_t *koff, float *cl) {
     int k0, k1, ns;
     chunk_groups(S, kgroup<DT, NP>(), chunk, grid_slots<DT, NP>(), k0, k1, ns);
-    grid_dispatch<DT, NP, 1, grid_slots<DT, NP>()>(ns, a, S, k0, k1, rb, re, lane, koff, cl);
+    grid_dispatch<DT, NP, 1, grid_slots<DT, NP>(), KAHAN>(ns, a, S, k0, k1, rb, re, lane, koff, cl);
 }
 
 // COUNTER: the work list is walked through the counter in a.queue, else statically (one
-// walk per instantiation, so the unit body is inlined once).
-template <int DT, int NP, bool COUNTER>
+// walk per instantiation, so the unit body is inlined once). KAHAN: compensated sums.
+template <int DT, int NP, bool COUNTER, bool KAHAN>
 __global__ __launch_bounds__(256, 4) void k_grid(GArgs a) {
     __shared__ UnitTable ut;
     __shared__ int64_t koff[WG_MAX_PLANES + 1];
@@ -622,7 +638,7 @@ __global__ __launch_bounds__(256, 4) void k_grid(GArgs a) {
         const int rel = u - uni(ut.first[m]);
         const int item = rel / nch, chunk = rel - item * nch;
         const int slot = uni(a.plan[kPlanOff + sidx(S)]) + item;
-        grid_chunk<DT, NP>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff, cl);
+        grid_chunk<DT, NP, KAHAN>(a, S, chunk, uni(a.items[2 * slot]), uni(a.items[2 * slot + 1]), lane, koff, cl);
     };
     if constexpr (COUNTER)
         for_each_unit(nunits, a.queue, unit);
@@ -992,19 +1008,22 @@ constexpr int kGridCounterBlocks = 1024;
 // 64 planes, 11.9 M runs: 10.8 ms against 11.8; 2048^2, 32 planes: 3.6 against 3.1 ms.
 constexpr int kGridCounterMinSide = 4096;
 
-// The gridder for a table type, polarisation count and walk.
-template <int DT, bool COUNTER>
+// The gridder for a table type, polarisation count, walk and summation.
+template <int DT, bool COUNTER, bool KAHAN>
 void (*pick_grid_np(int npol))(GArgs) {
-    return npol == 4 ? k_grid<DT, 4, COUNTER> : npol == 2 ? k_grid<DT, 2, COUNTER> : k_grid<DT, 1, COUNTER>;
+    return npol == 4   ? k_grid<DT, 4, COUNTER, KAHAN>
+           : npol == 2 ? k_grid<DT, 2, COUNTER, KAHAN>
+                       : k_grid<DT, 1, COUNTER, KAHAN>;
 }
-template <bool COUNTER>
+template <bool COUNTER, bool KAHAN>
 void (*pick_grid_dt(int dtype, int npol))(GArgs) {
-    return dtype == WG_KF32    ? pick_grid_np<WG_KF32, COUNTER>(npol)
-           : dtype == WG_KBF16 ? pick_grid_np<WG_KBF16, COUNTER>(npol)
-                               : pick_grid_np<WG_KF16, COUNTER>(npol);
+    return dtype == WG_KF32    ? pick_grid_np<WG_KF32, COUNTER, KAHAN>(npol)
+           : dtype == WG_KBF16 ? pick_grid_np<WG_KBF16, COUNTER, KAHAN>(npol)
+                               : pick_grid_np<WG_KF16, COUNTER, KAHAN>(npol);
 }
-void (*pick_grid(int dtype, int npol, bool counter))(GArgs) {
-    return counter ? pick_grid_dt<true>(dtype, npol) : pick_grid_dt<false>(dtype, npol);
+void (*pick_grid(int dtype, int npol, bool counter, bool kahan))(GArgs) {
+    if (kahan) return counter ? pick_grid_dt<true, true>(dtype, npol) : pick_grid_dt<false, true>(dtype, npol);
+    return counter ? pick_grid_dt<true, false>(dtype, npol) : pick_grid_dt<false, false>(dtype, npol);
 }
 
 // The degridder kernel for a table type and polarisation count.
@@ -1033,8 +1052,8 @@ extern "C" int wg_grid(const wg_geom *g, const wg_ktable *kt, const wg_runs *run
     const bool counter = g->n >= kGridCounterMinSide;
     a.queue = counter ? runs->plan + kPlanQueueGrid : nullptr;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(pick_grid(kt->dtype, a.npol, counter), dim3(counter ? kGridCounterBlocks : kGridBlocks),
-                       dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pick_grid(kt->dtype, a.npol, counter, !(g->flags & WG_PLAIN_SUMS)),
+                       dim3(counter ? kGridCounterBlocks : kGridBlocks), dim3(256), 0, s, a);
     return launch_status();
 }
 

@@ -26,6 +26,7 @@ WG_COMPRESS = 1
 WG_GRID_PER_CHANNEL = 2
 WG_W_STACKING = 4
 WG_POL_CIRCULAR = 8
+WG_PLAIN_SUMS = 16
 DTYPES = {"f32": WG_KF32, "bf16": WG_KBF16, "f16": WG_KF16}
 _ELEM_BYTES = {WG_KF32: 8, WG_KBF16: 4, WG_KF16: 4}
 
@@ -245,16 +246,18 @@ def finalise(geom: WgGeom, grid: torch.Tensor, normaliser: torch.Tensor, out=Non
 
 # -------------------------------------------------------------------------- owning helpers
 def make_geom(n, beta, n_w, s_lo, s_hi, m_img, du, w_max, compress=True, per_channel=False,
-              w_stacking=False, n_pol=1, circular=False) -> WgGeom:
+              w_stacking=False, n_pol=1, circular=False, plain_sums=False) -> WgGeom:
     flags = ((WG_COMPRESS if compress else 0) | (WG_GRID_PER_CHANNEL if per_channel else 0)
-             | (WG_W_STACKING if w_stacking else 0) | (WG_POL_CIRCULAR if circular else 0))
+             | (WG_W_STACKING if w_stacking else 0) | (WG_POL_CIRCULAR if circular else 0)
+             | (WG_PLAIN_SUMS if plain_sums else 0))
     return WgGeom(int(n), int(beta), int(n_w), int(s_lo), int(s_hi), int(m_img), float(du), float(w_max), flags,
                   int(n_pol))
 
 
-def geom_from_dict(d: dict, compress=True, per_channel=False, w_stacking=False, n_pol=1, circular=False) -> WgGeom:
+def geom_from_dict(d: dict, compress=True, per_channel=False, w_stacking=False, n_pol=1, circular=False,
+                   plain_sums=False) -> WgGeom:
     return make_geom(d["n"], d["beta"], d["n_w"], d["s_lo"], d["s_hi"], d["m_img"], d["du"], d["w_max"], compress,
-                     per_channel, w_stacking, n_pol, circular)
+                     per_channel, w_stacking, n_pol, circular, plain_sums)
 
 
 class KernelTable:

@@ -44,6 +44,10 @@ def test_status_strings_and_version(wg):
     assert wg.wg_version() >= 100
 
 
+def elems_f32_s63(wg):
+    return 32 * 64 * 63 * 69
+
+
 def test_ktable_sizes_and_geometry_validation(wg):
     g = wg.make_geom(2048, 8, 32, 9, 63, 256, 60.0, 3.0e4)
     elems, ws = wg.wg_ktable_sizes(g)
@@ -51,7 +55,14 @@ def test_ktable_sizes_and_geometry_validation(wg):
     # the largest support: a 2048-point oversampled plane (beta 4, 512 image samples) holds it
     elems, ws = wg.wg_ktable_sizes(wg.make_geom(4500, 4, 16, 9, 511, 512, 1.0, 3.0e4))
     assert elems == 16 * 16 * 511 * 517 and ws > 0
+    # every defined flag is accepted, with the plain-sums switch among them
+    assert wg.wg_ktable_sizes(wg.make_geom(2048, 8, 32, 9, 63, 256, 60.0, 3.0e4, per_channel=True,
+                                           circular=True, plain_sums=True))[0] == elems_f32_s63(wg)
+    unknown = wg.make_geom(2048, 8, 32, 9, 63, 256, 60.0, 3.0e4)
+    unknown.flags |= 32
     bad = [
+        unknown,                                               # an undefined flag bit
+        wg.make_geom(2048, 8, 32, 9, 63, 256, 60.0, 3.0e4, per_channel=True, w_stacking=True),  # both grid modes
         wg.make_geom(2047, 8, 32, 9, 63, 256, 60.0, 3.0e4),   # odd N
         wg.make_geom(2048, 6, 32, 9, 63, 256, 60.0, 3.0e4),   # beta not a power of two
         wg.make_geom(2048, 8, 32, 8, 63, 256, 60.0, 3.0e4),   # even support
@@ -134,7 +145,7 @@ def test_per_channel_grids_need_their_arrays(wg):
     g2 = wg.make_geom(8192, 8, 8, 7, 7, 256, 15.0, 100.0, per_channel=True)
     assert L.wg_compress(by(g2), by(kt), 1, 1, 1, None, None, 1, 32, 1, by(big), 1, None) == wg.WG_EUNSUPPORTED
     g_bad = wg.make_geom(256, 8, 8, 7, 7, 256, 15.0, 100.0)
-    g_bad.flags = 16
+    g_bad.flags = 32  # an undefined bit
     size = ctypes.c_int64(0), ctypes.c_size_t(0)
     assert L.wg_ktable_sizes(by(g_bad), by(size[0]), by(size[1])) == wg.WG_EINVAL
 

@@ -250,6 +250,37 @@ def test_grid_parity(case, dtype, tol):
     assert err_acc < 1e-5
 
 
+@pytest.mark.parametrize("case,npol,dtype", [("cfg1", 1, "f32"), ("cfg4", 1, "f32"), ("cfg4", 1, "bf16"),
+                                           ("cfg4", 4, "f32"), ("cfg1", 2, "f16")])
+def test_plain_sums_match_oracle(case, npol, dtype):
+    """WG_PLAIN_SUMS (plain FP32 sums per owned cell, the thesis's single-precision gridder):
+    the grid within the table type's bar of the FP64 oracle (1e-5 FP32, 3e-3 BF16, 1e-3 FP16),
+    within 1e-5 of the oracle on the same rounded table, and within 1e-5 of the default
+    Kahan-compensated grid of the same runs."""
+    if npol == 1:
+        geom, data = cfg1() if case == "cfg1" else cfg4_small()
+    else:
+        geom, data = _pol_case(case, npol, False)
+    say("plain sums", case, npol, dtype)
+    tol = {"f32": 1e-5, "bf16": 3e-3, "f16": 1e-3}[dtype]
+    uvw, il, vis, wt, fl = to_dev(data)
+    grids = {}
+    for plain in (False, True):
+        g = wg.geom_from_dict(geom, n_pol=npol, plain_sums=plain)
+        table = wg.KernelTable(g, dtype, device=DEV)
+        gr = wg.Gridder(g, table, uvw, il, wt, fl)
+        gr.compress(vis)
+        grids[plain] = gr.grid().cpu().numpy().astype(np.complex128)
+    t64, tq = otable(geom, "f64"), otable(geom, dtype)
+    Go = oracle.grid(geom, t64, oracle.compress(geom, t64, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"]))
+    Gq = oracle.grid(geom, tq, oracle.compress(geom, tq, data["uvw"], data["il"], data["vis"], data["wt"], data["flag"]))
+    err, err_q, err_k = rel_l2(grids[True], Go), rel_l2(grids[True], Gq), rel_l2(grids[True], grids[False])
+    say(f"  rel L2 vs FP64 oracle {err:.3e}; vs oracle on the rounded table {err_q:.3e}; vs Kahan {err_k:.3e}")
+    assert err < tol
+    assert err_q < 1e-5
+    assert err_k < 1e-5
+
+
 @pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 3e-3)])
 def test_large_supports_match_oracle(dtype, tol):
     """Supports of 101 to 349 (beyond 63: the plan's per-support words, the gridder's unit
