@@ -471,7 +471,7 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
         // carries gamma = 0: its step adds zero, so the loop needs no branch on it. Such a
         // failed run counts as moved, with cells inside the first grid's corner, so the next
         // good run commits what was held there (zero) and moves on.
-        auto accumulate = [&](int t, const Stage<DT, G> &st) {
+        auto accumulate = [&](int t, const Stage<DT, G> &st, auto fold) {
             float gr[NP], gi[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
@@ -497,7 +497,10 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                 flush();
             }
             // Kahan step with the product fused into the compensation:
-            // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t; with plain sums
+            // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t, in blocks of two runs: the
+            // first run of each pair (`fold`) only subtracts its product from c (two FMAs per
+            // component), and the second run's full step absorbs both (the value, s - c, is
+            // right after either run, so a commit may come between them). With plain sums
             // s += gamma*K, two FMAs per component. One sample serves every polarisation.
             // Class h takes sample h of the load, or sample G - 1 - h when the run reads
             // backwards along u (one copy of the sums per case, under a wave-uniform branch).
@@ -510,7 +513,10 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
                         const float2 kv = group_sample<DT, G>(st.k[m], sw ? G - 1 - h : h);
 #pragma unroll
                         for (int p = 0; p < NP; ++p) {
-                            if constexpr (KAHAN) {
+                            if constexpr (KAHAN && decltype(fold)::value) {
+                                cmp_r[m][h][p] = fmaf(-gr[p], kv.x, fmaf(gi[p], kv.y, cmp_r[m][h][p]));
+                                cmp_i[m][h][p] = fmaf(-gr[p], kv.y, fmaf(-gi[p], kv.x, cmp_i[m][h][p]));
+                            } else if constexpr (KAHAN) {
                                 const float yr = fmaf(gr[p], kv.x, -fmaf(gi[p], kv.y, cmp_r[m][h][p]));
                                 const float yi = fmaf(gr[p], kv.y, fmaf(gi[p], kv.x, -cmp_i[m][h][p]));
                                 const float tr = acc_r[m][h][p] + yr, ti = acc_i[m][h][p] + yi;
@@ -554,10 +560,10 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
         for (int t = 0; t < n; t += 2) {
             fetch(min(t + 1, n - 1), sb);
             __builtin_amdgcn_sched_barrier(0);
-            accumulate(t, sa);
+            accumulate(t, sa, std::true_type{});
             fetch(min(t + 2, n - 1), sa);
             __builtin_amdgcn_sched_barrier(0);
-            accumulate(t + 1, sb);
+            accumulate(t + 1, sb, std::false_type{});
         }
     }
     if (!first) {
