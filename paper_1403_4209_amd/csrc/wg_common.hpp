@@ -21,13 +21,14 @@ constexpr int kPadMax = 3;  // the widest padding (16-bit tables)
 
 // Groups per lane: the largest count any kernel instantiation uses, and the counts per
 // kernel, table type and polarisation count (measured; the notes give what one more group
-// per lane did).
+// per lane did: with Kahan sums it spills at the 128-VGPR cap, with plain sums it fits at
+// the VGPRs given and was no faster, or does not fit).
 constexpr int kGroupSlots = 3;
-constexpr int kGridGroups = 3;          // gridder, FP32 pairs, one polarisation (4: 126 VGPRs, no faster)
-constexpr int kGridGroupsNarrow = 2;    // gridder, 16-bit quads, one polarisation (3: 139 VGPRs)
-constexpr int kGridGroupsPol2 = 2;      // gridder, FP32 pairs, two polarisations (3: 125 VGPRs, no faster)
-constexpr int kGridGroupsPol4 = 1;      // gridder, FP32 pairs, four polarisations (2: 126 VGPRs, no faster)
-constexpr int kGridGroupsNarrowPol = 1; // gridder, 16-bit tables: quads with two (2: 133 VGPRs), pairs with four polarisations
+constexpr int kGridGroups = 3;          // gridder, FP32 pairs, one polarisation (4: 126 VGPRs plain)
+constexpr int kGridGroupsNarrow = 2;    // gridder, 16-bit quads, one polarisation (3: 139 VGPRs plain)
+constexpr int kGridGroupsPol2 = 2;      // gridder, FP32 pairs, two polarisations (3: 125 VGPRs plain)
+constexpr int kGridGroupsPol4 = 1;      // gridder, FP32 pairs, four polarisations (2: 126 VGPRs plain)
+constexpr int kGridGroupsNarrowPol = 1; // gridder, 16-bit tables: quads with two (2: 133 VGPRs plain), pairs with four polarisations
 constexpr int kDegridGroups = 3;        // degridder, FP32 pairs, one polarisation
 constexpr int kDegridGroupsNarrow = 3;  // degridder, 16-bit quads, one polarisation
 constexpr int kDegridGroupsPol = 3;     // degridder, FP32 pairs, two or four polarisations
