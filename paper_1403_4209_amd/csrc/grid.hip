@@ -339,9 +339,10 @@ template <int DT, int NP>
 constexpr int grid_slots();
 
 // Words of one wave's commit list (the cells of one footprint move, and their real and
-// imaginary values per polarisation): one entry per class the wave owns.
+// imaginary values per polarisation): one entry per class the wave owns, and 32 more for
+// the entries an earlier move left for the next one.
 template <int DT, int NP>
-constexpr int commit_words() { return kgroup<DT, NP>() * grid_slots<DT, NP>() * kWave * (1 + 2 * NP); }
+constexpr int commit_words() { return (kgroup<DT, NP>() * grid_slots<DT, NP>() * kWave + 32) * (1 + 2 * NP); }
 
 // KAHAN: compensated sums per owned cell, else plain FP32 sums.
 template <int DT, int NP, int NS, bool KAHAN>
@@ -390,8 +391,12 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
     // 2e + 1 taking the real and imaginary parts of entry e: one instruction covers the
     // contiguous values of 32 neighbouring cells (two or three cache lines), where one lane
     // per entry and one instruction per component touched twice as many lines, each half
-    // used; the L2's atomic cost goes by the lines an instruction touches.
-    constexpr int kStride = G * NS * kWave;  // entries of one list array: every class of the wave
+    // used; the L2's atomic cost goes by the lines an instruction touches. A footprint move
+    // adds only the list's whole blocks of 32 entries and moves the rest (at most 31) to its
+    // head, for the next move to complete; the chunk's end adds everything. (A move leaves
+    // one column or row of the footprint, a few cells per wave: added at once, they took an
+    // atomic instruction for about 11 entries.)
+    constexpr int kStride = G * NS * kWave + 32;  // entries of one list array: every class of the wave and a carried block
     static_assert(kStride * (1 + 2 * NP) <= commit_words<DT, NP>(), "commit list fits the wave's LDS");
     unsigned *cl_c = (unsigned *)cl_v;
     unsigned nlist = 0;  // wave-uniform
@@ -424,14 +429,26 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
 #pragma unroll
         for (int h = 0; h < G; ++h) nlist += (unsigned)__builtin_popcountll(bal[h]);
     };
-    auto flush = [&]() {
+    auto flush = [&](bool all) {
+        const unsigned nf = all ? nlist : (nlist & ~31u);
         const unsigned comp = (unsigned)lane & 1u;
-        for (unsigned e = (unsigned)lane >> 1; e < nlist; e += kWave / 2) {
+        for (unsigned e = (unsigned)lane >> 1; e < nf; e += kWave / 2) {
             float *val = a.grid + (2u * cl_c[e] + comp);  // cell indices < 2^31
 #pragma unroll
             for (int p = 0; p < NP; ++p) unsafeAtomicAdd(val + 2 * p * a.cells, cl_v[kStride * (1 + comp + 2 * p) + e]);
         }
-        nlist = 0;
+        const unsigned rem = nlist - nf;
+        if (nf != 0u && rem != 0u && (unsigned)lane < rem) {
+            const unsigned src = nf + (unsigned)lane;
+            unsigned c = cl_c[src];
+            float v[2 * NP];
+#pragma unroll
+            for (int q = 0; q < 2 * NP; ++q) v[q] = cl_v[kStride * (1 + q) + src];
+            cl_c[lane] = c;
+#pragma unroll
+            for (int q = 0; q < 2 * NP; ++q) cl_v[kStride * (1 + q) + lane] = v[q];
+        }
+        nlist = rem;
     };
     // Commits are only for classes that exist: not in an idle last slot, and not past the
     // end of a row's short last group.
@@ -494,7 +511,7 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
 #pragma unroll
                     for (int h = 0; h < G; ++h) cur[m][h] = yc[h];
                 }
-                flush();
+                flush(false);
             }
             // Kahan step with the product fused into the compensation:
             // y = gamma*K - c, t = s + y, c = (t - s) - y, s = t, in blocks of two runs: the
@@ -574,7 +591,7 @@ __device__ __attribute__((always_inline)) void grid_chunk_ns(const GArgs &a, int
             for (int h = 0; h < G; ++h) go[h] = owns(m, h);
             collect(m, go);
         }
-        flush();
+        flush(true);
     }
 }
 
