@@ -154,8 +154,11 @@ __device__ inline void dft_passes(const BuildArgs &a, const double2 *src, double
     constexpr int kDone = NS_LOG + kBits;
     constexpr bool kLast = kDone == LGM;
     constexpr int M = 1 << LGM, R = 1 << kBits, ns = 1 << NS_LOG;
-    auto lds_ld = [&](int b, int e) { return src[b * M + e]; };
-    auto lds_st = [&](int b, int e, double2 v) { dst[b * M + e] = v; };
+    // exchange positions swizzled within each 16 x 16 block of a transform: a radix-16
+    // pass stores its outputs 16 apart, which would put 16 neighbouring lanes on one LDS bank
+    auto swz = [](int e) { return e ^ ((e >> 4) & 15); };
+    auto lds_ld = [&](int b, int e) { return src[b * M + swz(e)]; };
+    auto lds_st = [&](int b, int e, double2 v) { dst[b * M + swz(e)] = v; };
     if constexpr (PASS == 0 && kLast)
         stockham_pass<R>(M, a.beta, ns, a.L, a.tw, first, out);
     else if constexpr (PASS == 0)
