@@ -930,21 +930,29 @@ __global__ void k_zero_work(GArgs a) {
 // (d[p], or conj d[s] when w < 0, s the slot its value went to). A wave takes 64 runs (in
 // record order) and its lanes walk their records in order, so that neighbouring lanes write
 // neighbouring records; each lane finds its record's run among the 64 by a shuffle search.
-// Records between runs (not griddable) keep the zero written before.
+// The wave writes every record from its first run's start (record 0 for the first wave) to
+// the next wave's first run's start (the last record for the last wave), so each record is
+// written once: records in no run (not griddable) get 0.
 template <int NP>
 __global__ void k_degrid_finish(GArgs a) {
     const int64_t n = a.stats->n_runs;
     const int64_t seglen = (int64_t)a.nt * a.nc;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    if (n == 0) {  // no runs: every record gets 0
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.n_rec * NP;
+             e += (int64_t)gridDim.x * blockDim.x)
+            a.vis_out[e] = make_float2(0.f, 0.f);
+        return;
+    }
     for (int64_t j0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave; j0 < n;
          j0 += nwaves * kWave) {
         const int nv = (int)min((int64_t)kWave, n - j0);
         const bool v = lane < nv;
         const int st = v ? a.start[j0 + lane] : 0x7FFFFFFF;  // runs are in record order
         const int ln = v ? a.len[j0 + lane] : 0;
-        const int64_t r_begin = __shfl(st, 0, kWave);
-        const int64_t r_end = min((int64_t)__shfl(st, nv - 1, kWave) + __shfl(ln, nv - 1, kWave), a.n_rec);
+        const int64_t r_begin = j0 == 0 ? 0 : (int64_t)__shfl(st, 0, kWave);
+        const int64_t r_end = j0 + kWave < n ? (int64_t)a.start[j0 + kWave] : a.n_rec;
         for (int64_t base = r_begin; base < r_end; base += kWave) {  // wave-uniform trip count
             const int64_t r = base + lane;
             int l = 0;  // the last of the 64 runs that starts at or before r
@@ -954,7 +962,12 @@ __global__ void k_degrid_finish(GArgs a) {
                 if (c < nv && sc <= r) l = c;
             }
             const int sl = __shfl(st, l, kWave), ll = __shfl(ln, l, kWave);
-            if (r >= r_end || r < sl || r >= (int64_t)sl + ll) continue;
+            if (r >= r_end) continue;
+            if (r < sl || r >= (int64_t)sl + ll) {  // in no run
+#pragma unroll
+                for (int p = 0; p < NP; ++p) a.vis_out[r * NP + p] = make_float2(0.f, 0.f);
+                continue;
+            }
             const int64_t j = j0 + l;
             const int64_t bb = r / seglen, tt = r - (r / a.nt) * a.nt;
             const double wm = a.uvw[(bb * a.nt + tt) * 3 + 2];
@@ -969,11 +982,6 @@ __global__ void k_degrid_finish(GArgs a) {
             }
         }
     }
-}
-
-__global__ void k_zero(float2 *p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = make_float2(0.f, 0.f);
 }
 
 GArgs make_args(const wg_geom *g, const wg_ktable *kt, const wg_runs *runs) {
@@ -1104,8 +1112,7 @@ extern "C" int wg_degrid(const wg_geom *g, const wg_ktable *kt, const wg_runs *r
     a.n_rec = n_rec;
     a.stats = stats;
     hipStream_t s = (hipStream_t)stream;
-    // records in no run get 0: clear the output and the per-run accumulators first
-    hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, s, (float2 *)vis_out, n_rec * a.npol);
+    // clear the per-run accumulators first (k_degrid_finish writes every record)
     hipLaunchKernelGGL(k_zero_work, dim3(2048), dim3(256), 0, s, a);
     hipLaunchKernelGGL(pick_degrid(kt->dtype, a.npol), dim3(kDegridBlocks), dim3(256), 0, s, a);
     hipLaunchKernelGGL(a.npol == 4 ? k_degrid_finish<4> : a.npol == 2 ? k_degrid_finish<2> : k_degrid_finish<1>,
