@@ -669,33 +669,38 @@ __global__ __launch_bounds__(256, 4) void k_grid(GArgs a) {
         for_each_unit_static(nunits, unit);
 }
 
-// Wave totals of a complex value (re, im), one per lane: lanes 0-31 receive the total of
-// re, lanes 32-63 the total of im. v_permlane32_swap trades the upper half of re for the
-// lower half of im, so the two swapped registers add to re[l] + re[l + 32] in the lower half
-// and im[l - 32] + im[l] in the upper half; v_permlane16_swap of a register with itself then
-// pairs rows 0 and 1, and rows 2 and 3; DPP moves inside each row (quad permutes, row
-// mirrors) finish the sums. One tree serves both components.
+// One DPP move within each row of 16 lanes (all rows and banks on).
 template <int CTRL>
 __device__ inline float dpp_f(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
-__device__ inline float wave_total_pair(float re, float im) {
-    const auto h = __builtin_amdgcn_permlane32_swap(__float_as_int(re), __float_as_int(im), false, false);
-    float v = __int_as_float(h[0]) + __int_as_float(h[1]);
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
-    v = __int_as_float(r[0]) + __int_as_float(r[1]);
-    v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f<0x141>(v);  // row_half_mirror
-    v += dpp_f<0x140>(v);  // row_mirror
-    return v;
+
+// Wave totals of two complex values at once: after the call, lanes 0-15 hold the total of
+// re0, 16-31 of re1, 32-47 of im0 and 48-63 of im1. v_permlane32_swap trades the upper half
+// of re for the lower half of im, so the two swapped registers add to re[l] + re[l + 32] in
+// the lower half and im[l - 32] + im[l] in the upper half; this for both values, then
+// v_permlane16_swap of the two results trades row 1 of the first for row 0 of the second
+// and row 3 of the first for row 2 of the second, so one add leaves one value per row and
+// the DPP moves inside each row finish all four.
+__device__ inline float wave_total_quad(float re0, float im0, float re1, float im1) {
+    const auto h0 = __builtin_amdgcn_permlane32_swap(__float_as_int(re0), __float_as_int(im0), false, false);
+    const auto h1 = __builtin_amdgcn_permlane32_swap(__float_as_int(re1), __float_as_int(im1), false, false);
+    const float v = __int_as_float(h0[0]) + __int_as_float(h0[1]);
+    const float w = __int_as_float(h1[0]) + __int_as_float(h1[1]);
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(w), false, false);
+    float u = __int_as_float(r[0]) + __int_as_float(r[1]);
+    u += dpp_f<0xB1>(u);   // quad_perm [1,0,3,2]
+    u += dpp_f<0x4E>(u);   // quad_perm [2,3,0,1]
+    u += dpp_f<0x141>(u);  // row_half_mirror
+    u += dpp_f<0x140>(u);  // row_mirror
+    return u;
 }
 
 // Adjoint, with the gridder's decomposition: a wave owns the same cell class groups of a
 // local chunk, keeps the grid value of each owned cell in a register and reloads the values
 // only when the footprint moves (about one run in seven), and forms per run the partial dot
 // product of conj(K) with those values (a short FMA chain per lane, then one lane-swap and
-// DPP tree over the wave for the real and imaginary parts together). The waves sharing a
+// DPP tree over the wave for the real and imaginary parts of two runs together). The waves sharing a
 // chunk add their partial sums into work[run]; k_degrid_finish hands d to the run's records.
 static_assert(kGridGroups <= kGroupSlots && kGridGroupsNarrow <= kGroupSlots && kGridGroupsPol2 <= kGroupSlots &&
                   kGridGroupsPol4 <= kGroupSlots && kGridGroupsNarrowPol <= kGroupSlots &&
@@ -797,13 +802,16 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
                 }
             }
         };
-        // this wave's sums: lane l holds component l >> 5 (0 real, 1 imaginary) of run
-        // base + (l & 31) in lo and of run base + 32 + (l & 31) in hi
+        // this wave's sums, reduced two runs at a time: for the pair of runs 2j and 2j + 1
+        // (j = 0..31 in the batch), lane 16k + (j & 15) of lo (j < 16) or hi (j >= 16) holds
+        // row k of the pair's totals: the real part of run 2j, of run 2j + 1, the imaginary
+        // part of run 2j, of run 2j + 1
         float lo[NP], hi[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) lo[p] = hi[p] = 0.f;
+        float qr[2][NP], qi[2][NP];  // the pair's partial sums in this lane
         auto consume = [&](int t, const DStage<DT, G> &st) {
-            float pr[NP], pim[NP];
+            float *pr = qr[t & 1], *pim = qi[t & 1];
 #pragma unroll
             for (int p = 0; p < NP; ++p) pr[p] = pim[p] = 0.f;
             // class h takes sample h of the load, or G - 1 - h when the run reads backwards
@@ -829,14 +837,17 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
                 sums(std::integral_constant<int, 0>{});
                 asm volatile("; samples in order");
             }
-            // the wave's sums for run t wait in lanes (t & 31) and 32 + (t & 31); two atomics
-            // per polarisation and batch add them all
-            const bool mine = (lane & 31) == (t & 31);
+        };
+        // the totals of the pair of runs t, t + 1 (t even) into their lanes; two atomics per
+        // polarisation and batch add them all
+        auto reduce_pair = [&](int t) {
+            const int j = t >> 1;
+            const bool mine = (lane & 15) == (j & 15);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const float d = wave_total_pair(pr[p], pim[p]);
-                lo[p] = (mine && t < 32) ? d : lo[p];
-                hi[p] = (mine && t >= 32) ? d : hi[p];
+                const float d = wave_total_quad(qr[0][p], qi[0][p], qr[1][p], qi[1][p]);
+                lo[p] = (mine && j < 16) ? d : lo[p];
+                hi[p] = (mine && j >= 16) ? d : hi[p];
             }
         };
 
@@ -852,9 +863,13 @@ __device__ __attribute__((always_inline)) void degrid_chunk_ns(const GArgs &a, i
                 fetch(min(t + 2, n - 1), sa);
                 consume(t + 1, sb);
                 if (sa.moved) load_values();
+            } else {
+#pragma unroll
+                for (int p = 0; p < NP; ++p) qr[1][p] = qi[1][p] = 0.f;
             }
+            reduce_pair(t);
         }
-        const int r = lane & 31, comp = lane >> 5;
+        const int row = lane >> 4, r = 2 * (lane & 15) + (row & 1), comp = row >> 1;
         const int ok_lo = __shfl(b.ok, r), ok_hi = __shfl(b.ok, r + 32);
         float *w = (float *)(a.work + (int64_t)(base + r) * NP) + comp;
         if (r < n && ok_lo)
