@@ -23,15 +23,15 @@ constexpr int kPadMax = 3;  // the widest padding (16-bit tables)
 // kernel, table type and polarisation count (measured; the notes give what one more group
 // per lane did: with Kahan sums it spills at the 128-VGPR cap, with plain sums it fits at
 // the VGPRs given and was no faster, or does not fit).
-constexpr int kGroupSlots = 3;
+constexpr int kGroupSlots = 5;
 constexpr int kGridGroups = 3;          // gridder, FP32 pairs, one polarisation (4: 126 VGPRs plain)
 constexpr int kGridGroupsNarrow = 2;    // gridder, 16-bit quads, one polarisation (3: 139 VGPRs plain)
 constexpr int kGridGroupsPol2 = 2;      // gridder, FP32 pairs, two polarisations (3: 125 VGPRs plain)
 constexpr int kGridGroupsPol4 = 1;      // gridder, FP32 pairs, four polarisations (2: 126 VGPRs plain)
 constexpr int kGridGroupsNarrowPol = 1; // gridder, 16-bit tables: quads with two (2: 133 VGPRs plain), pairs with four polarisations
-constexpr int kDegridGroups = 3;        // degridder, FP32 pairs, one polarisation
-constexpr int kDegridGroupsNarrow = 3;  // degridder, 16-bit quads, one polarisation
-constexpr int kDegridGroupsPol = 3;     // degridder, FP32 pairs, two or four polarisations
+constexpr int kDegridGroups = 5;        // degridder, FP32 pairs, one polarisation (3: 4 % slower, 6: alike)
+constexpr int kDegridGroupsNarrow = 3;  // degridder, 16-bit quads, one polarisation (4: 3 % slower, 5: 20 %)
+constexpr int kDegridGroupsPol = 4;     // degridder, FP32 pairs, two or four polarisations (3: 6 % slower)
 constexpr int kDegridGroupsNarrowPol = 2;  // degridder, 16-bit tables: quads with two, pairs with four
 
 // ---------------------------------------------------------------------------------------
