@@ -271,10 +271,10 @@ int wg_compress(const wg_geom *g, const wg_ktable *kt, const double *uvw, const 
  * gamma[p] * K[i][j] with
  * a = x + n/2 - H, row0 = y + n/2 - H, K the run's matrix. ACCUMULATES into `grid`
  * (complex64 [P][n][n], or [nc][P][n][n] with WG_GRID_PER_CHANNEL or [n_w][P][n][n]
- * with WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first. Accumulation is FP32: Kahan-
- * compensated sums per owned cell between commits (plain sums with g->flags & WG_PLAIN_SUMS,
- * as in the thesis's single-precision gridder), and commits with FP32 atomic adds, so the last
- * bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
+ * with WG_W_STACKING, run q going to grid runs->grid[q]); the caller zeroes it first.
+ * Accumulation is FP32: Kahan-compensated sums per owned cell between commits (plain sums
+ * with g->flags & WG_PLAIN_SUMS, as in the thesis's single-precision gridder), and commits
+ * with FP32 atomic adds, so the last bits depend on scheduling. `runs`, `stats` come from wg_compress with the same g and kt.
  * Errors: WG_EINVAL, WG_EUNSUPPORTED (kt->data_cap >= 2^28 elements: table byte offsets
  * are 32-bit), WG_EHIP.
  */

@@ -700,8 +700,9 @@ __device__ inline float wave_total_quad(float re0, float im0, float re1, float i
 // local chunk, keeps the grid value of each owned cell in a register and reloads the values
 // only when the footprint moves (about one run in seven), and forms per run the partial dot
 // product of conj(K) with those values (a short FMA chain per lane, then one lane-swap and
-// DPP tree over the wave for the real and imaginary parts of two runs together). The waves sharing a
-// chunk add their partial sums into work[run]; k_degrid_finish hands d to the run's records.
+// DPP tree over the wave for the real and imaginary parts of two runs together). The waves
+// sharing a chunk add their partial sums into work[run]; k_degrid_finish hands d to the
+// run's records.
 static_assert(kGridGroups <= kGroupSlots && kGridGroupsNarrow <= kGroupSlots && kGridGroupsPol2 <= kGroupSlots &&
                   kGridGroupsPol4 <= kGroupSlots && kGridGroupsNarrowPol <= kGroupSlots &&
                   kDegridGroups <= kGroupSlots && kDegridGroupsNarrow <= kGroupSlots &&
