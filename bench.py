@@ -117,7 +117,10 @@ def roofline(kernel, updates, ms, counters):
         # the vector memory path: fraction of cycles the texture-data units are busy
         out["vmem_td_busy_frac"] = counters[f"td_busy_{key}"]
     if f"valu_ipc_{key}" in counters:
+        # VALU wave-instructions per SIMD-cycle: a SIMD issues at most one a cycle, so this
+        # is also the fraction of issue slots the VALU took
         out["valu_insts_per_simd_cycle"] = counters[f"valu_ipc_{key}"]
+        out["valu_issue_frac"] = counters[f"valu_ipc_{key}"]
     return out
 
 
